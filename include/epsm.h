@@ -1,0 +1,202 @@
+/*
+ * epsm.h - C ABI of the MI355X (gfx950) exact packed string matching library.
+ *
+ * The operation is the exact string matching problem as the paper states it
+ * (Faro and Kulekci, "Fast Packed String Matching for Short Patterns",
+ * Introduction and Section 2): given a text t of length n and a pattern p of
+ * length m > 0 over bytes, report ALL positions s, 0 <= s <= n-m, with
+ * t[s+j] = p[j] for 0 <= j < m.  Overlapping occurrences are all reported;
+ * positions are 0-based starts written as int64 in strictly ascending order.
+ * Byte value 0 is an ordinary symbol; texts are length-counted.
+ *
+ * Method (Section 3): patterns with m < 16 are found by comparing each text
+ * position's packed window against the packed pattern prefix, then checking
+ * the rest exactly (the role of EPSMa/EPSMb, Sections 3.2-3.3).  Patterns
+ * with m >= 16 go through a fingerprint filter over aligned 8-byte text
+ * blocks, whose hash selects the pattern offsets j for which position
+ * (block - j) is a candidate, followed by an exact check (EPSMc, Section 3.4).
+ * Both variants report exactly the set above; the hash only changes speed.
+ *
+ * Conventions
+ *  - "d_" arguments are device pointers (HIP device memory of the device the
+ *    plan was created on); other pointers are host pointers.
+ *  - stream: a hipStream_t cast to void* (NULL = the default stream).  Every
+ *    search call is asynchronous and stream ordered; results are valid after
+ *    the stream is synchronised.  No call synchronises the stream, except
+ *    where stated.
+ *  - Errors are returned as epsm_status; a thread-local message is available
+ *    from epsm_last_error().  Synchronous returns report argument and launch
+ *    errors only.
+ *  - The caller owns every buffer it passes; the library never frees caller
+ *    memory.  A plan owns its own copy of the pattern and its device tables.
+ *  - Text and output pointers may have any alignment.
+ */
+#ifndef EPSM_H
+#define EPSM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    EPSM_OK = 0,
+    EPSM_EINVAL = 1,       /* invalid argument (m == 0, NULL pointer, bad flags) */
+    EPSM_ENOMEM = 2,       /* host or device allocation failed */
+    EPSM_EDEVICE = 3,      /* a HIP runtime call or kernel launch failed */
+    EPSM_EUNSUPPORTED = 4  /* valid request outside what this build supports */
+} epsm_status;
+
+/* Opaque, immutable after creation.  Safe to use concurrently from several
+ * host threads and on several streams. */
+typedef struct epsm_plan_s *epsm_plan_t;
+
+/* ---- plan flags -------------------------------------------------------- */
+/* Build host-side tables only (no device allocation); such a plan can be
+ * inspected with epsm_plan_get_info but is rejected by search calls. */
+#define EPSM_PLAN_HOST_ONLY 0x1u
+/* Force the direct-compare variant (any m). */
+#define EPSM_PLAN_FORCE_DIRECT 0x2u
+/* Force the fingerprint variant (requires m >= 15, see Section 3.4). */
+#define EPSM_PLAN_FORCE_FINGERPRINT 0x4u
+/* Test mode: the fingerprint hash is the constant 0, so every aligned block
+ * hits the same bucket and every offset is verified; output is unchanged. */
+#define EPSM_PLAN_COLLIDE 0x8u
+/* Fingerprint width k (bucket count 2^k), Section 3.4 uses k = 11.
+ * Encoded in bits 8..11 of flags as EPSM_PLAN_HASH_BITS(k), 8 <= k <= 14;
+ * 0 selects the default (11). */
+#define EPSM_PLAN_HASH_BITS(k) (((uint32_t)(k) & 0xFu) << 8)
+
+/* Variants */
+#define EPSM_VARIANT_DIRECT 1u
+#define EPSM_VARIANT_FINGERPRINT 2u
+
+/* Longest pattern this build accepts. */
+#define EPSM_MAX_M 4096u
+
+/*
+ * epsm_plan: preprocess pattern[0..m-1] (host memory, copied) for searches on
+ * the current HIP device.  Chooses the variant by m (direct for m < 16,
+ * fingerprint for m >= 16) unless forced by flags, packs the pattern into
+ * 32-bit words, and for the fingerprint variant builds the table of Section
+ * 3.4: entry v holds the set of offsets j in [0,7] with h(p[j..j+7]) = v.
+ * Returns EPSM_EINVAL for m == 0, a NULL pattern or out, or bad flags;
+ * EPSM_EUNSUPPORTED for m > EPSM_MAX_M; EPSM_ENOMEM / EPSM_EDEVICE if the
+ * device copy fails.  On success *out receives the plan.
+ */
+epsm_status epsm_plan(const uint8_t *pattern, uint64_t m, uint32_t flags, epsm_plan_t *out);
+
+/* Release a plan.  The caller guarantees no search using it is in flight. */
+void epsm_plan_destroy(epsm_plan_t plan);
+
+typedef struct {
+    uint64_t m;              /* pattern length */
+    uint32_t variant;        /* EPSM_VARIANT_* */
+    uint32_t flags;          /* flags the plan was built with */
+    uint32_t hash_bits;      /* k, fingerprint variant only (else 0) */
+    uint32_t prefix_words;   /* 32-bit pattern words compared in the filter */
+    uint32_t words[8];       /* pattern bytes 4i..4i+3, little endian, 0 past m */
+    uint32_t masks[8];       /* 0xFF in each byte lane that lies below m */
+    const uint16_t *table;   /* host copy of the fingerprint table, 2^k entries:
+                                bit (8-j) of entry v is set iff offset j is in
+                                bucket v; NULL for the direct variant.  Owned by
+                                the plan. */
+    int32_t device;          /* HIP device of the device tables, -1 if host only */
+} epsm_plan_info;
+
+/* Copy the plan's description to *info (host memory). */
+epsm_status epsm_plan_get_info(epsm_plan_t plan, epsm_plan_info *info);
+
+/* The fingerprint hash of an 8-byte block whose little-endian 32-bit halves
+ * are lo and hi, reduced to k bits (the role of wscrc & mask, Section 3.1 and
+ * 3.4).  Exposed so tests can check the table; the device uses the same
+ * function.  collide != 0 gives the constant-0 test hash. */
+uint32_t epsm_fingerprint(uint32_t lo, uint32_t hi, uint32_t k, int collide);
+
+/*
+ * epsm_search: write the occurrence positions of plan's pattern in
+ * d_text[0..n-1] to d_out.  d_out receives the first min(count,
+ * out_capacity) positions, ascending (a prefix of the full answer);
+ * *d_n_hits (device, uint64) receives the full count.  d_out may be NULL if
+ * out_capacity == 0.  n == 0 or m > n gives count 0.  Uses a library-owned
+ * workspace tied to the stream (grown on demand; growing allocates device
+ * memory, so reserve with epsm_reserve before capturing a graph).
+ */
+epsm_status epsm_search(epsm_plan_t plan, const uint8_t *d_text, uint64_t n,
+                        int64_t *d_out, uint64_t out_capacity,
+                        uint64_t *d_n_hits, void *stream);
+
+/* epsm_count: the occurrence count only, to *d_n_hits (device, uint64). */
+epsm_status epsm_count(epsm_plan_t plan, const uint8_t *d_text, uint64_t n,
+                       uint64_t *d_n_hits, void *stream);
+
+/* ---- batched search ------------------------------------------------------ */
+
+typedef struct {
+    const uint8_t *d_text;   /* device pointer */
+    uint64_t n;              /* length in bytes */
+} epsm_text_ref;
+
+typedef struct {
+    uint32_t text;           /* index into texts[] */
+    epsm_plan_t plan;        /* pattern to search in that text */
+} epsm_pair_ref;
+
+#define EPSM_BATCH_COUNT_ONLY 0x1u
+
+typedef struct {
+    const epsm_text_ref *texts;  /* host array [n_texts] */
+    uint32_t n_texts;
+    const epsm_pair_ref *pairs;  /* host array [n_pairs] */
+    uint32_t n_pairs;
+    int64_t *d_out;              /* concatenated positions, pair order */
+    uint64_t out_capacity;       /* entries available in d_out */
+    uint64_t *d_counts;          /* device [n_pairs]: full count of each pair */
+    uint64_t *d_offsets;         /* device [n_pairs]: exclusive prefix of counts */
+    uint64_t *d_total;           /* device, optional (may be NULL): sum of counts */
+    uint32_t flags;              /* EPSM_BATCH_* */
+} epsm_batch;
+
+/*
+ * epsm_search_batch: every (text, pattern) pair of the batch in one
+ * stream-ordered submission.  Pair k's positions (relative to its text) are
+ * d_out[d_offsets[k] .. d_offsets[k] + d_counts[k]) in ascending order;
+ * entries at or beyond out_capacity are not written (counts and offsets are
+ * always complete).  With EPSM_BATCH_COUNT_ONLY only counts, offsets and
+ * total are produced.  Output is identical to calling epsm_search per pair.
+ * All plans must live on the current device.  The host arrays are read
+ * before the call returns.
+ */
+epsm_status epsm_search_batch(const epsm_batch *batch, void *stream);
+
+/* ---- workspace and diagnostics -------------------------------------------- */
+
+/* Make sure the workspace tied to `stream` can serve texts of up to max_n
+ * bytes and batches of up to max_units tiles without allocating again. */
+epsm_status epsm_reserve(void *stream, uint64_t max_n, uint64_t max_units);
+
+/* Free every cached workspace (synchronises the device). */
+void epsm_release(void);
+
+/* Synchronise `stream` and report EPSM_EDEVICE if a kernel launched on it
+ * ever gave up one of its bounded inter-workgroup waits (its output is then
+ * not trustworthy).  Such a wait is not expected to time out; this is a
+ * diagnostic for tests.  Returns EPSM_OK otherwise. */
+epsm_status epsm_stream_check(void *stream);
+
+/* Thread-local description of the last error on this thread ("" if none). */
+const char *epsm_last_error(void);
+
+/* Static name of a status code. */
+const char *epsm_status_string(epsm_status s);
+
+/* Library version as major*10000 + minor*100 + patch. */
+int epsm_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* EPSM_H */

@@ -1,0 +1,159 @@
+"""Exact packed string matching on MI355X (gfx950).
+
+Python binding of the C ABI in include/epsm.h.  Every step of the search runs
+in the HIP kernels of libepsm.so; this module only marshals arguments.  torch
+supplies device memory (uint8 / int64 / uint64 tensors) and streams.
+
+    import paper_1209_6449_amd as epsm
+    text = torch.frombuffer(bytearray(b"..."), dtype=torch.uint8).cuda()
+    pos = epsm.search(text, b"pattern")        # int64 tensor of start positions
+    n = epsm.count(text, b"pattern")
+"""
+from __future__ import annotations
+
+import ctypes
+
+import torch
+
+from . import _lib
+from ._lib import (BATCH_COUNT_ONLY, MAX_M, PLAN_COLLIDE, PLAN_FORCE_DIRECT,  # noqa: F401
+                   PLAN_FORCE_FINGERPRINT, PLAN_HASH_BITS, PLAN_HOST_ONLY, VARIANT_DIRECT,
+                   VARIANT_FINGERPRINT)
+
+__all__ = ["EpsmError", "Plan", "search", "count", "search_into", "count_into", "reserve",
+           "stream_check", "lib", "library_path"]
+
+
+def lib():
+    return _lib.load()
+
+
+def library_path() -> str:
+    return _lib.LIB_PATH
+
+
+class EpsmError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        L = lib()
+        self.status = status
+        self.name = L.epsm_status_string(status).decode()
+        self.detail = L.epsm_last_error().decode()
+        super().__init__(f"{where}: {self.name}: {self.detail}")
+
+
+def _check(status: int, where: str) -> None:
+    if status != _lib.EPSM_OK:
+        raise EpsmError(status, where)
+
+
+def _stream_handle(stream) -> int | None:
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    if isinstance(stream, int):
+        return stream or None
+    return stream.cuda_stream or None
+
+
+class Plan:
+    """A preprocessed pattern (epsm_plan).  Device tables live on the current device."""
+
+    def __init__(self, pattern: bytes, flags: int = 0):
+        pattern = bytes(pattern)
+        self.pattern = pattern
+        self.flags = flags
+        self._handle = ctypes.c_void_p()
+        self._buf = ctypes.create_string_buffer(pattern, max(len(pattern), 1))
+        _check(lib().epsm_plan(ctypes.cast(self._buf, ctypes.c_void_p), len(pattern), flags,
+                               ctypes.byref(self._handle)), "epsm_plan")
+
+    @property
+    def handle(self) -> int:
+        return self._handle.value
+
+    @property
+    def m(self) -> int:
+        return len(self.pattern)
+
+    def info(self) -> dict:
+        inf = _lib.PlanInfo()
+        _check(lib().epsm_plan_get_info(self._handle, ctypes.byref(inf)), "epsm_plan_get_info")
+        table = None
+        if inf.table:
+            table = [inf.table[i] for i in range(1 << inf.hash_bits)]
+        return {
+            "m": inf.m, "variant": inf.variant, "flags": inf.flags, "hash_bits": inf.hash_bits,
+            "prefix_words": inf.prefix_words, "words": list(inf.words), "masks": list(inf.masks),
+            "table": table, "device": inf.device,
+        }
+
+    def close(self) -> None:
+        if self._handle and self._handle.value:
+            lib().epsm_plan_destroy(self._handle)
+            self._handle = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _as_plan(pattern_or_plan, flags: int = 0) -> Plan:
+    if isinstance(pattern_or_plan, Plan):
+        return pattern_or_plan
+    return Plan(pattern_or_plan, flags)
+
+
+def _check_text(text: torch.Tensor) -> None:
+    if not isinstance(text, torch.Tensor) or text.dtype != torch.uint8 or not text.is_cuda:
+        raise TypeError("text must be a uint8 CUDA (HIP) tensor")
+    if text.dim() != 1 or (text.numel() > 1 and text.stride(0) != 1):
+        raise ValueError("text must be a contiguous 1-D tensor")
+
+
+def search_into(plan: Plan, text: torch.Tensor, out: torch.Tensor | None, n_hits: torch.Tensor,
+                stream=None) -> None:
+    """epsm_search into caller tensors: out (int64), n_hits (uint64/int64, 1 element)."""
+    _check_text(text)
+    cap = 0 if out is None else out.numel()
+    out_ptr = None if out is None or cap == 0 else out.data_ptr()
+    _check(lib().epsm_search(plan.handle, text.data_ptr() if text.numel() else None,
+                             text.numel(), out_ptr, cap, n_hits.data_ptr(),
+                             _stream_handle(stream)), "epsm_search")
+
+
+def count_into(plan: Plan, text: torch.Tensor, n_hits: torch.Tensor, stream=None) -> None:
+    _check_text(text)
+    _check(lib().epsm_count(plan.handle, text.data_ptr() if text.numel() else None,
+                            text.numel(), n_hits.data_ptr(), _stream_handle(stream)),
+           "epsm_count")
+
+
+def count(text: torch.Tensor, pattern, flags: int = 0, stream=None) -> int:
+    """Number of occurrences (synchronises the stream)."""
+    plan = _as_plan(pattern, flags)
+    hits = torch.zeros(1, dtype=torch.int64, device=text.device)
+    count_into(plan, text, hits, stream)
+    return int(hits.item())
+
+
+def search(text: torch.Tensor, pattern, flags: int = 0, stream=None) -> torch.Tensor:
+    """All occurrence positions as an int64 tensor (counts, allocates, then searches)."""
+    plan = _as_plan(pattern, flags)
+    hits = torch.zeros(1, dtype=torch.int64, device=text.device)
+    count_into(plan, text, hits, stream)
+    n = int(hits.item())
+    out = torch.empty(n, dtype=torch.int64, device=text.device)
+    search_into(plan, text, out, hits, stream)
+    if int(hits.item()) != n:
+        raise RuntimeError("count changed between passes")
+    return out
+
+
+def stream_check(stream=None) -> None:
+    """Synchronise the stream; raise if a kernel on it gave up a bounded wait."""
+    _check(lib().epsm_stream_check(_stream_handle(stream)), "epsm_stream_check")
+
+
+def reserve(max_n: int, max_units: int = 0, stream=None) -> None:
+    _check(lib().epsm_reserve(_stream_handle(stream), max_n, max_units), "epsm_reserve")

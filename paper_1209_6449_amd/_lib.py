@@ -1,0 +1,109 @@
+"""ctypes declarations of the C ABI in include/epsm.h (argument marshalling only)."""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libepsm.so")
+
+EPSM_OK = 0
+EPSM_EINVAL = 1
+EPSM_ENOMEM = 2
+EPSM_EDEVICE = 3
+EPSM_EUNSUPPORTED = 4
+
+PLAN_HOST_ONLY = 0x1
+PLAN_FORCE_DIRECT = 0x2
+PLAN_FORCE_FINGERPRINT = 0x4
+PLAN_COLLIDE = 0x8
+
+
+def PLAN_HASH_BITS(k: int) -> int:
+    return (k & 0xF) << 8
+
+
+VARIANT_DIRECT = 1
+VARIANT_FINGERPRINT = 2
+BATCH_COUNT_ONLY = 0x1
+MAX_M = 4096
+
+
+class PlanInfo(ctypes.Structure):
+    _fields_ = [
+        ("m", ctypes.c_uint64),
+        ("variant", ctypes.c_uint32),
+        ("flags", ctypes.c_uint32),
+        ("hash_bits", ctypes.c_uint32),
+        ("prefix_words", ctypes.c_uint32),
+        ("words", ctypes.c_uint32 * 8),
+        ("masks", ctypes.c_uint32 * 8),
+        ("table", ctypes.POINTER(ctypes.c_uint16)),
+        ("device", ctypes.c_int32),
+    ]
+
+
+class TextRef(ctypes.Structure):
+    _fields_ = [("d_text", ctypes.c_void_p), ("n", ctypes.c_uint64)]
+
+
+class PairRef(ctypes.Structure):
+    _fields_ = [("text", ctypes.c_uint32), ("plan", ctypes.c_void_p)]
+
+
+class Batch(ctypes.Structure):
+    _fields_ = [
+        ("texts", ctypes.POINTER(TextRef)),
+        ("n_texts", ctypes.c_uint32),
+        ("pairs", ctypes.POINTER(PairRef)),
+        ("n_pairs", ctypes.c_uint32),
+        ("d_out", ctypes.c_void_p),
+        ("out_capacity", ctypes.c_uint64),
+        ("d_counts", ctypes.c_void_p),
+        ("d_offsets", ctypes.c_void_p),
+        ("d_total", ctypes.c_void_p),
+        ("flags", ctypes.c_uint32),
+    ]
+
+
+# name -> (restype, argtypes); every symbol include/epsm.h declares
+SIGNATURES = {
+    "epsm_plan": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint32,
+                                 ctypes.POINTER(ctypes.c_void_p)]),
+    "epsm_plan_destroy": (None, [ctypes.c_void_p]),
+    "epsm_plan_get_info": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(PlanInfo)]),
+    "epsm_fingerprint": (ctypes.c_uint32, [ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32,
+                                           ctypes.c_int]),
+    "epsm_search": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64,
+                                   ctypes.c_void_p, ctypes.c_uint64, ctypes.c_void_p,
+                                   ctypes.c_void_p]),
+    "epsm_count": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64,
+                                  ctypes.c_void_p, ctypes.c_void_p]),
+    "epsm_search_batch": (ctypes.c_int, [ctypes.POINTER(Batch), ctypes.c_void_p]),
+    "epsm_reserve": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint64]),
+    "epsm_release": (None, []),
+    "epsm_stream_check": (ctypes.c_int, [ctypes.c_void_p]),
+    "epsm_last_error": (ctypes.c_char_p, []),
+    "epsm_status_string": (ctypes.c_char_p, [ctypes.c_int]),
+    "epsm_version": (ctypes.c_int, []),
+}
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load libepsm.so; raises if it has not been built (there is no fallback)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(
+            f"{path} is missing: build it with paper_1209_6449_amd.build.build() "
+            "(hipcc --offload-arch=gfx950); there is no CPU fallback")
+    lib = ctypes.CDLL(path)
+    for name, (res, args) in SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib

@@ -1,0 +1,56 @@
+"""Build libepsm.so (HIP, gfx950) in-tree with hipcc."""
+from __future__ import annotations
+
+import os
+import subprocess
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+CSRC = os.path.join(HERE, "csrc")
+LIB = os.path.join(HERE, "libepsm.so")
+SOURCES = ["epsm_kernels.hip", "epsm_api.hip"]
+
+HIPCC_FLAGS = [
+    "--offload-arch=gfx950",
+    "-O3",
+    "-std=c++17",
+    "-fPIC",
+    "-shared",
+    "-Wall",
+    # never emit packed-FP32 instructions (none are needed: integer code)
+    "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    "-I", os.path.join(ROOT, "include"),
+]
+
+
+def hipcc() -> str:
+    path = os.path.join(os.environ.get("ROCM_PATH", "/opt/rocm"), "bin", "hipcc")
+    return path if os.path.exists(path) else "hipcc"
+
+
+def build(out: str = LIB, extra: list[str] | None = None, verbose: bool = False) -> str:
+    srcs = [os.path.join(CSRC, s) for s in SOURCES]
+    tmp = out + ".tmp"
+    cmd = [hipcc()] + HIPCC_FLAGS + (extra or []) + srcs + ["-o", tmp]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, out)
+    return out
+
+
+def dump_isa(dest_dir: str) -> None:
+    """Write the gfx950 assembly of the kernels (for inspection)."""
+    os.makedirs(dest_dir, exist_ok=True)
+    src = os.path.join(CSRC, "epsm_kernels.hip")
+    cmd = [hipcc(), "--offload-arch=gfx950", "-O3", "-std=c++17", "--cuda-device-only", "-S",
+           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+           "-I", os.path.join(ROOT, "include"), src, "-o", os.path.join(dest_dir, "epsm_kernels.s")]
+    subprocess.run(cmd, check=True)
+
+
+if __name__ == "__main__":
+    build(verbose=True)
+    if len(sys.argv) > 1 and sys.argv[1] == "--isa":
+        dump_isa(sys.argv[2] if len(sys.argv) > 2 else "_work/isa")

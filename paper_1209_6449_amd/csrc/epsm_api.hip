@@ -1,0 +1,364 @@
+// C ABI of the exact packed string matching library (see include/epsm.h).
+//
+// Host side: pattern preprocessing (Sections 3.2-3.4: packed pattern words
+// for the direct compare, the fingerprint table for EPSMc), argument checks,
+// a per-stream device workspace for the look-back status words, and kernel
+// launches.  Nothing here touches text bytes: all matching runs on the GPU.
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/epsm.h"
+#include "epsm_internal.h"
+
+using namespace epsm;
+
+struct epsm_plan_s {
+    std::vector<uint8_t> pattern;
+    std::vector<uint16_t> table;  // host copy, fingerprint only
+    DevPlan dev{};                // pointers filled for device plans
+    uint32_t flags = 0;
+    int device = -1;
+    uint8_t *d_pattern = nullptr;
+    uint16_t *d_table = nullptr;
+};
+
+namespace {
+
+thread_local std::string g_last_error;
+
+epsm_status fail(epsm_status s, const std::string &msg) {
+    g_last_error = msg;
+    return s;
+}
+
+epsm_status hip_fail(hipError_t e, const char *what) {
+    return fail(e == hipErrorOutOfMemory ? EPSM_ENOMEM : EPSM_EDEVICE,
+                std::string(what) + ": " + hipGetErrorString(e));
+}
+
+constexpr uint32_t kKnownPlanFlags = EPSM_PLAN_HOST_ONLY | EPSM_PLAN_FORCE_DIRECT |
+                                     EPSM_PLAN_FORCE_FINGERPRINT | EPSM_PLAN_COLLIDE |
+                                     EPSM_PLAN_HASH_BITS(0xF);
+constexpr uint32_t kDefaultHashBits = 11;  // k = 11 in Section 3.4
+
+// Default tile: 4 waves x 4 KiB per wave = 16 KiB per workgroup tile.
+TileConfig g_tile = {4, 4};
+int g_cus = 0;
+
+// ---- workspace: look-back status words + ticket, one buffer per stream ----
+struct Workspace {
+    uint8_t *ptr = nullptr;
+    size_t bytes = 0;
+    int device = -1;
+};
+std::mutex g_ws_mutex;
+std::map<std::pair<int, hipStream_t>, Workspace> g_ws;
+
+epsm_status workspace_for(hipStream_t stream, size_t bytes, uint8_t **out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    std::lock_guard<std::mutex> lock(g_ws_mutex);
+    Workspace &ws = g_ws[{dev, stream}];
+    if (ws.bytes < bytes) {
+        if (ws.ptr) {
+            e = hipFree(ws.ptr);  // implicitly synchronises: no kernel still uses it
+            ws.ptr = nullptr;
+            ws.bytes = 0;
+            if (e != hipSuccess) return hip_fail(e, "hipFree(workspace)");
+        }
+        size_t want = std::max<size_t>(bytes, 1 << 16);
+        want = (want + 4095) & ~size_t(4095);
+        e = hipMalloc(&ws.ptr, want);
+        if (e != hipSuccess) {
+            ws.ptr = nullptr;
+            return hip_fail(e, "hipMalloc(workspace)");
+        }
+        ws.bytes = want;
+        ws.device = dev;
+    }
+    *out = ws.ptr;
+    return EPSM_OK;
+}
+
+// One device word per (device, stream) that kernels set when a bounded wait
+// gives up; read back by epsm_stream_check.
+std::map<std::pair<int, hipStream_t>, uint32_t *> g_fault;
+
+uint32_t *fault_word(hipStream_t stream) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return nullptr;
+    std::lock_guard<std::mutex> lock(g_ws_mutex);
+    uint32_t *&f = g_fault[{dev, stream}];
+    if (!f) {
+        if (hipMalloc(&f, 256) != hipSuccess) {
+            f = nullptr;
+            return nullptr;
+        }
+        if (hipMemset(f, 0, 256) != hipSuccess) {
+            (void)hipFree(f);
+            f = nullptr;
+        }
+    }
+    return f;
+}
+
+int cu_count() {
+    if (g_cus == 0) {
+        int dev = 0, cus = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess)
+            g_cus = cus;
+        if (g_cus <= 0) g_cus = 256;
+    }
+    return g_cus;
+}
+
+uint32_t load_le32(const uint8_t *p, uint64_t m, uint64_t at) {
+    uint32_t v = 0;
+    for (int b = 0; b < 4; ++b)
+        if (at + b < m) v |= (uint32_t)p[at + b] << (8 * b);
+    return v;
+}
+
+epsm_status check_plan(epsm_plan_t plan) {
+    if (!plan) return fail(EPSM_EINVAL, "plan is NULL");
+    if (plan->device < 0) return fail(EPSM_EINVAL, "plan was built host-only (EPSM_PLAN_HOST_ONLY)");
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    if (dev != plan->device) return fail(EPSM_EINVAL, "plan belongs to another device");
+    return EPSM_OK;
+}
+
+// Count (write = false) or positions (write = true) for one text.
+epsm_status run_search(epsm_plan_t plan, const uint8_t *d_text, uint64_t n, int64_t *d_out,
+                       uint64_t cap, uint64_t *d_n_hits, hipStream_t stream, bool write) {
+    epsm_status st = check_plan(plan);
+    if (st != EPSM_OK) return st;
+    if (!d_n_hits) return fail(EPSM_EINVAL, "d_n_hits is NULL");
+    if (n > 0 && !d_text) return fail(EPSM_EINVAL, "d_text is NULL");
+    if (write && cap > 0 && !d_out) return fail(EPSM_EINVAL, "d_out is NULL with out_capacity > 0");
+    const uint64_t m = plan->dev.m;
+    if (n == 0 || m > n) {
+        hipError_t e = launch_set_u64(d_n_hits, 0, stream);
+        return e == hipSuccess ? EPSM_OK : hip_fail(e, "launch(set)");
+    }
+    ScanArgs a{};
+    const uintptr_t addr = (uintptr_t)d_text;
+    a.base = (const uint8_t *)(addr & ~uintptr_t(15));
+    a.delta = addr & 15;
+    a.last = a.delta + n - m;
+    a.load_end = (a.delta + n + 15) & ~uint64_t(15);
+    a.out = d_out;
+    a.cap = write ? cap : 0;
+    a.n_hits = d_n_hits;
+    a.write = write ? 1 : 0;
+    a.plan = plan->dev;
+    const uint64_t tile_bytes = (uint64_t)g_tile.bytes();
+    const uint64_t tiles = (a.last + 1 + tile_bytes - 1) / tile_bytes;
+    if (tiles > 0xFFFFFFF0ull) return fail(EPSM_EUNSUPPORTED, "text too long for 32-bit tile tickets");
+    a.num_tiles = (uint32_t)tiles;
+
+    uint8_t *ws = nullptr;
+    const size_t ws_bytes = 256 + (size_t)tiles * sizeof(uint64_t);
+    st = workspace_for(stream, ws_bytes, &ws);
+    if (st != EPSM_OK) return st;
+    a.ticket = (uint32_t *)ws;
+    a.status = (uint64_t *)(ws + 256);
+    a.fault = fault_word(stream);
+    if (!a.fault) return fail(EPSM_ENOMEM, "fault word allocation");
+    hipError_t e = launch_zero_u64((uint64_t *)ws, ws_bytes / 8, stream);
+    if (e != hipSuccess) return hip_fail(e, "launch(zero)");
+
+    int per_cu = scan_blocks_per_cu(g_tile, a.plan);
+    if (per_cu <= 0) per_cu = 1;
+    const uint64_t grid = std::min<uint64_t>(tiles, (uint64_t)per_cu * cu_count());
+    e = launch_scan(a, g_tile, (int)grid, stream);
+    if (e != hipSuccess) return hip_fail(e, "launch(scan)");
+    return EPSM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+uint32_t epsm_fingerprint(uint32_t lo, uint32_t hi, uint32_t k, int collide) {
+    if (collide) return 0;
+    return fp_hash(lo, hi, k);
+}
+
+epsm_status epsm_plan(const uint8_t *pattern, uint64_t m, uint32_t flags, epsm_plan_t *out) {
+    g_last_error.clear();
+    if (!out) return fail(EPSM_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!pattern) return fail(EPSM_EINVAL, "pattern is NULL");
+    if (m == 0) return fail(EPSM_EINVAL, "m must be > 0");
+    if (m > EPSM_MAX_M) return fail(EPSM_EUNSUPPORTED, "m exceeds EPSM_MAX_M");
+    if (flags & ~kKnownPlanFlags) return fail(EPSM_EINVAL, "unknown plan flags");
+    if ((flags & EPSM_PLAN_FORCE_DIRECT) && (flags & EPSM_PLAN_FORCE_FINGERPRINT))
+        return fail(EPSM_EINVAL, "FORCE_DIRECT and FORCE_FINGERPRINT are exclusive");
+    uint32_t k = (flags >> 8) & 0xF;
+    if (k == 0) k = kDefaultHashBits;
+    if (k < 8 || k > 14) return fail(EPSM_EINVAL, "hash bits must be in [8, 14]");
+
+    bool fingerprint = m >= 16;
+    if (flags & EPSM_PLAN_FORCE_DIRECT) fingerprint = false;
+    if (flags & EPSM_PLAN_FORCE_FINGERPRINT) {
+        if (m < 15) return fail(EPSM_EINVAL, "the fingerprint variant needs m >= 15");
+        fingerprint = true;
+    }
+
+    epsm_plan_s *p = new (std::nothrow) epsm_plan_s();
+    if (!p) return fail(EPSM_ENOMEM, "plan allocation");
+    p->pattern.assign(pattern, pattern + m);
+    p->flags = flags;
+    DevPlan &d = p->dev;
+    d.m = m;
+    for (int j = 0; j < 8; ++j) {
+        d.pw[j] = load_le32(pattern, m, 4ull * j);
+        uint32_t mask = 0;
+        for (int b = 0; b < 4; ++b)
+            if (4ull * j + b < m) mask |= 0xFFu << (8 * b);
+        d.pmask[j] = mask;
+    }
+    d.variant = fingerprint ? EPSM_VARIANT_FINGERPRINT : EPSM_VARIANT_DIRECT;
+    d.nl = (fingerprint || m > 16) ? 3 : 2;
+    const uint32_t nwmax = 4 * d.nl - 4;
+    const uint64_t words = (m + 3) / 4;
+    d.nw = (uint32_t)std::min<uint64_t>(words, nwmax);
+    d.pk = (uint32_t)std::min<uint64_t>(m, 4);
+    d.collide = (flags & EPSM_PLAN_COLLIDE) ? 1 : 0;
+    d.hash_bits = fingerprint ? k : 0;
+    if (fingerprint) {
+        // Section 3.4: L[v] = { j : h(p[j..j+7]) = v }, offsets j in [0, 7].
+        p->table.assign((size_t)1 << k, 0);
+        for (uint32_t j = 0; j < 8 && j + 8 <= m; ++j) {
+            const uint32_t lo = load_le32(pattern, m, j), hi = load_le32(pattern, m, j + 4);
+            const uint32_t v = epsm_fingerprint(lo, hi, k, d.collide);
+            p->table[v] |= (uint16_t)(1u << (8 - j));
+        }
+    }
+
+    if (!(flags & EPSM_PLAN_HOST_ONLY)) {
+        hipError_t e = hipGetDevice(&p->device);
+        if (e != hipSuccess) {
+            delete p;
+            return hip_fail(e, "hipGetDevice");
+        }
+        const size_t pat_bytes = (m + 15) & ~uint64_t(15);
+        e = hipMalloc(&p->d_pattern, pat_bytes);
+        if (e == hipSuccess) e = hipMemset(p->d_pattern, 0, pat_bytes);
+        if (e == hipSuccess) e = hipMemcpy(p->d_pattern, pattern, m, hipMemcpyHostToDevice);
+        if (e == hipSuccess && fingerprint) {
+            e = hipMalloc(&p->d_table, p->table.size() * sizeof(uint16_t));
+            if (e == hipSuccess)
+                e = hipMemcpy(p->d_table, p->table.data(), p->table.size() * sizeof(uint16_t),
+                              hipMemcpyHostToDevice);
+        }
+        if (e != hipSuccess) {
+            epsm_status s = hip_fail(e, "plan device copy");
+            epsm_plan_destroy(p);
+            return s;
+        }
+        d.pattern = p->d_pattern;
+        d.table = p->d_table;
+    }
+    *out = p;
+    return EPSM_OK;
+}
+
+void epsm_plan_destroy(epsm_plan_t plan) {
+    if (!plan) return;
+    if (plan->d_pattern) (void)hipFree(plan->d_pattern);
+    if (plan->d_table) (void)hipFree(plan->d_table);
+    delete plan;
+}
+
+epsm_status epsm_plan_get_info(epsm_plan_t plan, epsm_plan_info *info) {
+    if (!plan || !info) return fail(EPSM_EINVAL, "NULL argument");
+    const DevPlan &d = plan->dev;
+    info->m = d.m;
+    info->variant = d.variant;
+    info->flags = plan->flags;
+    info->hash_bits = d.hash_bits;
+    info->prefix_words = d.nw;
+    for (int j = 0; j < 8; ++j) {
+        info->words[j] = d.pw[j];
+        info->masks[j] = d.pmask[j];
+    }
+    info->table = plan->table.empty() ? nullptr : plan->table.data();
+    info->device = plan->device;
+    return EPSM_OK;
+}
+
+epsm_status epsm_search(epsm_plan_t plan, const uint8_t *d_text, uint64_t n, int64_t *d_out,
+                        uint64_t out_capacity, uint64_t *d_n_hits, void *stream) {
+    g_last_error.clear();
+    return run_search(plan, d_text, n, d_out, out_capacity, d_n_hits, (hipStream_t)stream, true);
+}
+
+epsm_status epsm_count(epsm_plan_t plan, const uint8_t *d_text, uint64_t n, uint64_t *d_n_hits,
+                       void *stream) {
+    g_last_error.clear();
+    return run_search(plan, d_text, n, nullptr, 0, d_n_hits, (hipStream_t)stream, false);
+}
+
+epsm_status epsm_search_batch(const epsm_batch *batch, void *stream) {
+    (void)stream;
+    if (!batch) return fail(EPSM_EINVAL, "batch is NULL");
+    return fail(EPSM_EUNSUPPORTED, "batched search not built yet");
+}
+
+epsm_status epsm_reserve(void *stream, uint64_t max_n, uint64_t max_units) {
+    g_last_error.clear();
+    const uint64_t tiles = max_n / (uint64_t)g_tile.bytes() + 2 + max_units;
+    uint8_t *ws = nullptr;
+    return workspace_for((hipStream_t)stream, 256 + tiles * sizeof(uint64_t), &ws);
+}
+
+void epsm_release(void) {
+    std::lock_guard<std::mutex> lock(g_ws_mutex);
+    for (auto &kv : g_ws)
+        if (kv.second.ptr) (void)hipFree(kv.second.ptr);
+    g_ws.clear();
+    for (auto &kv : g_fault)
+        if (kv.second) (void)hipFree(kv.second);
+    g_fault.clear();
+}
+
+epsm_status epsm_stream_check(void *stream) {
+    g_last_error.clear();
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+    uint32_t *f = fault_word(s);
+    if (!f) return fail(EPSM_ENOMEM, "fault word allocation");
+    uint32_t v = 0;
+    e = hipMemcpy(&v, f, sizeof(v), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpy(fault word)");
+    if (v) return fail(EPSM_EDEVICE, "a kernel on this stream gave up a bounded wait");
+    return EPSM_OK;
+}
+
+const char *epsm_last_error(void) { return g_last_error.c_str(); }
+
+const char *epsm_status_string(epsm_status s) {
+    switch (s) {
+        case EPSM_OK: return "EPSM_OK";
+        case EPSM_EINVAL: return "EPSM_EINVAL";
+        case EPSM_ENOMEM: return "EPSM_ENOMEM";
+        case EPSM_EDEVICE: return "EPSM_EDEVICE";
+        case EPSM_EUNSUPPORTED: return "EPSM_EUNSUPPORTED";
+    }
+    return "EPSM_UNKNOWN";
+}
+
+int epsm_version(void) { return 100; }
+
+}  // extern "C"

@@ -1,0 +1,79 @@
+// Internal definitions shared by the host library and the gfx950 kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace epsm {
+
+constexpr int kWave = 64;           // CDNA wavefront width
+constexpr int kPiece = 16;          // bytes per lane per load (one dwordx4)
+constexpr int kWavePiece = kWave * kPiece;  // 1 KiB per wave per load
+
+// Status word of the single-pass scan (decoupled look-back): flag in the two
+// top bits, running count in the low 62.
+constexpr uint64_t kFlagAggregate = 1ull << 62;
+constexpr uint64_t kFlagInclusive = 2ull << 62;
+constexpr uint64_t kValueMask = (1ull << 62) - 1;
+// Upper bound on status polls per look-back step (each poll sleeps ~64
+// cycles plus a memory round trip: several seconds in total).  Every wait is
+// expected to end long before; the bound only guarantees the kernel drains.
+constexpr uint32_t kSpinLimit = 1u << 22;
+
+// Fingerprint hash of an aligned 8-byte text block (lo = bytes 0..3, hi =
+// bytes 4..7, little endian), reduced to `bits` bits.  A two-multiply
+// multiplicative hash: the top bits of the final product depend on every
+// input bit.  Any deterministic function is correct because every candidate
+// is verified exactly; this one is cheap on the VALU.
+__host__ __device__ inline uint32_t fp_hash(uint32_t lo, uint32_t hi, uint32_t bits) {
+    uint32_t x = lo ^ (hi * 0x85EBCA77u);
+    return (x * 0x9E3779B1u) >> (32u - bits);
+}
+
+// Pattern as the kernels see it (kernel argument or device array element).
+struct DevPlan {
+    uint32_t pw[8];          // pattern bytes 4j..4j+3 (little endian), 0 past m
+    uint32_t pmask[8];       // 0xFF byte lanes below m
+    uint64_t m;
+    uint32_t nw;             // words compared from registers: min(ceil(m/4), 4*NL)
+    uint32_t variant;        // 1 direct, 2 fingerprint
+    uint32_t pk;             // direct prefix kind: min(m, 4)
+    uint32_t hash_bits;      // fingerprint: k
+    uint32_t collide;        // fingerprint: constant-0 hash (test mode)
+    uint32_t nl;             // dwordx4 loads per lane per piece (2 or 3)
+    const uint16_t *table;   // fingerprint table, 2^k entries (device)
+    const uint8_t *pattern;  // full pattern (device), for m > 4*nw
+};
+
+// One search over one text.
+struct ScanArgs {
+    const uint8_t *base;     // 16-byte aligned address at or below the text start
+    uint64_t delta;          // text start - base, 0..15
+    uint64_t last;           // delta + n - m: largest valid start in base coordinates
+    uint64_t load_end;       // round_up(delta + n, 16): readable bytes from base
+    int64_t *out;            // positions (may be null when cap == 0)
+    uint64_t cap;
+    uint64_t *n_hits;        // full count (device)
+    uint64_t *status;        // [num_tiles] look-back words, zeroed before launch
+    uint32_t *ticket;        // tile counter, zeroed before launch
+    uint32_t *fault;         // set to 1 if a bounded wait gave up (never expected)
+    uint32_t num_tiles;
+    uint32_t write;          // 0: count only
+    DevPlan plan;
+};
+
+// Tile geometry of one kernel configuration.
+struct TileConfig {
+    int waves;   // waves per workgroup
+    int pieces;  // 1 KiB pieces per wave per tile
+    int bytes() const { return waves * pieces * kWavePiece; }
+};
+
+// Launchers (epsm_kernels.hip).  Return hipSuccess or the launch error.
+hipError_t launch_zero_u64(uint64_t *p, uint64_t count, hipStream_t s);
+hipError_t launch_set_u64(uint64_t *p, uint64_t value, hipStream_t s);
+hipError_t launch_scan(const ScanArgs &a, TileConfig cfg, int grid, hipStream_t s);
+int scan_blocks_per_cu(TileConfig cfg, const DevPlan &p);
+bool tile_config_supported(TileConfig cfg);
+
+}  // namespace epsm

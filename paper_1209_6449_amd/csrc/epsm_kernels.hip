@@ -1,0 +1,412 @@
+// gfx950 kernels of the exact packed string matching scan.
+//
+// Layout.  A search runs over "base coordinates": base is the text start
+// rounded down to 16 bytes and a text position s is base coordinate s+delta.
+// A tile is WAVES*PIECES KiB of base coordinates; wave w of a workgroup owns
+// the contiguous PIECES KiB at w*PIECES KiB inside the tile, and in piece u
+// lane L owns the 16 start positions [u*1024 + 16L, +16).  Each lane loads
+// its 16 bytes plus the following 16 (32 for long patterns) with dwordx4
+// buffer loads; the buffer descriptor's record count clamps reads at the
+// 16-byte-rounded text end, so the (m-1)-byte halo past a tile (Section 3.3's
+// reason for wsblend) is just the next bytes of the same coalesced stream.
+//
+// Filter.  Direct variant (m < 16, the job of EPSMa/EPSMb in Sections
+// 3.2-3.3): for each of the lane's 16 starts, the 4-byte window at that start
+// is cut from two registers with v_alignbyte and compared with the packed
+// pattern prefix (masked for m < 4); candidates are checked on the next
+// pattern words only when some lane of the wave still has one, so the common
+// case costs one alignbyte and one compare per position.  Fingerprint variant
+// (m >= 16, EPSMc of Section 3.4): every aligned 8-byte block q is hashed;
+// the table entry of the hash lists the offsets j in [0,7] with
+// h(p[j..j+7]) = h(block), and start q-j becomes a candidate.  With offsets
+// 0..7 and m >= 15 every occurrence is hit by exactly one (block, offset)
+// pair.  Candidates are then verified against the whole pattern.
+//
+// Output.  Each lane keeps a 16-bit hit mask per piece.  Tiles are taken in
+// ticket order from a counter by persistent workgroups; the tile's count is
+// published and a single-pass decoupled look-back over the predecessors'
+// status words gives its exclusive prefix, so positions are written in
+// ascending order in one pass over the text.
+#include "epsm_internal.h"
+
+namespace epsm {
+
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+// gfx9-family raw buffer descriptor word 3 (32-bit data format, no swizzle).
+constexpr int kRsrcWord3 = 0x00020000;
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const uint8_t *p, uint32_t bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<uint8_t *>(p), (short)0, (int)bytes,
+                                             kRsrcWord3);
+}
+
+__device__ __forceinline__ u32x4 load16(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+    return __builtin_amdgcn_raw_buffer_load_b128(r, (int)off, 0, 0);
+}
+
+// Window of 4 text bytes starting at byte k of the lane's register run w.
+template <int N>
+__device__ __forceinline__ uint32_t window(const uint32_t (&w)[N], int k) {
+    const int q = k >> 2, r = k & 3;
+    return r == 0 ? w[q] : __builtin_amdgcn_alignbyte(w[q + 1], w[q], (uint32_t)r);
+}
+
+__device__ __forceinline__ uint64_t ballot(bool c) { return __builtin_amdgcn_ballot_w64(c); }
+__device__ __forceinline__ bool wave_any(bool c) { return ballot(c) != 0; }
+
+// Narrow a wave mask of candidates at lane byte k with pattern words
+// j0..nw-1 (each compare is one v_cmp whose result is the wave mask itself).
+// Stops as soon as no lane of the wave has a candidate left.
+template <int NWMAX, int N>
+__device__ __forceinline__ uint64_t verify_words(const uint32_t (&w)[N], int k, uint64_t b, int j0,
+                                                 const DevPlan &p) {
+#pragma unroll
+    for (int j = 0; j < NWMAX; ++j) {
+        if (j >= j0 && j < (int)p.nw && b != 0)
+            b &= ballot((window(w, k + 4 * j) & p.pmask[j]) == p.pw[j]);
+    }
+    return b;
+}
+
+// Per-lane 16-bit mask from the 16 wave masks: bit k of lane L is bit L of b[k].
+__device__ __forceinline__ uint32_t lanes_from_masks(const uint64_t (&b)[16]) {
+    uint32_t lm = 0;
+#pragma unroll
+    for (int k = 15; k >= 0; --k)
+        lm = lm + lm + (__builtin_amdgcn_inverse_ballot_w64(b[k]) ? 1u : 0u);
+    return lm;
+}
+
+// Direct variant: 16-bit hit mask of one lane piece (positions 0..15).
+template <int NL, int PK>
+__device__ __forceinline__ uint32_t direct_mask(const uint32_t (&w)[NL * 4 + 1], const DevPlan &p) {
+    constexpr int NWMAX = 4 * NL - 4;
+    uint64_t b[16];
+    uint64_t any = 0;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+        const int q = k >> 2, r = k & 3;
+        bool c;
+        if constexpr (PK == 1) {
+            c = ((w[q] >> (8 * r)) & 0xFFu) == p.pw[0];
+        } else if constexpr (PK == 2) {
+            c = (window(w, k) & 0xFFFFu) == p.pw[0];
+        } else if constexpr (PK == 3) {
+            // bytes k..k+2 of the run and a zero top byte in one v_perm
+            const uint32_t sel = (uint32_t)r | ((uint32_t)(r + 1) << 8) |
+                                 ((uint32_t)(r + 2) << 16) | (0x0Cu << 24);
+            c = __builtin_amdgcn_perm(w[q + 1], w[q], sel) == p.pw[0];
+        } else {
+            c = window(w, k) == p.pw[0];
+        }
+        uint64_t bk = ballot(c);
+        if constexpr (PK >= 4) bk = verify_words<NWMAX>(w, k, bk, 1, p);
+        b[k] = bk;
+        any |= bk;
+    }
+    return any ? lanes_from_masks(b) : 0u;
+}
+
+// Fingerprint variant: the lane hashes the blocks at its byte 0, 8 and 16
+// (the last one is the next lane's first block).  Table entry bit (8-j)
+// marks offset j, so the candidates relative to the lane start are
+// block0: bit 8 -> start 0; block8: bits 1..8 -> starts 1..8;
+// block16: bits 1..7 -> starts 9..15 (bit 8 = start 16 belongs to the next lane).
+template <int NL>
+__device__ __forceinline__ uint32_t fingerprint_mask(const uint32_t (&w)[NL * 4 + 1],
+                                                     const DevPlan &p, const uint16_t *tab) {
+    constexpr int NWMAX = 4 * NL - 4;
+    uint32_t v0 = 0, v1 = 0, v2 = 0;
+    if (!p.collide) {
+        v0 = fp_hash(w[0], w[1], p.hash_bits);
+        v1 = fp_hash(w[2], w[3], p.hash_bits);
+        v2 = fp_hash(w[4], w[5], p.hash_bits);
+    }
+    const uint32_t cm = ((uint32_t)tab[v0] >> 8) | (uint32_t)tab[v1] |
+                        (((uint32_t)tab[v2] << 8) & 0xFFFFu);
+    if (!wave_any(cm != 0)) return 0u;
+    uint64_t b[16];
+    uint64_t any = 0;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+        uint64_t bk = ballot((cm >> k) & 1u);
+        if (bk) bk = verify_words<NWMAX>(w, k, bk, 0, p);
+        b[k] = bk;
+        any |= bk;
+    }
+    return any ? lanes_from_masks(b) : 0u;
+}
+
+// Start positions of the lane piece at base coordinate s0 that are valid
+// (delta <= s <= last), as a 16-bit mask.
+__device__ __forceinline__ uint32_t valid_mask(uint64_t s0, uint64_t delta, uint64_t last) {
+    uint32_t lo = 0, hi = 16;
+    if (delta > s0) lo = (delta - s0) > 16 ? 16u : (uint32_t)(delta - s0);
+    if (last < s0) hi = 0;
+    else if (last - s0 < 15) hi = (uint32_t)(last - s0) + 1;
+    return ((1u << hi) - 1u) & ~((1u << lo) - 1u);
+}
+
+// Exact check of pattern bytes [4*nw, m) for each candidate (patterns longer
+// than the register run); reads the text and pattern from global memory.
+__device__ __noinline__ uint32_t tail_check(uint32_t mk, uint64_t s0, const uint8_t *base,
+                                            const uint8_t *pattern, uint64_t m, uint32_t from) {
+    uint32_t keep = 0;
+    while (mk) {
+        const uint32_t k = __builtin_ctz(mk);
+        mk &= mk - 1;
+        const uint8_t *t = base + s0 + k;
+        bool ok = true;
+        for (uint64_t j = from; j < m; ++j) {
+            if (t[j] != pattern[j]) { ok = false; break; }
+        }
+        if (ok) keep |= 1u << k;
+    }
+    return keep;
+}
+
+__device__ __forceinline__ uint32_t wave_sum32(uint32_t v) {
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, kWave);
+    return v;
+}
+
+__device__ __forceinline__ uint64_t wave_sum64(uint64_t v) {
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, kWave);
+    return v;
+}
+
+__device__ __forceinline__ uint32_t wave_incl_scan32(uint32_t v, int lane) {
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+        const uint32_t t = __shfl_up(v, d, kWave);
+        if (lane >= d) v += t;
+    }
+    return v;
+}
+
+__device__ __forceinline__ void status_store(uint64_t *p, uint64_t v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ uint64_t status_load(uint64_t *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Single-pass look-back, run by one full wave.  Publishes the tile's count,
+// walks back over predecessors 64 at a time until an inclusive prefix is
+// found, publishes the tile's inclusive prefix, returns the exclusive one.
+// Every wait ends: a tile's aggregate is published before its own look-back,
+// and tiles are ticketed in order, so all predecessors are running or done.
+__device__ uint64_t look_back(uint64_t *status, uint32_t tile, uint64_t cnt, int lane,
+                              uint32_t *fault) {
+    if (tile == 0) {
+        if (lane == 0) status_store(&status[0], kFlagInclusive | cnt);
+        return 0;
+    }
+    if (lane == 0) status_store(&status[tile], kFlagAggregate | cnt);
+    uint64_t excl = 0;
+    int64_t top = (int64_t)tile - 1;
+    for (;;) {
+        const int64_t idx = top - lane;
+        uint64_t st = kFlagInclusive;  // before tile 0: an inclusive zero
+        if (idx >= 0) {
+            st = status_load(&status[idx]);
+            uint32_t polls = 0;
+            while ((st >> 62) == 0) {
+                if (++polls == kSpinLimit) {
+                    __hip_atomic_store(fault, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    st = kFlagInclusive;
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(1);
+                st = status_load(&status[idx]);
+            }
+        }
+        const uint64_t incl = __ballot((st >> 62) == 2);
+        const int first = incl ? __ffsll((unsigned long long)incl) - 1 : kWave;
+        const uint64_t v = lane <= first ? (st & kValueMask) : 0;
+        excl += wave_sum64(v);
+        if (incl) break;
+        top -= kWave;
+    }
+    if (lane == 0) status_store(&status[tile], kFlagInclusive | (excl + cnt));
+    return excl;
+}
+
+template <int WAVES, int U, int NL, int VAR, int PK>
+__global__ __launch_bounds__(WAVES * kWave) void scan_kernel(ScanArgs a) {
+    extern __shared__ __attribute__((aligned(16))) uint16_t s_table[];
+    __shared__ uint32_t s_tile;
+    __shared__ uint32_t s_wcnt[WAVES];
+    __shared__ uint64_t s_excl;
+    constexpr uint32_t kTile = WAVES * U * kWavePiece;
+    const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
+
+    if constexpr (VAR == 2) {
+        const uint32_t words = (1u << a.plan.hash_bits) / 8;  // 16-byte rows of the table
+        const u32x4 *src = reinterpret_cast<const u32x4 *>(a.plan.table);
+        u32x4 *dst = reinterpret_cast<u32x4 *>(s_table);
+        for (uint32_t i = tid; i < words; i += WAVES * kWave) dst[i] = src[i];
+    }
+
+    for (;;) {
+        if (tid == 0) s_tile = atomicAdd(a.ticket, 1u);
+        __syncthreads();
+        const uint32_t tile = s_tile;
+        if (tile >= a.num_tiles) break;
+
+        const uint64_t tile_start = (uint64_t)tile * kTile;
+        const uint64_t avail = a.load_end - tile_start;
+        const uint32_t nrec = avail > 0xFFFFFFF0ull ? 0xFFFFFFF0u : (uint32_t)avail;
+        const __amdgpu_buffer_rsrc_t rsrc = make_rsrc(a.base + tile_start, nrec);
+        const uint32_t lane_off = (uint32_t)wave * U * kWavePiece + (uint32_t)lane * kPiece;
+
+        uint32_t w[U][NL * 4 + 1];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+#pragma unroll
+            for (int l = 0; l < NL; ++l) {
+                const u32x4 v = load16(rsrc, lane_off + u * kWavePiece + l * kPiece);
+                w[u][4 * l + 0] = v.x;
+                w[u][4 * l + 1] = v.y;
+                w[u][4 * l + 2] = v.z;
+                w[u][4 * l + 3] = v.w;
+            }
+            w[u][NL * 4] = 0;
+        }
+
+        uint32_t lm[U];
+        uint32_t cnt = 0;
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            uint32_t mk;
+            if constexpr (VAR == 1) mk = direct_mask<NL, PK>(w[u], a.plan);
+            else mk = fingerprint_mask<NL>(w[u], a.plan, s_table);
+            const uint64_t s0 = tile_start + lane_off + u * kWavePiece;
+            // only the first tile holds starts below delta and only the last
+            // one starts past `last`
+            if (tile == 0 || tile == a.num_tiles - 1) mk &= valid_mask(s0, a.delta, a.last);
+            if (a.plan.m > 4u * a.plan.nw && wave_any(mk != 0)) mk = tail_check(mk, s0, a.base, a.plan.pattern, a.plan.m, 4u * a.plan.nw);
+            lm[u] = mk;
+            cnt += __popc(mk);
+        }
+
+        const uint32_t wtot = wave_sum32(cnt);
+        if (lane == 0) s_wcnt[wave] = wtot;
+        __syncthreads();
+        if (wave == 0) {
+            uint64_t tile_cnt = 0;
+#pragma unroll
+            for (int i = 0; i < WAVES; ++i) tile_cnt += s_wcnt[i];
+            const uint64_t excl = look_back(a.status, tile, tile_cnt, lane, a.fault);
+            if (lane == 0) {
+                s_excl = excl;
+                if (tile == a.num_tiles - 1) *a.n_hits = excl + tile_cnt;
+            }
+        }
+        __syncthreads();
+
+        if (a.write) {
+            uint64_t obase = s_excl;
+            for (int i = 0; i < wave; ++i) obase += s_wcnt[i];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const uint32_t c = __popc(lm[u]);
+                if (wave_any(c != 0)) {
+                    const uint32_t incl = wave_incl_scan32(c, lane);
+                    const uint32_t tot = __shfl(incl, kWave - 1, kWave);
+                    uint64_t idx = obase + (incl - c);
+                    const int64_t pos0 =
+                        (int64_t)(tile_start + lane_off + u * kWavePiece) - (int64_t)a.delta;
+                    uint32_t bits = lm[u];
+                    while (bits) {
+                        const uint32_t k = __builtin_ctz(bits);
+                        bits &= bits - 1;
+                        if (idx < a.cap) a.out[idx] = pos0 + k;
+                        ++idx;
+                    }
+                    obase += tot;
+                }
+            }
+        }
+        __syncthreads();
+    }
+}
+
+__global__ void zero_u64_kernel(uint64_t *p, uint64_t count) {
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += stride) p[i] = 0;
+}
+
+__global__ void set_u64_kernel(uint64_t *p, uint64_t value) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) *p = value;
+}
+
+hipError_t launch_zero_u64(uint64_t *p, uint64_t count, hipStream_t s) {
+    if (count == 0) return hipSuccess;
+    uint64_t blocks = (count + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(zero_u64_kernel, dim3((uint32_t)blocks), dim3(256), 0, s, p, count);
+    return hipGetLastError();
+}
+
+hipError_t launch_set_u64(uint64_t *p, uint64_t value, hipStream_t s) {
+    hipLaunchKernelGGL(set_u64_kernel, dim3(1), dim3(64), 0, s, p, value);
+    return hipGetLastError();
+}
+
+typedef void (*ScanFn)(ScanArgs);
+
+template <int WAVES, int U>
+static ScanFn pick(const DevPlan &p) {
+    if (p.variant == 2) return scan_kernel<WAVES, U, 3, 2, 4>;
+    if (p.nl == 3) return scan_kernel<WAVES, U, 3, 1, 4>;
+    switch (p.pk) {
+        case 1: return scan_kernel<WAVES, U, 2, 1, 1>;
+        case 2: return scan_kernel<WAVES, U, 2, 1, 2>;
+        case 3: return scan_kernel<WAVES, U, 2, 1, 3>;
+        default: return scan_kernel<WAVES, U, 2, 1, 4>;
+    }
+}
+
+static ScanFn pick_fn(TileConfig cfg, const DevPlan &p) {
+    if (cfg.waves == 4 && cfg.pieces == 4) return pick<4, 4>(p);
+    if (cfg.waves == 4 && cfg.pieces == 2) return pick<4, 2>(p);
+    if (cfg.waves == 4 && cfg.pieces == 1) return pick<4, 1>(p);
+    if (cfg.waves == 8 && cfg.pieces == 2) return pick<8, 2>(p);
+    return nullptr;
+}
+
+bool tile_config_supported(TileConfig cfg) {
+    DevPlan p{};
+    p.variant = 1;
+    p.nl = 2;
+    p.pk = 4;
+    return pick_fn(cfg, p) != nullptr;
+}
+
+static size_t table_bytes(const DevPlan &p) {
+    return p.variant == 2 ? ((size_t)2 << p.hash_bits) : 0;
+}
+
+int scan_blocks_per_cu(TileConfig cfg, const DevPlan &p) {
+    ScanFn fn = pick_fn(cfg, p);
+    if (!fn) return 0;
+    int blocks = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, fn, cfg.waves * kWave,
+                                                     table_bytes(p)) != hipSuccess)
+        return 0;
+    return blocks;
+}
+
+hipError_t launch_scan(const ScanArgs &a, TileConfig cfg, int grid, hipStream_t s) {
+    ScanFn fn = pick_fn(cfg, a.plan);
+    if (!fn) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(fn, dim3(grid), dim3(cfg.waves * kWave), table_bytes(a.plan), s, a);
+    return hipGetLastError();
+}
+
+}  // namespace epsm

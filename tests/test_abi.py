@@ -1,0 +1,132 @@
+"""Host-side checks of the C ABI (no GPU compute): symbols, plan logic, errors."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_1209_6449_amd as epsm
+from paper_1209_6449_amd import _lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "epsm.h")
+
+
+def declared_functions() -> list[str]:
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(epsm_[a-z_]+)\s*\(", src)) - {"epsm_plan_s"})
+
+
+def test_library_exports_every_declared_symbol():
+    names = declared_functions()
+    assert "epsm_search" in names and "epsm_search_batch" in names and "epsm_count" in names
+    lib = ctypes.CDLL(_lib.LIB_PATH)
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing, missing
+    # the binding declares the same set
+    assert sorted(_lib.SIGNATURES) == names
+
+
+def test_version_and_status_strings():
+    L = epsm.lib()
+    assert L.epsm_version() >= 100
+    assert L.epsm_status_string(0) == b"EPSM_OK"
+    assert L.epsm_status_string(4) == b"EPSM_EUNSUPPORTED"
+
+
+def host_plan(p: bytes, flags: int = 0) -> dict:
+    return epsm.Plan(p, flags | epsm.PLAN_HOST_ONLY).info()
+
+
+@pytest.mark.parametrize("m", list(range(1, 16)))
+def test_short_patterns_use_direct_variant(m):
+    info = host_plan(bytes(range(1, m + 1)))
+    assert info["variant"] == epsm.VARIANT_DIRECT and info["table"] is None
+    assert info["device"] == -1
+
+
+@pytest.mark.parametrize("m", [16, 17, 24, 31, 32, 33, 100])
+def test_long_patterns_use_fingerprint_variant(m):
+    info = host_plan(bytes((7 * i) % 251 for i in range(m)))
+    assert info["variant"] == epsm.VARIANT_FINGERPRINT and info["hash_bits"] == 11
+
+
+def test_packed_words_and_masks_little_endian():
+    p = bytes([0x00, 0x11, 0x22, 0x33, 0x44, 0x55])
+    info = host_plan(p)
+    assert info["words"][0] == 0x33221100 and info["words"][1] == 0x5544
+    assert info["masks"][0] == 0xFFFFFFFF and info["masks"][1] == 0xFFFF and info["masks"][2] == 0
+    assert info["prefix_words"] == 2
+
+
+def le32(b: bytes, at: int) -> int:
+    return int.from_bytes(b[at:at + 4], "little")
+
+
+@pytest.mark.parametrize("bits", [8, 11, 14])
+def test_fingerprint_table_is_section_3_4_bucket_map(bits):
+    """Bucket h(p[j..j+7]) holds offset j (bit 8-j) for j in 0..7, and nothing else."""
+    L = epsm.lib()
+    rng = np.random.default_rng(bits)
+    for m in (15, 16, 20, 32, 40):
+        p = rng.integers(0, 4, m).astype(np.uint8).tobytes()
+        flags = epsm.PLAN_HASH_BITS(bits) | (epsm.PLAN_FORCE_FINGERPRINT if m == 15 else 0)
+        info = host_plan(p, flags)
+        table = info["table"]
+        assert len(table) == 1 << bits
+        expect = [0] * (1 << bits)
+        for j in range(8):
+            v = L.epsm_fingerprint(le32(p, j), le32(p, j + 4), bits, 0)
+            assert v < (1 << bits)
+            expect[v] |= 1 << (8 - j)
+        assert table == expect
+
+
+def test_collide_mode_puts_every_offset_in_bucket_zero():
+    info = host_plan(bytes(range(20)), epsm.PLAN_COLLIDE)
+    assert info["table"][0] == 0b111111110 and not any(info["table"][1:])
+
+
+def test_force_flags():
+    assert host_plan(b"x" * 20, epsm.PLAN_FORCE_DIRECT)["variant"] == epsm.VARIANT_DIRECT
+    assert host_plan(b"x" * 15, epsm.PLAN_FORCE_FINGERPRINT)["variant"] == epsm.VARIANT_FINGERPRINT
+
+
+@pytest.mark.parametrize("pattern,flags", [
+    (b"", 0),                                                        # m == 0
+    (b"abc", epsm.PLAN_FORCE_FINGERPRINT),                           # needs m >= 15
+    (b"abc", epsm.PLAN_FORCE_DIRECT | epsm.PLAN_FORCE_FINGERPRINT),  # exclusive
+    (b"abc", 0x10000),                                               # unknown flag
+    (b"a" * 20, epsm.PLAN_HASH_BITS(5)),                             # k out of range
+])
+def test_plan_rejects_bad_arguments(pattern, flags):
+    with pytest.raises(epsm.EpsmError) as e:
+        epsm.Plan(pattern, flags | epsm.PLAN_HOST_ONLY)
+    assert e.value.status == _lib.EPSM_EINVAL and e.value.detail
+
+
+def test_plan_rejects_too_long_pattern():
+    with pytest.raises(epsm.EpsmError) as e:
+        epsm.Plan(b"a" * (epsm.MAX_M + 1), epsm.PLAN_HOST_ONLY)
+    assert e.value.status == _lib.EPSM_EUNSUPPORTED
+
+
+def test_null_arguments_rejected():
+    L = epsm.lib()
+    out = ctypes.c_void_p()
+    assert L.epsm_plan(None, 3, 0, ctypes.byref(out)) == _lib.EPSM_EINVAL
+    assert L.epsm_plan_get_info(None, None) == _lib.EPSM_EINVAL
+    assert L.epsm_search(None, None, 0, None, 0, None, None) == _lib.EPSM_EINVAL
+    assert L.epsm_count(None, None, 0, None, None) == _lib.EPSM_EINVAL
+    assert L.epsm_search_batch(None, None) == _lib.EPSM_EINVAL
+
+
+def test_host_only_plan_is_rejected_by_search():
+    plan = epsm.Plan(b"abc", epsm.PLAN_HOST_ONLY)
+    L = epsm.lib()
+    dummy = ctypes.c_uint64()
+    st = L.epsm_search(plan.handle, ctypes.addressof(dummy), 8, None, 0, ctypes.addressof(dummy), None)
+    assert st == _lib.EPSM_EINVAL
+    assert b"host-only" in L.epsm_last_error()

@@ -1,0 +1,211 @@
+"""GPU parity: positions and counts from the HIP kernels equal the CPU oracle.
+
+Integer work, so the bar is bit-exact equality of the int64 position arrays
+and of the counts.  Each case prints its parameters before touching the GPU.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TILE = 16 * 1024  # default workgroup tile (4 waves x 4 KiB)
+
+
+@pytest.fixture(scope="module")
+def epsm():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1209_6449_amd as mod
+    mod.lib()
+    return mod
+
+
+def say(msg: str) -> None:
+    print(msg, flush=True)
+
+
+def to_gpu(arr: np.ndarray, offset: int = 0) -> torch.Tensor:
+    """Device copy of arr starting `offset` bytes into a fresh allocation."""
+    buf = torch.zeros(arr.size + offset + 1, dtype=torch.uint8, device="cuda")
+    if arr.size:
+        buf[offset:offset + arr.size] = torch.from_numpy(np.ascontiguousarray(arr)).cuda()
+    return buf[offset:offset + arr.size]
+
+
+def check(epsm, text: np.ndarray, pattern: bytes, flags: int = 0, offset: int = 0, label: str = ""):
+    say(f"case {label} n={text.size} m={len(pattern)} flags={flags:#x} offset={offset}")
+    t = to_gpu(text, offset)
+    plan = epsm.Plan(pattern, flags)
+    got = epsm.search(t, plan).cpu().numpy()
+    exp = oracle.positions(text, pattern)
+    assert got.dtype == np.int64
+    assert np.array_equal(got, exp), (label, len(got), len(exp), got[:10], exp[:10])
+    assert epsm.count(t, plan) == exp.size
+    epsm.stream_check()
+    return exp.size
+
+
+def test_config1_all_patterns(epsm):
+    """1 MiB ACGT text, 100 patterns cut from it (25 per m in {2,4,8,16})."""
+    spec, cases = W.config1()
+    text = W.gen_numpy(spec)
+    t = to_gpu(text)
+    for i, c in enumerate(cases):
+        say(f"config1 pattern {i} m={len(c.pattern)} offset={c.offset}")
+        got = epsm.search(t, c.pattern).cpu().numpy()
+        exp = oracle.positions(text, c.pattern)
+        assert np.array_equal(got, exp), i
+        assert c.offset in set(exp.tolist())
+    epsm.stream_check()
+
+
+EDGE_NS = [1, 2, 3, 4, 5, 7, 8, 15, 16, 17, 31, 32, 33, 63, 64, 65, 1023, 1024, 1025,
+           TILE - 1, TILE, TILE + 1, 2 * TILE + 33, 3 * TILE + 7]
+
+
+@pytest.mark.parametrize("m", list(range(1, 34)) + [40, 64, 100])
+def test_edge_lengths_binary_text(epsm, m):
+    """sigma = 2 text (many hits), n around lane/wave/tile boundaries, cut patterns."""
+    rng = np.random.default_rng(1000 + m)
+    for n in [x for x in EDGE_NS if x >= 1] + [m - 1, m, m + 1]:
+        if n <= 0:
+            continue
+        text = rng.integers(0, 2, n).astype(np.uint8)
+        if n >= m:
+            # patterns cut at the very start and the very end of the text
+            check(epsm, text, text[:m].tobytes(), label="start")
+            check(epsm, text, text[n - m:].tobytes(), label="end")
+        else:
+            check(epsm, text, rng.integers(0, 2, m).astype(np.uint8).tobytes(), label="long")
+
+
+def test_empty_text_and_pattern_longer_than_text(epsm):
+    hits = torch.full((1,), 99, dtype=torch.int64, device="cuda")
+    plan = epsm.Plan(b"abc")
+    empty = torch.zeros(0, dtype=torch.uint8, device="cuda")
+    say("case empty text")
+    epsm.search_into(plan, empty, None, hits)
+    assert int(hits.item()) == 0
+    hits.fill_(99)
+    say("case m > n")
+    epsm.search_into(plan, torch.zeros(2, dtype=torch.uint8, device="cuda"), None, hits)
+    assert int(hits.item()) == 0
+
+
+@pytest.mark.parametrize("offset", range(16))
+def test_unaligned_text_start(epsm, offset):
+    rng = np.random.default_rng(offset)
+    text = rng.integers(0, 3, 3 * TILE + 5).astype(np.uint8)
+    for m in (1, 2, 3, 4, 5, 9, 15, 16, 17, 32, 33):
+        check(epsm, text, text[:m].tobytes(), offset=offset, label="unaligned-start")
+        check(epsm, text, text[-m:].tobytes(), offset=offset, label="unaligned-end")
+
+
+@pytest.mark.parametrize("sigma", [1, 2, 4, 20, 64, 128, 256])
+def test_alphabet_sizes(epsm, sigma):
+    rng = np.random.default_rng(sigma)
+    n = 5 * TILE + 77
+    text = rng.integers(0, sigma, n).astype(np.uint8)
+    for m in (1, 2, 3, 4, 5, 6, 7, 8, 9, 11, 12, 13, 15, 16, 17, 20, 24, 28, 31, 32, 33, 48):
+        o = int(rng.integers(0, n - m + 1))
+        check(epsm, text, text[o:o + m].tobytes(), label=f"sigma{sigma}-cut")
+        check(epsm, text, rng.integers(0, sigma, m).astype(np.uint8).tobytes(),
+              label=f"sigma{sigma}-random")
+
+
+def test_zero_and_ff_bytes(epsm):
+    rng = np.random.default_rng(7)
+    n = 2 * TILE + 100
+    text = np.where(rng.random(n) < 0.5, 0, 255).astype(np.uint8)
+    text[rng.integers(0, n, 200)] = 0x7F
+    for m in (1, 2, 3, 4, 7, 8, 12, 16, 19, 32):
+        check(epsm, text, bytes([0] * m), label="zeros")
+        check(epsm, text, bytes([255] * m), label="ffs")
+        o = int(rng.integers(0, n - m))
+        check(epsm, text, text[o:o + m].tobytes(), label="mixed")
+
+
+@pytest.mark.parametrize("m", [15, 16, 17, 20, 24, 31, 32, 33, 40, 64])
+def test_forced_variants_agree(epsm, m):
+    rng = np.random.default_rng(m)
+    text = rng.integers(0, 4, 3 * TILE + 11).astype(np.uint8)
+    o = int(rng.integers(0, text.size - m))
+    p = text[o:o + m].tobytes()
+    check(epsm, text, p, epsm.PLAN_FORCE_DIRECT, label="force-direct")
+    check(epsm, text, p, epsm.PLAN_FORCE_FINGERPRINT, label="force-fingerprint")
+    check(epsm, text, p, epsm.PLAN_FORCE_FINGERPRINT | epsm.PLAN_COLLIDE, label="collide")
+
+
+@pytest.mark.parametrize("bits", [8, 9, 12, 14])
+def test_hash_width_does_not_change_output(epsm, bits):
+    rng = np.random.default_rng(bits)
+    text = rng.integers(0, 2, 2 * TILE + 3).astype(np.uint8)
+    for m in (16, 23, 32):
+        o = int(rng.integers(0, text.size - m))
+        check(epsm, text, text[o:o + m].tobytes(), epsm.PLAN_HASH_BITS(bits), label=f"k{bits}")
+
+
+def test_periodic_patterns_collide_in_one_bucket(epsm):
+    text = np.frombuffer(b"ab" * (3 * TILE), dtype=np.uint8)
+    for m in (16, 17, 20, 32):
+        check(epsm, text, (b"ab" * 20)[:m], label="period2")
+        check(epsm, text, (b"ba" * 20)[:m], label="period2-shift")
+
+
+@pytest.mark.parametrize("m", [1, 2, 3, 4, 8, 15, 16, 31, 32, 33])
+def test_unary_text_closed_form(epsm, m):
+    """a^n with a^m: positions 0..n-m exactly (checked against the closed form)."""
+    n = 2 * 1024 * 1024 + 13
+    say(f"case unary n={n} m={m}")
+    t = torch.full((n,), 0x61, dtype=torch.uint8, device="cuda")
+    got = epsm.search(t, b"a" * m)
+    assert got.numel() == n - m + 1
+    assert torch.equal(got, torch.arange(n - m + 1, dtype=torch.int64, device="cuda"))
+    epsm.stream_check()
+
+
+def test_truncated_output_is_prefix_and_count_is_full(epsm):
+    n = 100_000
+    t = torch.full((n,), 0x61, dtype=torch.uint8, device="cuda")
+    plan = epsm.Plan(b"aa")
+    for cap in (0, 1, 17, 5000, n - 1 - 1, n - 1, n + 10):
+        say(f"case truncation cap={cap}")
+        out = torch.full((max(cap, 1),), -7, dtype=torch.int64, device="cuda")
+        hits = torch.zeros(1, dtype=torch.int64, device="cuda")
+        epsm.search_into(plan, t, out[:cap] if cap else None, hits)
+        assert int(hits.item()) == n - 1
+        k = min(cap, n - 1)
+        assert torch.equal(out[:k].cpu(), torch.arange(k, dtype=torch.int64))
+        if cap > n - 1:
+            assert bool((out[n - 1:cap] == -7).all())
+
+
+def test_repeated_runs_are_identical(epsm):
+    rng = np.random.default_rng(3)
+    text = rng.integers(0, 2, 7 * TILE + 9).astype(np.uint8)
+    t = to_gpu(text)
+    for p in (b"\x00", b"\x01\x00\x01", bytes(text[100:117])):
+        say(f"case determinism m={len(p)}")
+        a = epsm.search(t, p)
+        b = epsm.search(t, p)
+        assert torch.equal(a, b)
+
+
+def test_positions_are_sound_and_increasing_random(epsm):
+    """Randomised sizes/alphabets/patterns; full equality with the oracle."""
+    rng = np.random.default_rng(12345)
+    for i in range(60):
+        sigma = int(rng.choice([1, 2, 3, 4, 8, 20, 64, 256]))
+        n = int(rng.integers(1, 200_000))
+        m = int(rng.integers(1, 40))
+        text = rng.integers(0, sigma, n).astype(np.uint8)
+        if n >= m and rng.random() < 0.6:
+            o = int(rng.integers(0, n - m + 1))
+            p = text[o:o + m].tobytes()
+        else:
+            p = rng.integers(0, sigma, m).astype(np.uint8).tobytes()
+        check(epsm, text, p, offset=int(rng.integers(0, 16)), label=f"random{i}")
