@@ -171,6 +171,15 @@ typedef struct {
  */
 epsm_status epsm_search_batch(const epsm_batch *batch, void *stream);
 
+/* ---- tuning ------------------------------------------------------------- */
+
+/* Select the workgroup tile used by later single-text searches: `waves`
+ * wavefronts of 64 lanes per workgroup, each scanning `pieces` KiB per tile
+ * (tile = waves * pieces KiB).  Built configurations: 8x16 (default), 8x8,
+ * 4x16, 16x8, 16x16; others return EPSM_EUNSUPPORTED.  Process-wide; not thread safe
+ * against concurrent searches.  Output never depends on the choice. */
+epsm_status epsm_set_tile_config(uint32_t waves, uint32_t pieces);
+
 /* ---- workspace and diagnostics -------------------------------------------- */
 
 /* Make sure the workspace tied to `stream` can serve texts of up to max_n

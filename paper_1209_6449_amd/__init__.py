@@ -150,6 +150,11 @@ def search(text: torch.Tensor, pattern, flags: int = 0, stream=None) -> torch.Te
     return out
 
 
+def set_tile_config(waves: int, pieces: int) -> None:
+    """Workgroup tile for later searches: waves x pieces KiB (output is unaffected)."""
+    _check(lib().epsm_set_tile_config(waves, pieces), "epsm_set_tile_config")
+
+
 def stream_check(stream=None) -> None:
     """Synchronise the stream; raise if a kernel on it gave up a bounded wait."""
     _check(lib().epsm_stream_check(_stream_handle(stream)), "epsm_stream_check")

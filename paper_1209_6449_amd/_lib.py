@@ -80,6 +80,7 @@ SIGNATURES = {
     "epsm_count": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64,
                                   ctypes.c_void_p, ctypes.c_void_p]),
     "epsm_search_batch": (ctypes.c_int, [ctypes.POINTER(Batch), ctypes.c_void_p]),
+    "epsm_set_tile_config": (ctypes.c_int, [ctypes.c_uint32, ctypes.c_uint32]),
     "epsm_reserve": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint64]),
     "epsm_release": (None, []),
     "epsm_stream_check": (ctypes.c_int, [ctypes.c_void_p]),

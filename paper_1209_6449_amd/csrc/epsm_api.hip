@@ -46,11 +46,10 @@ constexpr uint32_t kKnownPlanFlags = EPSM_PLAN_HOST_ONLY | EPSM_PLAN_FORCE_DIREC
                                      EPSM_PLAN_HASH_BITS(0xF);
 constexpr uint32_t kDefaultHashBits = 11;  // k = 11 in Section 3.4
 
-// Default tile: 4 waves x 4 KiB per wave = 16 KiB per workgroup tile.
-TileConfig g_tile = {4, 4};
-int g_cus = 0;
+// Default tile: 8 waves x 16 KiB per wave = 128 KiB per workgroup tile.
+TileConfig g_tile = {8, 16};
 
-// ---- workspace: look-back status words + ticket, one buffer per stream ----
+// ---- workspace: look-back status words, one buffer per stream ----
 struct Workspace {
     uint8_t *ptr = nullptr;
     size_t bytes = 0;
@@ -108,17 +107,6 @@ uint32_t *fault_word(hipStream_t stream) {
     return f;
 }
 
-int cu_count() {
-    if (g_cus == 0) {
-        int dev = 0, cus = 0;
-        if (hipGetDevice(&dev) == hipSuccess &&
-            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess)
-            g_cus = cus;
-        if (g_cus <= 0) g_cus = 256;
-    }
-    return g_cus;
-}
-
 uint32_t load_le32(const uint8_t *p, uint64_t m, uint64_t at) {
     uint32_t v = 0;
     for (int b = 0; b < 4; ++b)
@@ -162,25 +150,28 @@ epsm_status run_search(epsm_plan_t plan, const uint8_t *d_text, uint64_t n, int6
     a.plan = plan->dev;
     const uint64_t tile_bytes = (uint64_t)g_tile.bytes();
     const uint64_t tiles = (a.last + 1 + tile_bytes - 1) / tile_bytes;
-    if (tiles > 0xFFFFFFF0ull) return fail(EPSM_EUNSUPPORTED, "text too long for 32-bit tile tickets");
+    if (tiles > 0x7FFFFFFFull) return fail(EPSM_EUNSUPPORTED, "text too long for the tile grid");
     a.num_tiles = (uint32_t)tiles;
 
     uint8_t *ws = nullptr;
-    const size_t ws_bytes = 256 + (size_t)tiles * sizeof(uint64_t);
+    // workspace: [count bins][look-back status words]
+    const size_t bins_bytes = kCountBins * sizeof(uint64_t);
+    const size_t ws_bytes = bins_bytes + (write ? (size_t)tiles * sizeof(uint64_t) : 0);
     st = workspace_for(stream, ws_bytes, &ws);
     if (st != EPSM_OK) return st;
-    a.ticket = (uint32_t *)ws;
-    a.status = (uint64_t *)(ws + 256);
+    a.bins = (uint64_t *)ws;
+    a.status = (uint64_t *)(ws + bins_bytes);
     a.fault = fault_word(stream);
     if (!a.fault) return fail(EPSM_ENOMEM, "fault word allocation");
     hipError_t e = launch_zero_u64((uint64_t *)ws, ws_bytes / 8, stream);
     if (e != hipSuccess) return hip_fail(e, "launch(zero)");
 
-    int per_cu = scan_blocks_per_cu(g_tile, a.plan);
-    if (per_cu <= 0) per_cu = 1;
-    const uint64_t grid = std::min<uint64_t>(tiles, (uint64_t)per_cu * cu_count());
-    e = launch_scan(a, g_tile, (int)grid, stream);
+    e = launch_scan(a, g_tile, (int)tiles, stream);
     if (e != hipSuccess) return hip_fail(e, "launch(scan)");
+    if (!write) {
+        e = launch_sum_bins(a.bins, d_n_hits, stream);
+        if (e != hipSuccess) return hip_fail(e, "launch(sum_bins)");
+    }
     return EPSM_OK;
 }
 
@@ -315,11 +306,20 @@ epsm_status epsm_search_batch(const epsm_batch *batch, void *stream) {
     return fail(EPSM_EUNSUPPORTED, "batched search not built yet");
 }
 
+epsm_status epsm_set_tile_config(uint32_t waves, uint32_t pieces) {
+    g_last_error.clear();
+    TileConfig c{(int)waves, (int)pieces};
+    if (!tile_config_supported(c)) return fail(EPSM_EUNSUPPORTED, "tile configuration not built");
+    g_tile = c;
+    return EPSM_OK;
+}
+
 epsm_status epsm_reserve(void *stream, uint64_t max_n, uint64_t max_units) {
     g_last_error.clear();
     const uint64_t tiles = max_n / (uint64_t)g_tile.bytes() + 2 + max_units;
     uint8_t *ws = nullptr;
-    return workspace_for((hipStream_t)stream, 256 + tiles * sizeof(uint64_t), &ws);
+    return workspace_for((hipStream_t)stream, kCountBins * sizeof(uint64_t) + tiles * sizeof(uint64_t),
+                         &ws);
 }
 
 void epsm_release(void) {

@@ -19,6 +19,9 @@ constexpr uint64_t kValueMask = (1ull << 62) - 1;
 // cycles plus a memory round trip: several seconds in total).  Every wait is
 // expected to end long before; the bound only guarantees the kernel drains.
 constexpr uint32_t kSpinLimit = 1u << 22;
+// Count-only searches add per-tile counts into this many words (spreading
+// the device-scope atomics over many addresses) and then sum them.
+constexpr int kCountBins = 256;
 
 // Fingerprint hash of an aligned 8-byte text block (lo = bytes 0..3, hi =
 // bytes 4..7, little endian), reduced to `bits` bits.  A two-multiply
@@ -55,7 +58,7 @@ struct ScanArgs {
     uint64_t cap;
     uint64_t *n_hits;        // full count (device)
     uint64_t *status;        // [num_tiles] look-back words, zeroed before launch
-    uint32_t *ticket;        // tile counter, zeroed before launch
+    uint64_t *bins;          // [kCountBins] count-only partial sums, zeroed before launch
     uint32_t *fault;         // set to 1 if a bounded wait gave up (never expected)
     uint32_t num_tiles;
     uint32_t write;          // 0: count only
@@ -72,6 +75,7 @@ struct TileConfig {
 // Launchers (epsm_kernels.hip).  Return hipSuccess or the launch error.
 hipError_t launch_zero_u64(uint64_t *p, uint64_t count, hipStream_t s);
 hipError_t launch_set_u64(uint64_t *p, uint64_t value, hipStream_t s);
+hipError_t launch_sum_bins(const uint64_t *bins, uint64_t *out, hipStream_t s);
 hipError_t launch_scan(const ScanArgs &a, TileConfig cfg, int grid, hipStream_t s);
 int scan_blocks_per_cu(TileConfig cfg, const DevPlan &p);
 bool tile_config_supported(TileConfig cfg);

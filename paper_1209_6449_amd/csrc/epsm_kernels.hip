@@ -2,13 +2,15 @@
 //
 // Layout.  A search runs over "base coordinates": base is the text start
 // rounded down to 16 bytes and a text position s is base coordinate s+delta.
-// A tile is WAVES*PIECES KiB of base coordinates; wave w of a workgroup owns
-// the contiguous PIECES KiB at w*PIECES KiB inside the tile, and in piece u
-// lane L owns the 16 start positions [u*1024 + 16L, +16).  Each lane loads
-// its 16 bytes plus the following 16 (32 for long patterns) with dwordx4
-// buffer loads; the buffer descriptor's record count clamps reads at the
-// 16-byte-rounded text end, so the (m-1)-byte halo past a tile (Section 3.3's
-// reason for wsblend) is just the next bytes of the same coalesced stream.
+// A tile is WAVES * PIECES KiB of base coordinates; wave w of a workgroup
+// owns the contiguous PIECES KiB at w*PIECES KiB inside the tile and walks
+// it in chunks of U pieces, loading chunk c+1 while it computes chunk c.  In
+// piece i lane L owns the 16 start positions [i*1024 + 16L, +16).  Each lane
+// loads its 16 bytes plus the following 16 (32 for long patterns) with
+// dwordx4 buffer loads; the buffer descriptor's record count clamps reads at
+// the 16-byte-rounded text end, so the (m-1)-byte halo past a piece (Section
+// 3.3's reason for wsblend) is just the next bytes of the same coalesced
+// stream.
 //
 // Filter.  Direct variant (m < 16, the job of EPSMa/EPSMb in Sections
 // 3.2-3.3): for each of the lane's 16 starts, the 4-byte window at that start
@@ -22,11 +24,15 @@
 // 0..7 and m >= 15 every occurrence is hit by exactly one (block, offset)
 // pair.  Candidates are then verified against the whole pattern.
 //
-// Output.  Each lane keeps a 16-bit hit mask per piece.  Tiles are taken in
-// ticket order from a counter by persistent workgroups; the tile's count is
-// published and a single-pass decoupled look-back over the predecessors'
-// status words gives its exclusive prefix, so positions are written in
-// ascending order in one pass over the text.
+// Output.  Each lane parks a 16-bit hit mask per piece in LDS.  Workgroup b
+// owns tile b; it publishes the tile's count and a single-pass decoupled
+// look-back over the predecessors' status words gives its exclusive prefix,
+// so positions are written in ascending order in one pass over the text.
+// Two measured constraints shape this: no tile counter is used (a
+// device-scope atomic on one address serialises the workgroups, one every
+// ~12 ns), and tiles are large (the inclusive-prefix frontier advances by
+// one 64-entry look-back window per memory round trip, so it moves
+// 64 * tile bytes per ~1 us).  Count-only searches skip the look-back.
 #include "epsm_internal.h"
 
 namespace epsm {
@@ -57,13 +63,15 @@ __device__ __forceinline__ bool wave_any(bool c) { return ballot(c) != 0; }
 
 // Narrow a wave mask of candidates at lane byte k with pattern words
 // j0..nw-1 (each compare is one v_cmp whose result is the wave mask itself).
-// Stops as soon as no lane of the wave has a candidate left.
-template <int NWMAX, int N>
+// Stops as soon as no lane of the wave has a candidate left.  nw is the
+// template constant NW, or the plan's runtime value when NW == 0.
+template <int NWMAX, int NW, int N>
 __device__ __forceinline__ uint64_t verify_words(const uint32_t (&w)[N], int k, uint64_t b, int j0,
                                                  const DevPlan &p) {
 #pragma unroll
     for (int j = 0; j < NWMAX; ++j) {
-        if (j >= j0 && j < (int)p.nw && b != 0)
+        const bool in_range = NW > 0 ? (j < NW) : (j < (int)p.nw);
+        if (j >= j0 && in_range && b != 0)
             b &= ballot((window(w, k + 4 * j) & p.pmask[j]) == p.pw[j]);
     }
     return b;
@@ -79,7 +87,7 @@ __device__ __forceinline__ uint32_t lanes_from_masks(const uint64_t (&b)[16]) {
 }
 
 // Direct variant: 16-bit hit mask of one lane piece (positions 0..15).
-template <int NL, int PK>
+template <int NL, int PK, int NW>
 __device__ __forceinline__ uint32_t direct_mask(const uint32_t (&w)[NL * 4 + 1], const DevPlan &p) {
     constexpr int NWMAX = 4 * NL - 4;
     uint64_t b[16];
@@ -101,7 +109,7 @@ __device__ __forceinline__ uint32_t direct_mask(const uint32_t (&w)[NL * 4 + 1],
             c = window(w, k) == p.pw[0];
         }
         uint64_t bk = ballot(c);
-        if constexpr (PK >= 4) bk = verify_words<NWMAX>(w, k, bk, 1, p);
+        if constexpr (PK >= 4) bk = verify_words<NWMAX, NW>(w, k, bk, 1, p);
         b[k] = bk;
         any |= bk;
     }
@@ -131,7 +139,7 @@ __device__ __forceinline__ uint32_t fingerprint_mask(const uint32_t (&w)[NL * 4 
 #pragma unroll
     for (int k = 0; k < 16; ++k) {
         uint64_t bk = ballot((cm >> k) & 1u);
-        if (bk) bk = verify_words<NWMAX>(w, k, bk, 0, p);
+        if (bk) bk = verify_words<NWMAX, 0>(w, k, bk, 0, p);
         b[k] = bk;
         any |= bk;
     }
@@ -199,7 +207,8 @@ __device__ __forceinline__ uint64_t status_load(uint64_t *p) {
 // walks back over predecessors 64 at a time until an inclusive prefix is
 // found, publishes the tile's inclusive prefix, returns the exclusive one.
 // Every wait ends: a tile's aggregate is published before its own look-back,
-// and tiles are ticketed in order, so all predecessors are running or done.
+// and a tile only waits on lower-indexed workgroups, which in-order dispatch
+// has already started.  The poll bound only guarantees termination.
 __device__ uint64_t look_back(uint64_t *status, uint32_t tile, uint64_t cnt, int lane,
                               uint32_t *fault) {
     if (tile == 0) {
@@ -236,104 +245,159 @@ __device__ uint64_t look_back(uint64_t *status, uint32_t tile, uint64_t cnt, int
     return excl;
 }
 
-template <int WAVES, int U, int NL, int VAR, int PK>
+template <int U, int NL>
+__device__ __forceinline__ void load_chunk(uint32_t (&w)[U][NL * 4 + 1], __amdgpu_buffer_rsrc_t r,
+                                           uint32_t off) {
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+#pragma unroll
+        for (int l = 0; l < NL; ++l) {
+            const u32x4 v = load16(r, off + u * kWavePiece + l * kPiece);
+            w[u][4 * l + 0] = v.x;
+            w[u][4 * l + 1] = v.y;
+            w[u][4 * l + 2] = v.z;
+            w[u][4 * l + 3] = v.w;
+        }
+        w[u][NL * 4] = 0;
+    }
+}
+
+// Hit masks of the U pieces of one chunk, parked in LDS (two 16-bit masks per
+// word); returns the lane's hit count.
+template <int U, int NL, int VAR, int PK, int NW, int PAIRS, int THREADS>
+__device__ __forceinline__ uint32_t process_chunk(const uint32_t (&w)[U][NL * 4 + 1], int c,
+                                                  const ScanArgs &a, const uint16_t *tab,
+                                                  uint64_t lane_start, bool edge, bool tail,
+                                                  uint32_t (*s_mask)[THREADS], int tid) {
+    uint32_t cnt = 0, lo = 0;
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        uint32_t mk;
+        if constexpr (VAR == 1) mk = direct_mask<NL, PK, NW>(w[u], a.plan);
+        else mk = fingerprint_mask<NL>(w[u], a.plan, tab);
+        const int piece = c * U + u;
+        const uint64_t s0 = lane_start + (uint64_t)piece * kWavePiece;
+        // only the first tile holds starts below delta and only the last
+        // one holds starts past `last`
+        if (edge) mk &= valid_mask(s0, a.delta, a.last);
+        if (tail && wave_any(mk != 0))
+            mk = tail_check(mk, s0, a.base, a.plan.pattern, a.plan.m, 4u * a.plan.nw);
+        cnt += __popc(mk);
+        if (u & 1) s_mask[piece >> 1][tid] = lo | (mk << 16);
+        else lo = mk;
+    }
+    return cnt;
+}
+
+template <int WAVES, int U, int C, int NL, int VAR, int PK, int NW>
 __global__ __launch_bounds__(WAVES * kWave) void scan_kernel(ScanArgs a) {
+    constexpr int kThreads = WAVES * kWave;
+    constexpr int kPieces = U * C;  // pieces per wave per tile
+    constexpr uint32_t kWaveSpan = kPieces * kWavePiece;
+    constexpr uint32_t kTile = WAVES * kWaveSpan;
+    static_assert(U % 2 == 0 && C % 2 == 0, "masks are packed in pairs; chunks ping-pong");
     extern __shared__ __attribute__((aligned(16))) uint16_t s_table[];
-    __shared__ uint32_t s_tile;
+    __shared__ uint32_t s_mask[kPieces / 2][kThreads];
     __shared__ uint32_t s_wcnt[WAVES];
     __shared__ uint64_t s_excl;
-    constexpr uint32_t kTile = WAVES * U * kWavePiece;
     const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
 
     if constexpr (VAR == 2) {
-        const uint32_t words = (1u << a.plan.hash_bits) / 8;  // 16-byte rows of the table
+        const uint32_t rows = (1u << a.plan.hash_bits) / 8;  // 16-byte rows of the table
         const u32x4 *src = reinterpret_cast<const u32x4 *>(a.plan.table);
         u32x4 *dst = reinterpret_cast<u32x4 *>(s_table);
-        for (uint32_t i = tid; i < words; i += WAVES * kWave) dst[i] = src[i];
-    }
-
-    for (;;) {
-        if (tid == 0) s_tile = atomicAdd(a.ticket, 1u);
-        __syncthreads();
-        const uint32_t tile = s_tile;
-        if (tile >= a.num_tiles) break;
-
-        const uint64_t tile_start = (uint64_t)tile * kTile;
-        const uint64_t avail = a.load_end - tile_start;
-        const uint32_t nrec = avail > 0xFFFFFFF0ull ? 0xFFFFFFF0u : (uint32_t)avail;
-        const __amdgpu_buffer_rsrc_t rsrc = make_rsrc(a.base + tile_start, nrec);
-        const uint32_t lane_off = (uint32_t)wave * U * kWavePiece + (uint32_t)lane * kPiece;
-
-        uint32_t w[U][NL * 4 + 1];
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-#pragma unroll
-            for (int l = 0; l < NL; ++l) {
-                const u32x4 v = load16(rsrc, lane_off + u * kWavePiece + l * kPiece);
-                w[u][4 * l + 0] = v.x;
-                w[u][4 * l + 1] = v.y;
-                w[u][4 * l + 2] = v.z;
-                w[u][4 * l + 3] = v.w;
-            }
-            w[u][NL * 4] = 0;
-        }
-
-        uint32_t lm[U];
-        uint32_t cnt = 0;
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            uint32_t mk;
-            if constexpr (VAR == 1) mk = direct_mask<NL, PK>(w[u], a.plan);
-            else mk = fingerprint_mask<NL>(w[u], a.plan, s_table);
-            const uint64_t s0 = tile_start + lane_off + u * kWavePiece;
-            // only the first tile holds starts below delta and only the last
-            // one starts past `last`
-            if (tile == 0 || tile == a.num_tiles - 1) mk &= valid_mask(s0, a.delta, a.last);
-            if (a.plan.m > 4u * a.plan.nw && wave_any(mk != 0)) mk = tail_check(mk, s0, a.base, a.plan.pattern, a.plan.m, 4u * a.plan.nw);
-            lm[u] = mk;
-            cnt += __popc(mk);
-        }
-
-        const uint32_t wtot = wave_sum32(cnt);
-        if (lane == 0) s_wcnt[wave] = wtot;
-        __syncthreads();
-        if (wave == 0) {
-            uint64_t tile_cnt = 0;
-#pragma unroll
-            for (int i = 0; i < WAVES; ++i) tile_cnt += s_wcnt[i];
-            const uint64_t excl = look_back(a.status, tile, tile_cnt, lane, a.fault);
-            if (lane == 0) {
-                s_excl = excl;
-                if (tile == a.num_tiles - 1) *a.n_hits = excl + tile_cnt;
-            }
-        }
-        __syncthreads();
-
-        if (a.write) {
-            uint64_t obase = s_excl;
-            for (int i = 0; i < wave; ++i) obase += s_wcnt[i];
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const uint32_t c = __popc(lm[u]);
-                if (wave_any(c != 0)) {
-                    const uint32_t incl = wave_incl_scan32(c, lane);
-                    const uint32_t tot = __shfl(incl, kWave - 1, kWave);
-                    uint64_t idx = obase + (incl - c);
-                    const int64_t pos0 =
-                        (int64_t)(tile_start + lane_off + u * kWavePiece) - (int64_t)a.delta;
-                    uint32_t bits = lm[u];
-                    while (bits) {
-                        const uint32_t k = __builtin_ctz(bits);
-                        bits &= bits - 1;
-                        if (idx < a.cap) a.out[idx] = pos0 + k;
-                        ++idx;
-                    }
-                    obase += tot;
-                }
-            }
-        }
+        for (uint32_t i = tid; i < rows; i += kThreads) dst[i] = src[i];
         __syncthreads();
     }
+
+    // Workgroup index = tile index (no counter: see the header comment).
+    const uint32_t tile = blockIdx.x;
+    const uint64_t tile_start = (uint64_t)tile * kTile;
+    const uint64_t avail = a.load_end - tile_start;
+    const uint32_t nrec = avail > 0xFFFFFFF0ull ? 0xFFFFFFF0u : (uint32_t)avail;
+    const __amdgpu_buffer_rsrc_t rsrc = make_rsrc(a.base + tile_start, nrec);
+    const uint32_t lane_off = (uint32_t)wave * kWaveSpan + (uint32_t)lane * kPiece;
+    const uint64_t lane_start = tile_start + lane_off;
+    const bool edge = tile == 0 || tile == a.num_tiles - 1;
+    const bool tail = a.plan.m > 4u * a.plan.nw;
+
+    uint32_t wa[U][NL * 4 + 1], wb[U][NL * 4 + 1];
+    uint32_t cnt = 0;
+    load_chunk<U, NL>(wa, rsrc, lane_off);
+#pragma unroll 1
+    for (int c = 0; c < C; c += 2) {
+        load_chunk<U, NL>(wb, rsrc, lane_off + (uint32_t)(c + 1) * U * kWavePiece);
+        cnt += process_chunk<U, NL, VAR, PK, NW, kPieces / 2, kThreads>(
+            wa, c, a, s_table, lane_start, edge, tail, s_mask, tid);
+        if (c + 2 < C) load_chunk<U, NL>(wa, rsrc, lane_off + (uint32_t)(c + 2) * U * kWavePiece);
+        cnt += process_chunk<U, NL, VAR, PK, NW, kPieces / 2, kThreads>(
+            wb, c + 1, a, s_table, lane_start, edge, tail, s_mask, tid);
+    }
+
+    const uint32_t wtot = wave_sum32(cnt);
+    if (lane == 0) s_wcnt[wave] = wtot;
+    __syncthreads();
+    uint64_t tile_cnt = 0;
+#pragma unroll
+    for (int i = 0; i < WAVES; ++i) tile_cnt += s_wcnt[i];
+
+    if (!a.write) {
+        // count only: no ordering needed; spread the adds over kCountBins words
+        if (tid == 0 && tile_cnt)
+            atomicAdd((unsigned long long *)&a.bins[tile & (kCountBins - 1)],
+                      (unsigned long long)tile_cnt);
+        return;
+    }
+    if (wave == 0) {
+        const uint64_t excl = look_back(a.status, tile, tile_cnt, lane, a.fault);
+        if (lane == 0) {
+            s_excl = excl;
+            if (tile == a.num_tiles - 1) *a.n_hits = excl + tile_cnt;
+        }
+    }
+    __syncthreads();
+
+    uint64_t obase = s_excl;
+    for (int i = 0; i < wave; ++i) obase += s_wcnt[i];
+    if (wtot == 0) return;
+#pragma unroll 2
+    for (int piece = 0; piece < kPieces; ++piece) {
+        const uint32_t mk = (s_mask[piece >> 1][tid] >> ((piece & 1) * 16)) & 0xFFFFu;
+        const uint32_t c = __popc(mk);
+        if (wave_any(c != 0)) {
+            const uint32_t incl = wave_incl_scan32(c, lane);
+            const uint32_t tot = __shfl(incl, kWave - 1, kWave);
+            uint64_t idx = obase + (incl - c);
+            const int64_t pos0 = (int64_t)(lane_start + (uint64_t)piece * kWavePiece) - (int64_t)a.delta;
+            uint32_t bits = mk;
+            while (bits) {
+                const uint32_t k = __builtin_ctz(bits);
+                bits &= bits - 1;
+                if (idx < a.cap) a.out[idx] = pos0 + k;
+                ++idx;
+            }
+            obase += tot;
+        }
+    }
+}
+
+// Sum of the count bins into *out (one workgroup of kCountBins threads).
+__global__ __launch_bounds__(kCountBins) void sum_bins_kernel(const uint64_t *bins, uint64_t *out) {
+    __shared__ uint64_t s_part[kCountBins / kWave];
+    const int tid = threadIdx.x;
+    const uint64_t v = wave_sum64(bins[tid]);
+    if ((tid & (kWave - 1)) == 0) s_part[tid / kWave] = v;
+    __syncthreads();
+    if (tid == 0) {
+        uint64_t total = 0;
+        for (int i = 0; i < kCountBins / kWave; ++i) total += s_part[i];
+        *out = total;
+    }
+}
+
+hipError_t launch_sum_bins(const uint64_t *bins, uint64_t *out, hipStream_t s) {
+    hipLaunchKernelGGL(sum_bins_kernel, dim3(1), dim3(kCountBins), 0, s, bins, out);
+    return hipGetLastError();
 }
 
 __global__ void zero_u64_kernel(uint64_t *p, uint64_t count) {
@@ -360,23 +424,33 @@ hipError_t launch_set_u64(uint64_t *p, uint64_t value, hipStream_t s) {
 
 typedef void (*ScanFn)(ScanArgs);
 
-template <int WAVES, int U>
+// Direct variant with m <= 16 uses chunks of 4 pieces (two dwordx4 loads per
+// piece); the 3-load variants (fingerprint, direct with m > 16) use chunks of
+// 2 pieces to stay within the register budget.
+template <int WAVES, int PIECES>
 static ScanFn pick(const DevPlan &p) {
-    if (p.variant == 2) return scan_kernel<WAVES, U, 3, 2, 4>;
-    if (p.nl == 3) return scan_kernel<WAVES, U, 3, 1, 4>;
+    if (p.variant == 2) return scan_kernel<WAVES, 2, PIECES / 2, 3, 2, 4, 0>;
+    if (p.nl == 3) return scan_kernel<WAVES, 2, PIECES / 2, 3, 1, 4, 0>;
     switch (p.pk) {
-        case 1: return scan_kernel<WAVES, U, 2, 1, 1>;
-        case 2: return scan_kernel<WAVES, U, 2, 1, 2>;
-        case 3: return scan_kernel<WAVES, U, 2, 1, 3>;
-        default: return scan_kernel<WAVES, U, 2, 1, 4>;
+        case 1: return scan_kernel<WAVES, 4, PIECES / 4, 2, 1, 1, 1>;
+        case 2: return scan_kernel<WAVES, 4, PIECES / 4, 2, 1, 2, 1>;
+        case 3: return scan_kernel<WAVES, 4, PIECES / 4, 2, 1, 3, 1>;
+        default: break;
+    }
+    switch (p.nw) {
+        case 1: return scan_kernel<WAVES, 4, PIECES / 4, 2, 1, 4, 1>;
+        case 2: return scan_kernel<WAVES, 4, PIECES / 4, 2, 1, 4, 2>;
+        case 3: return scan_kernel<WAVES, 4, PIECES / 4, 2, 1, 4, 3>;
+        default: return scan_kernel<WAVES, 4, PIECES / 4, 2, 1, 4, 4>;
     }
 }
 
 static ScanFn pick_fn(TileConfig cfg, const DevPlan &p) {
-    if (cfg.waves == 4 && cfg.pieces == 4) return pick<4, 4>(p);
-    if (cfg.waves == 4 && cfg.pieces == 2) return pick<4, 2>(p);
-    if (cfg.waves == 4 && cfg.pieces == 1) return pick<4, 1>(p);
-    if (cfg.waves == 8 && cfg.pieces == 2) return pick<8, 2>(p);
+    if (cfg.waves == 8 && cfg.pieces == 16) return pick<8, 16>(p);
+    if (cfg.waves == 8 && cfg.pieces == 8) return pick<8, 8>(p);
+    if (cfg.waves == 4 && cfg.pieces == 16) return pick<4, 16>(p);
+    if (cfg.waves == 16 && cfg.pieces == 8) return pick<16, 8>(p);
+    if (cfg.waves == 16 && cfg.pieces == 16) return pick<16, 16>(p);
     return nullptr;
 }
 

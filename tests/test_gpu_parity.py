@@ -12,7 +12,7 @@ import workloads as W
 
 pytestmark = pytest.mark.gpu
 
-TILE = 16 * 1024  # default workgroup tile (4 waves x 4 KiB)
+TILE = 128 * 1024  # default workgroup tile (8 waves x 16 KiB)
 
 
 @pytest.fixture(scope="module")
