@@ -49,7 +49,7 @@ constexpr uint32_t kDefaultHashBits = 11;  // k = 11 in Section 3.4
 // Default tile: 8 waves x 16 KiB per wave = 128 KiB per workgroup tile.
 TileConfig g_tile = {8, 16};
 
-// ---- workspace: look-back status words, one buffer per stream ----
+// ---- workspace: count bins and look-back status words, one buffer per stream ----
 struct Workspace {
     uint8_t *ptr = nullptr;
     size_t bytes = 0;

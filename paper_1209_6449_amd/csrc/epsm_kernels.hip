@@ -28,11 +28,14 @@
 // owns tile b; it publishes the tile's count and a single-pass decoupled
 // look-back over the predecessors' status words gives its exclusive prefix,
 // so positions are written in ascending order in one pass over the text.
-// Two measured constraints shape this: no tile counter is used (a
-// device-scope atomic on one address serialises the workgroups, one every
-// ~12 ns), and tiles are large (the inclusive-prefix frontier advances by
-// one 64-entry look-back window per memory round trip, so it moves
-// 64 * tile bytes per ~1 us).  Count-only searches skip the look-back.
+// Measured constraints shape the schedule: a device-scope atomic on one
+// address serialises its callers (one every ~12 ns), so no tile counter is
+// used; the inclusive-prefix frontier advances by one 64-entry look-back
+// window per memory round trip, so tiles are large (64 * 128 KiB per ~1 us);
+// and a persistent workgroup that walks several consecutive tiles delays the
+// counts of its later tiles behind the writes of its earlier ones, which
+// serialises the chain, so workgroups are not persistent.  Count-only
+// searches skip the look-back.
 #include "epsm_internal.h"
 
 namespace epsm {
@@ -245,6 +248,26 @@ __device__ uint64_t look_back(uint64_t *status, uint32_t tile, uint64_t cnt, int
     return excl;
 }
 
+// Positions staged per wave before they are written out (wave-relative
+// offsets; one piece adds at most 1024).
+constexpr uint32_t kStage = 1024;
+
+// Write stage[0..fill) as positions wave_pos0 + stage[j] to out[obase + j]
+// (entries at or past cap are dropped).  Lanes write consecutive entries.
+__device__ __forceinline__ void flush_stage(const uint32_t *stage, uint32_t fill, int64_t *out,
+                                            uint64_t cap, uint64_t obase, int64_t wave_pos0,
+                                            int lane) {
+    // the stage was filled by other lanes of this wave: order the LDS accesses
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    for (uint32_t j = lane; j < fill; j += kWave) {
+        const uint64_t idx = obase + j;
+        if (idx < cap) out[idx] = wave_pos0 + stage[j];
+    }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
 template <int U, int NL>
 __device__ __forceinline__ void load_chunk(uint32_t (&w)[U][NL * 4 + 1], __amdgpu_buffer_rsrc_t r,
                                            uint32_t off) {
@@ -289,8 +312,51 @@ __device__ __forceinline__ uint32_t process_chunk(const uint32_t (&w)[U][NL * 4 
     return cnt;
 }
 
+// Write phase of one tile, run by each wave on its own span: expand the
+// parked masks into wave-relative offsets staged in LDS (ascending), and
+// flush the stage with consecutive lanes writing consecutive int64 entries.
+template <int PIECES, int THREADS>
+__device__ __forceinline__ void write_tile(const uint32_t (*s_mask)[THREADS], uint32_t *stage,
+                                           const ScanArgs &a, uint64_t obase, int64_t wave_pos0,
+                                           int tid, int lane) {
+    uint32_t fill = 0;
+#pragma unroll 1
+    for (int piece = 0; piece < PIECES; ++piece) {
+        const uint32_t mk = (s_mask[piece >> 1][tid] >> ((piece & 1) * 16)) & 0xFFFFu;
+        const uint32_t c = __popc(mk);
+        if (!wave_any(c != 0)) continue;
+        const uint32_t incl = wave_incl_scan32(c, lane);
+        const uint32_t tot = __shfl(incl, kWave - 1, kWave);
+        if (fill + tot > kStage) {
+            flush_stage(stage, fill, a.out, a.cap, obase, wave_pos0, lane);
+            obase += fill;
+            fill = 0;
+        }
+        uint32_t at = fill + incl - c;
+        const uint32_t rel0 = (uint32_t)piece * kWavePiece + (uint32_t)lane * kPiece;
+        uint32_t bits = mk;
+        while (bits) {
+            const uint32_t k = __builtin_ctz(bits);
+            bits &= bits - 1;
+            stage[at++] = rel0 + k;
+        }
+        fill += tot;
+    }
+    if (fill) flush_stage(stage, fill, a.out, a.cap, obase, wave_pos0, lane);
+}
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t tile_rsrc(const ScanArgs &a, uint64_t tile_start) {
+    const uint64_t avail = a.load_end - tile_start;
+    const uint32_t nrec = avail > 0xFFFFFFF0ull ? 0xFFFFFFF0u : (uint32_t)avail;
+    return make_rsrc(a.base + tile_start, nrec);
+}
+
+// One workgroup per tile (workgroup index = tile index, no counter).  Every
+// tile publishes its count as soon as it is computed, independently of the
+// other tiles' look-back and write phases; a look-back only waits on lower
+// workgroup indices, which in-order dispatch has already started.
 template <int WAVES, int U, int C, int NL, int VAR, int PK, int NW>
-__global__ __launch_bounds__(WAVES * kWave) void scan_kernel(ScanArgs a) {
+__global__ __launch_bounds__(WAVES * kWave, 4) void scan_kernel(ScanArgs a) {
     constexpr int kThreads = WAVES * kWave;
     constexpr int kPieces = U * C;  // pieces per wave per tile
     constexpr uint32_t kWaveSpan = kPieces * kWavePiece;
@@ -298,10 +364,21 @@ __global__ __launch_bounds__(WAVES * kWave) void scan_kernel(ScanArgs a) {
     static_assert(U % 2 == 0 && C % 2 == 0, "masks are packed in pairs; chunks ping-pong");
     extern __shared__ __attribute__((aligned(16))) uint16_t s_table[];
     __shared__ uint32_t s_mask[kPieces / 2][kThreads];
+    __shared__ uint32_t s_stage[WAVES][kStage];
     __shared__ uint32_t s_wcnt[WAVES];
     __shared__ uint64_t s_excl;
     const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
 
+    const uint32_t tile = blockIdx.x;
+    const uint64_t tile_start = (uint64_t)tile * kTile;
+    const __amdgpu_buffer_rsrc_t rsrc = tile_rsrc(a, tile_start);
+    const uint32_t lane_off = (uint32_t)wave * kWaveSpan + (uint32_t)lane * kPiece;
+    const uint64_t lane_start = tile_start + lane_off;
+    const bool edge = tile == 0 || tile == a.num_tiles - 1;
+    const bool tail = a.plan.m > 4u * a.plan.nw;
+
+    uint32_t wa[U][NL * 4 + 1], wb[U][NL * 4 + 1];
+    load_chunk<U, NL>(wa, rsrc, lane_off);
     if constexpr (VAR == 2) {
         const uint32_t rows = (1u << a.plan.hash_bits) / 8;  // 16-byte rows of the table
         const u32x4 *src = reinterpret_cast<const u32x4 *>(a.plan.table);
@@ -310,20 +387,7 @@ __global__ __launch_bounds__(WAVES * kWave) void scan_kernel(ScanArgs a) {
         __syncthreads();
     }
 
-    // Workgroup index = tile index (no counter: see the header comment).
-    const uint32_t tile = blockIdx.x;
-    const uint64_t tile_start = (uint64_t)tile * kTile;
-    const uint64_t avail = a.load_end - tile_start;
-    const uint32_t nrec = avail > 0xFFFFFFF0ull ? 0xFFFFFFF0u : (uint32_t)avail;
-    const __amdgpu_buffer_rsrc_t rsrc = make_rsrc(a.base + tile_start, nrec);
-    const uint32_t lane_off = (uint32_t)wave * kWaveSpan + (uint32_t)lane * kPiece;
-    const uint64_t lane_start = tile_start + lane_off;
-    const bool edge = tile == 0 || tile == a.num_tiles - 1;
-    const bool tail = a.plan.m > 4u * a.plan.nw;
-
-    uint32_t wa[U][NL * 4 + 1], wb[U][NL * 4 + 1];
     uint32_t cnt = 0;
-    load_chunk<U, NL>(wa, rsrc, lane_off);
 #pragma unroll 1
     for (int c = 0; c < C; c += 2) {
         load_chunk<U, NL>(wb, rsrc, lane_off + (uint32_t)(c + 1) * U * kWavePiece);
@@ -333,7 +397,6 @@ __global__ __launch_bounds__(WAVES * kWave) void scan_kernel(ScanArgs a) {
         cnt += process_chunk<U, NL, VAR, PK, NW, kPieces / 2, kThreads>(
             wb, c + 1, a, s_table, lane_start, edge, tail, s_mask, tid);
     }
-
     const uint32_t wtot = wave_sum32(cnt);
     if (lane == 0) s_wcnt[wave] = wtot;
     __syncthreads();
@@ -356,29 +419,11 @@ __global__ __launch_bounds__(WAVES * kWave) void scan_kernel(ScanArgs a) {
         }
     }
     __syncthreads();
-
+    if (wtot == 0) return;
     uint64_t obase = s_excl;
     for (int i = 0; i < wave; ++i) obase += s_wcnt[i];
-    if (wtot == 0) return;
-#pragma unroll 2
-    for (int piece = 0; piece < kPieces; ++piece) {
-        const uint32_t mk = (s_mask[piece >> 1][tid] >> ((piece & 1) * 16)) & 0xFFFFu;
-        const uint32_t c = __popc(mk);
-        if (wave_any(c != 0)) {
-            const uint32_t incl = wave_incl_scan32(c, lane);
-            const uint32_t tot = __shfl(incl, kWave - 1, kWave);
-            uint64_t idx = obase + (incl - c);
-            const int64_t pos0 = (int64_t)(lane_start + (uint64_t)piece * kWavePiece) - (int64_t)a.delta;
-            uint32_t bits = mk;
-            while (bits) {
-                const uint32_t k = __builtin_ctz(bits);
-                bits &= bits - 1;
-                if (idx < a.cap) a.out[idx] = pos0 + k;
-                ++idx;
-            }
-            obase += tot;
-        }
-    }
+    const int64_t wave_pos0 = (int64_t)(tile_start + (uint64_t)wave * kWaveSpan) - (int64_t)a.delta;
+    write_tile<kPieces, kThreads>(s_mask, s_stage[wave], a, obase, wave_pos0, tid, lane);
 }
 
 // Sum of the count bins into *out (one workgroup of kCountBins threads).
@@ -424,24 +469,23 @@ hipError_t launch_set_u64(uint64_t *p, uint64_t value, hipStream_t s) {
 
 typedef void (*ScanFn)(ScanArgs);
 
-// Direct variant with m <= 16 uses chunks of 4 pieces (two dwordx4 loads per
-// piece); the 3-load variants (fingerprint, direct with m > 16) use chunks of
-// 2 pieces to stay within the register budget.
+// Chunks of 2 pieces (two or three dwordx4 loads per piece and lane, two
+// chunks in flight) keep the kernels within about 100 VGPRs.
 template <int WAVES, int PIECES>
 static ScanFn pick(const DevPlan &p) {
     if (p.variant == 2) return scan_kernel<WAVES, 2, PIECES / 2, 3, 2, 4, 0>;
     if (p.nl == 3) return scan_kernel<WAVES, 2, PIECES / 2, 3, 1, 4, 0>;
     switch (p.pk) {
-        case 1: return scan_kernel<WAVES, 4, PIECES / 4, 2, 1, 1, 1>;
-        case 2: return scan_kernel<WAVES, 4, PIECES / 4, 2, 1, 2, 1>;
-        case 3: return scan_kernel<WAVES, 4, PIECES / 4, 2, 1, 3, 1>;
+        case 1: return scan_kernel<WAVES, 2, PIECES / 2, 2, 1, 1, 1>;
+        case 2: return scan_kernel<WAVES, 2, PIECES / 2, 2, 1, 2, 1>;
+        case 3: return scan_kernel<WAVES, 2, PIECES / 2, 2, 1, 3, 1>;
         default: break;
     }
     switch (p.nw) {
-        case 1: return scan_kernel<WAVES, 4, PIECES / 4, 2, 1, 4, 1>;
-        case 2: return scan_kernel<WAVES, 4, PIECES / 4, 2, 1, 4, 2>;
-        case 3: return scan_kernel<WAVES, 4, PIECES / 4, 2, 1, 4, 3>;
-        default: return scan_kernel<WAVES, 4, PIECES / 4, 2, 1, 4, 4>;
+        case 1: return scan_kernel<WAVES, 2, PIECES / 2, 2, 1, 4, 1>;
+        case 2: return scan_kernel<WAVES, 2, PIECES / 2, 2, 1, 4, 2>;
+        case 3: return scan_kernel<WAVES, 2, PIECES / 2, 2, 1, 4, 3>;
+        default: return scan_kernel<WAVES, 2, PIECES / 2, 2, 1, 4, 4>;
     }
 }
 
