@@ -30,8 +30,8 @@
 // so positions are written in ascending order in one pass over the text.
 // Measured constraints shape the schedule: a device-scope atomic on one
 // address serialises its callers (one every ~12 ns), so no tile counter is
-// used; the inclusive-prefix frontier advances by one 64-entry look-back
-// window per memory round trip, so tiles are large (64 * 128 KiB per ~1 us);
+// used; the inclusive-prefix frontier advances by one look-back window per
+// memory round trip, so tiles are large (64 * 128 KiB per round trip);
 // and a persistent workgroup that walks several consecutive tiles delays the
 // counts of its later tiles behind the writes of its earlier ones, which
 // serialises the chain, so workgroups are not persistent.  Count-only
@@ -90,6 +90,11 @@ __device__ __forceinline__ uint32_t lanes_from_masks(const uint64_t (&b)[16]) {
 }
 
 // Direct variant: 16-bit hit mask of one lane piece (positions 0..15).
+// All 16 prefix compares come first and their wave masks are OR-ed once;
+// only a wave with some candidate narrows them with the remaining pattern
+// words and transposes them into per-lane masks.  Keeping the common path
+// free of per-position branches matters: the scalar unit issues one
+// instruction per SIMD every four cycles and was the bottleneck.
 template <int NL, int PK, int NW>
 __device__ __forceinline__ uint32_t direct_mask(const uint32_t (&w)[NL * 4 + 1], const DevPlan &p) {
     constexpr int NWMAX = 4 * NL - 4;
@@ -111,12 +116,20 @@ __device__ __forceinline__ uint32_t direct_mask(const uint32_t (&w)[NL * 4 + 1],
         } else {
             c = window(w, k) == p.pw[0];
         }
-        uint64_t bk = ballot(c);
-        if constexpr (PK >= 4) bk = verify_words<NWMAX, NW>(w, k, bk, 1, p);
-        b[k] = bk;
-        any |= bk;
+        b[k] = ballot(c);
+        any |= b[k];
     }
-    return any ? lanes_from_masks(b) : 0u;
+    if (any == 0) return 0u;
+    if constexpr (PK >= 4 && (NW == 0 || NW > 1)) {
+        any = 0;
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+            if (b[k]) b[k] = verify_words<NWMAX, NW>(w, k, b[k], 1, p);
+            any |= b[k];
+        }
+        if (any == 0) return 0u;
+    }
+    return lanes_from_masks(b);
 }
 
 // Fingerprint variant: the lane hashes the blocks at its byte 0, 8 and 16
@@ -207,11 +220,34 @@ __device__ __forceinline__ uint64_t status_load(uint64_t *p) {
 }
 
 // Single-pass look-back, run by one full wave.  Publishes the tile's count,
-// walks back over predecessors 64 at a time until an inclusive prefix is
-// found, publishes the tile's inclusive prefix, returns the exclusive one.
+// then reads kLookWindow predecessor status words per step (kLookLoads per
+// lane, issued together, so one memory round trip per step) until an
+// inclusive prefix is found; publishes the tile's inclusive prefix and
+// returns the exclusive one.  The window bounds how fast the inclusive
+// frontier can advance (kLookWindow * tile bytes per round trip); measured,
+// a 256-entry window was no faster than 64 on 128 KiB tiles, so one load
+// per lane is used.
 // Every wait ends: a tile's aggregate is published before its own look-back,
 // and a tile only waits on lower-indexed workgroups, which in-order dispatch
 // has already started.  The poll bound only guarantees termination.
+constexpr int kLookLoads = 1;
+constexpr int kLookWindow = kLookLoads * kWave;
+
+__device__ __forceinline__ uint64_t poll_status(uint64_t *status, int64_t idx, uint32_t *fault) {
+    if (idx < 0) return kFlagInclusive;  // before tile 0: an inclusive zero
+    uint64_t st = status_load(&status[idx]);
+    uint32_t polls = 0;
+    while ((st >> 62) == 0) {
+        if (++polls == kSpinLimit) {
+            __hip_atomic_store(fault, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            return kFlagInclusive;
+        }
+        __builtin_amdgcn_s_sleep(1);
+        st = status_load(&status[idx]);
+    }
+    return st;
+}
+
 __device__ uint64_t look_back(uint64_t *status, uint32_t tile, uint64_t cnt, int lane,
                               uint32_t *fault) {
     if (tile == 0) {
@@ -222,27 +258,26 @@ __device__ uint64_t look_back(uint64_t *status, uint32_t tile, uint64_t cnt, int
     uint64_t excl = 0;
     int64_t top = (int64_t)tile - 1;
     for (;;) {
-        const int64_t idx = top - lane;
-        uint64_t st = kFlagInclusive;  // before tile 0: an inclusive zero
-        if (idx >= 0) {
-            st = status_load(&status[idx]);
-            uint32_t polls = 0;
-            while ((st >> 62) == 0) {
-                if (++polls == kSpinLimit) {
-                    __hip_atomic_store(fault, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    st = kFlagInclusive;
-                    break;
-                }
-                __builtin_amdgcn_s_sleep(1);
-                st = status_load(&status[idx]);
+        // entry j*64 + lane of the window is tile top - (j*64 + lane)
+        uint64_t st[kLookLoads];
+#pragma unroll
+        for (int j = 0; j < kLookLoads; ++j) {
+            const int64_t idx = top - (j * kWave + lane);
+            st[j] = idx >= 0 ? status_load(&status[idx]) : kFlagInclusive;
+        }
+        bool found = false;
+#pragma unroll
+        for (int j = 0; j < kLookLoads; ++j) {
+            if (!found) {
+                if ((st[j] >> 62) == 0) st[j] = poll_status(status, top - (j * kWave + lane), fault);
+                const uint64_t incl = __ballot((st[j] >> 62) == 2);
+                const int first = incl ? __ffsll((unsigned long long)incl) - 1 : kWave;
+                excl += wave_sum64(lane <= first ? (st[j] & kValueMask) : 0);
+                found = incl != 0;
             }
         }
-        const uint64_t incl = __ballot((st >> 62) == 2);
-        const int first = incl ? __ffsll((unsigned long long)incl) - 1 : kWave;
-        const uint64_t v = lane <= first ? (st & kValueMask) : 0;
-        excl += wave_sum64(v);
-        if (incl) break;
-        top -= kWave;
+        if (found) break;
+        top -= kLookWindow;
     }
     if (lane == 0) status_store(&status[tile], kFlagInclusive | (excl + cnt));
     return excl;
