@@ -180,6 +180,31 @@ epsm_status epsm_search_batch(const epsm_batch *batch, void *stream);
  * against concurrent searches.  Output never depends on the choice. */
 epsm_status epsm_set_tile_config(uint32_t waves, uint32_t pieces);
 
+/*
+ * Prepared batches, for callers that run the same batch structure many times
+ * (a serving loop, graph replays).  epsm_batch_prepare validates the batch,
+ * builds the work descriptors and copies them to device memory owned by the
+ * returned handle (synchronous; the host arrays may be freed afterwards).
+ * The output pointers of *batch are recorded and reused by every launch.
+ * epsm_batch_launch submits the batch on `stream`: on a non-null stream the
+ * kernel sequence is captured into a HIP graph on first use and replayed
+ * after that (no host round trip, no allocation); on the null stream the
+ * kernels are launched directly.  Launches on one handle must not overlap.
+ * Plans referenced by the batch must outlive the handle.
+ */
+typedef struct epsm_batch_plan_s *epsm_batch_plan_t;
+epsm_status epsm_batch_prepare(const epsm_batch *batch, epsm_batch_plan_t *out);
+epsm_status epsm_batch_launch(epsm_batch_plan_t bp, void *stream);
+void epsm_batch_destroy(epsm_batch_plan_t bp);
+/* Work units (text tiles), (pair, tile) entries and tile bytes of a prepared
+ * batch; any output pointer may be NULL. */
+epsm_status epsm_batch_get_info(epsm_batch_plan_t bp, uint64_t *units, uint64_t *entries,
+                                uint32_t *tile_bytes);
+
+/* Select the batch tile (`waves` KiB per text tile: 4, 8 or 16) used by later
+ * batch calls.  Output never depends on the choice. */
+epsm_status epsm_set_batch_config(uint32_t waves);
+
 /* ---- workspace and diagnostics -------------------------------------------- */
 
 /* Make sure the workspace tied to `stream` can serve texts of up to max_n

@@ -21,7 +21,8 @@ from ._lib import (BATCH_COUNT_ONLY, MAX_M, PLAN_COLLIDE, PLAN_FORCE_DIRECT,  # 
                    VARIANT_FINGERPRINT)
 
 __all__ = ["EpsmError", "Plan", "search", "count", "search_into", "count_into", "reserve",
-           "stream_check", "lib", "library_path"]
+           "stream_check", "lib", "library_path", "Batch", "BatchPlan", "search_batch",
+           "set_tile_config", "set_batch_config"]
 
 
 def lib():
@@ -162,3 +163,106 @@ def stream_check(stream=None) -> None:
 
 def reserve(max_n: int, max_units: int = 0, stream=None) -> None:
     _check(lib().epsm_reserve(_stream_handle(stream), max_n, max_units), "epsm_reserve")
+
+
+# ---------------------------------------------------------------------------
+# batched search
+
+
+class Batch:
+    """Marshalled epsm_batch: texts (uint8 CUDA tensors) and (text index, Plan) pairs.
+
+    Output tensors are allocated by the caller or by search_batch; this class
+    only keeps the ctypes arrays (and the tensors they point into) alive.
+    """
+
+    def __init__(self, texts, pairs, out=None, counts=None, offsets=None, total=None,
+                 count_only: bool = False):
+        for t in texts:
+            _check_text(t)
+        self.texts = list(texts)
+        self.pairs = [(int(ti), p) for ti, p in pairs]
+        dev = self.texts[0].device if self.texts else torch.device("cuda")
+        n_pairs = len(self.pairs)
+        self.counts = counts if counts is not None else torch.zeros(max(n_pairs, 1), dtype=torch.int64, device=dev)
+        self.offsets = offsets if offsets is not None else torch.zeros(max(n_pairs, 1), dtype=torch.int64, device=dev)
+        self.total = total if total is not None else torch.zeros(1, dtype=torch.int64, device=dev)
+        self.out = out
+        tr = (_lib.TextRef * max(len(self.texts), 1))()
+        for i, t in enumerate(self.texts):
+            tr[i].d_text = t.data_ptr() if t.numel() else None
+            tr[i].n = t.numel()
+        pr = (_lib.PairRef * max(n_pairs, 1))()
+        for k, (ti, p) in enumerate(self.pairs):
+            pr[k].text = ti
+            pr[k].plan = p.handle
+        self._tr, self._pr = tr, pr
+        b = _lib.Batch()
+        b.texts = ctypes.cast(tr, ctypes.POINTER(_lib.TextRef))
+        b.n_texts = len(self.texts)
+        b.pairs = ctypes.cast(pr, ctypes.POINTER(_lib.PairRef))
+        b.n_pairs = n_pairs
+        b.d_out = out.data_ptr() if out is not None and out.numel() else None
+        b.out_capacity = 0 if out is None else out.numel()
+        b.d_counts = self.counts.data_ptr()
+        b.d_offsets = self.offsets.data_ptr()
+        b.d_total = self.total.data_ptr()
+        b.flags = BATCH_COUNT_ONLY if count_only else 0
+        self.struct = b
+
+    def run(self, stream=None) -> None:
+        """One-shot epsm_search_batch (descriptors go through the stream's workspace)."""
+        _check(lib().epsm_search_batch(ctypes.byref(self.struct), _stream_handle(stream)),
+               "epsm_search_batch")
+
+
+class BatchPlan:
+    """A prepared batch (epsm_batch_prepare); launch() replays a captured graph."""
+
+    def __init__(self, batch: Batch):
+        self.batch = batch  # keeps the referenced tensors and plans alive
+        self._handle = ctypes.c_void_p()
+        _check(lib().epsm_batch_prepare(ctypes.byref(batch.struct), ctypes.byref(self._handle)),
+               "epsm_batch_prepare")
+
+    def launch(self, stream=None) -> None:
+        _check(lib().epsm_batch_launch(self._handle, _stream_handle(stream)), "epsm_batch_launch")
+
+    def info(self) -> dict:
+        u, e, tb = ctypes.c_uint64(), ctypes.c_uint64(), ctypes.c_uint32()
+        _check(lib().epsm_batch_get_info(self._handle, ctypes.byref(u), ctypes.byref(e),
+                                         ctypes.byref(tb)), "epsm_batch_get_info")
+        return {"units": u.value, "entries": e.value, "tile_bytes": tb.value}
+
+    def close(self) -> None:
+        if self._handle and self._handle.value:
+            lib().epsm_batch_destroy(self._handle)
+            self._handle = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def search_batch(texts, pairs, stream=None):
+    """All (text, pattern) pairs; returns (positions, counts, offsets) as int64 tensors.
+
+    pairs: iterable of (text index, Plan or bytes).  Runs a count-only batch to
+    size the output, then the full batch.
+    """
+    pairs = [(ti, _as_plan(p)) for ti, p in pairs]
+    b0 = Batch(texts, pairs, count_only=True)
+    b0.run(stream)
+    total = int(b0.total.item())
+    dev = texts[0].device if texts else torch.device("cuda")
+    out = torch.empty(max(total, 1), dtype=torch.int64, device=dev)
+    b1 = Batch(texts, pairs, out=out[:total] if total else None)
+    b1.run(stream)
+    n = len(pairs)
+    return out[:total], b1.counts[:n], b1.offsets[:n]
+
+
+def set_batch_config(waves: int) -> None:
+    _check(lib().epsm_set_batch_config(waves), "epsm_set_batch_config")

@@ -81,6 +81,13 @@ SIGNATURES = {
                                   ctypes.c_void_p, ctypes.c_void_p]),
     "epsm_search_batch": (ctypes.c_int, [ctypes.POINTER(Batch), ctypes.c_void_p]),
     "epsm_set_tile_config": (ctypes.c_int, [ctypes.c_uint32, ctypes.c_uint32]),
+    "epsm_set_batch_config": (ctypes.c_int, [ctypes.c_uint32]),
+    "epsm_batch_prepare": (ctypes.c_int, [ctypes.POINTER(Batch), ctypes.POINTER(ctypes.c_void_p)]),
+    "epsm_batch_launch": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    "epsm_batch_destroy": (None, [ctypes.c_void_p]),
+    "epsm_batch_get_info": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_uint64),
+                                           ctypes.POINTER(ctypes.c_uint64),
+                                           ctypes.POINTER(ctypes.c_uint32)]),
     "epsm_reserve": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint64]),
     "epsm_release": (None, []),
     "epsm_stream_check": (ctypes.c_int, [ctypes.c_void_p]),

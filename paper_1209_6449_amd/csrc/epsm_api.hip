@@ -17,6 +17,8 @@
 
 using namespace epsm;
 
+struct epsm_batch_plan_s;
+
 struct epsm_plan_s {
     std::vector<uint8_t> pattern;
     std::vector<uint16_t> table;  // host copy, fingerprint only
@@ -25,6 +27,16 @@ struct epsm_plan_s {
     int device = -1;
     uint8_t *d_pattern = nullptr;
     uint16_t *d_table = nullptr;
+};
+
+// Where a batch writes its results.
+struct epsm_batch_outputs {
+    int64_t *d_out;
+    uint64_t cap;
+    uint64_t *d_counts;
+    uint64_t *d_offsets;
+    uint64_t *d_total;
+    bool write;
 };
 
 namespace {
@@ -175,7 +187,173 @@ epsm_status run_search(epsm_plan_t plan, const uint8_t *d_text, uint64_t n, int6
     return EPSM_OK;
 }
 
+
+// ---- batched search: host side ----------------------------------------------
+
+int g_batch_waves = 8;  // batch tile = g_batch_waves KiB
+
+struct HostBatch {
+    std::vector<BatchTextDesc> texts;
+    std::vector<BatchPairDesc> pairs;
+    std::vector<uint32_t> order;
+    std::vector<BatchUnit> units;
+    uint64_t entries = 0;
+    int waves = 8;
+};
+
+// Byte layout of the device copy of a batch: descriptors, then the
+// (pair, tile) counts, their offsets and the scan's block sums.
+struct BatchLayout {
+    size_t texts, pairs, order, units, ptc, pto, bsum, total;
+    explicit BatchLayout(const HostBatch &hb) {
+        auto up = [](size_t x) { return (x + 255) & ~size_t(255); };
+        size_t at = 0;
+        texts = at; at += up(hb.texts.size() * sizeof(BatchTextDesc));
+        pairs = at; at += up(hb.pairs.size() * sizeof(BatchPairDesc));
+        order = at; at += up(hb.order.size() * sizeof(uint32_t));
+        units = at; at += up(hb.units.size() * sizeof(BatchUnit));
+        ptc = at; at += up(hb.entries * sizeof(uint32_t));
+        pto = at; at += up((hb.entries + 1) * sizeof(uint64_t));
+        bsum = at; at += up(((hb.entries + kScanBlock - 1) / kScanBlock + 1) * sizeof(uint64_t));
+        total = at;
+    }
+};
+
+struct BatchPtrs {
+    BatchTextDesc *texts;
+    BatchPairDesc *pairs;
+    uint32_t *order;
+    BatchUnit *units;
+    uint32_t *ptc;
+    uint64_t *pto;
+    uint64_t *bsum;
+};
+
+BatchPtrs batch_ptrs(uint8_t *base, const BatchLayout &L) {
+    return {(BatchTextDesc *)(base + L.texts), (BatchPairDesc *)(base + L.pairs),
+            (uint32_t *)(base + L.order), (BatchUnit *)(base + L.units), (uint32_t *)(base + L.ptc),
+            (uint64_t *)(base + L.pto), (uint64_t *)(base + L.bsum)};
+}
+
+epsm_status build_batch(const epsm_batch *b, int waves, HostBatch &hb) {
+    if (!b) return fail(EPSM_EINVAL, "batch is NULL");
+    if (b->flags & ~EPSM_BATCH_COUNT_ONLY) return fail(EPSM_EINVAL, "unknown batch flags");
+    if (b->n_texts && !b->texts) return fail(EPSM_EINVAL, "texts is NULL");
+    if (b->n_pairs && !b->pairs) return fail(EPSM_EINVAL, "pairs is NULL");
+    if (b->n_pairs && (!b->d_counts || !b->d_offsets))
+        return fail(EPSM_EINVAL, "d_counts and d_offsets are required");
+    const bool write = !(b->flags & EPSM_BATCH_COUNT_ONLY);
+    if (write && b->out_capacity && !b->d_out) return fail(EPSM_EINVAL, "d_out is NULL with out_capacity > 0");
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    const uint64_t tile_bytes = (uint64_t)waves * kWavePiece;
+    hb.waves = waves;
+    hb.texts.assign(b->n_texts, BatchTextDesc{});
+    std::vector<uint32_t> text_tiles(b->n_texts, 0), text_pairs(b->n_texts, 0);
+    for (uint32_t i = 0; i < b->n_texts; ++i) {
+        const epsm_text_ref &t = b->texts[i];
+        if (t.n && !t.d_text) return fail(EPSM_EINVAL, "a text with n > 0 has a NULL pointer");
+        const uintptr_t addr = (uintptr_t)t.d_text;
+        BatchTextDesc &d = hb.texts[i];
+        d.base = (const uint8_t *)(addr & ~uintptr_t(15));
+        d.delta = addr & 15;
+        d.n = t.n;
+        d.load_end = (d.delta + t.n + 15) & ~uint64_t(15);
+        const uint64_t tiles = t.n ? (d.delta + t.n + tile_bytes - 1) / tile_bytes : 0;
+        if (tiles > 0xFFFFFFFFull) return fail(EPSM_EUNSUPPORTED, "text too long for a batch");
+        text_tiles[i] = (uint32_t)tiles;
+    }
+    hb.pairs.assign(b->n_pairs, BatchPairDesc{});
+    uint64_t entries = 0;
+    for (uint32_t k = 0; k < b->n_pairs; ++k) {
+        const epsm_pair_ref &pr = b->pairs[k];
+        if (pr.text >= b->n_texts) return fail(EPSM_EINVAL, "pair refers to a text out of range");
+        epsm_status st = check_plan(pr.plan);
+        if (st != EPSM_OK) return st;
+        BatchPairDesc &d = hb.pairs[k];
+        d.plan = pr.plan->dev;
+        d.text = pr.text;
+        d.tiles = pr.plan->dev.m <= b->texts[pr.text].n ? text_tiles[pr.text] : 0;
+        d.cnt_base = entries;
+        entries += d.tiles;
+        if (d.tiles) text_pairs[pr.text]++;
+    }
+    hb.entries = entries;
+    // pairs grouped by text (pair order kept within a text)
+    std::vector<uint32_t> start(b->n_texts + 1, 0);
+    for (uint32_t i = 0; i < b->n_texts; ++i) start[i + 1] = start[i] + text_pairs[i];
+    hb.order.assign(start[b->n_texts], 0);
+    std::vector<uint32_t> fillp(start.begin(), start.end() - 1);
+    for (uint32_t k = 0; k < b->n_pairs; ++k)
+        if (hb.pairs[k].tiles) hb.order[fillp[hb.pairs[k].text]++] = k;
+    uint64_t units = 0;
+    for (uint32_t i = 0; i < b->n_texts; ++i) {
+        hb.texts[i].pair_begin = start[i];
+        hb.texts[i].pair_end = start[i + 1];
+        if (text_pairs[i]) units += text_tiles[i];
+    }
+    if (units > 0x7FFFFFFFull) return fail(EPSM_EUNSUPPORTED, "batch has too many tiles");
+    hb.units.reserve(units);
+    for (uint32_t i = 0; i < b->n_texts; ++i)
+        if (text_pairs[i])
+            for (uint32_t t = 0; t < text_tiles[i]; ++t) hb.units.push_back({i, t});
+    return EPSM_OK;
+}
+
+epsm_status upload_batch(const HostBatch &hb, const BatchLayout &L, uint8_t *dev, hipStream_t s) {
+    const BatchPtrs P = batch_ptrs(dev, L);
+    hipError_t e = hipSuccess;
+    auto put = [&](void *dst, const void *src, size_t bytes) {
+        if (e == hipSuccess && bytes) e = hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, s);
+    };
+    put(P.texts, hb.texts.data(), hb.texts.size() * sizeof(BatchTextDesc));
+    put(P.pairs, hb.pairs.data(), hb.pairs.size() * sizeof(BatchPairDesc));
+    put(P.order, hb.order.data(), hb.order.size() * sizeof(uint32_t));
+    put(P.units, hb.units.data(), hb.units.size() * sizeof(BatchUnit));
+    // pageable sources: the copies are staged before hipMemcpyAsync returns,
+    // but finish them here so the host vectors can be released safely
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    return e == hipSuccess ? EPSM_OK : hip_fail(e, "batch descriptor upload");
+}
+
+// The kernel sequence of one batch (stream ordered, no host round trip).
+epsm_status run_batch(const BatchPtrs &P, const HostBatch &hb, const epsm_batch_outputs &o,
+                      hipStream_t s) {
+    BatchArgs a{};
+    a.texts = P.texts;
+    a.pairs = P.pairs;
+    a.pair_order = P.order;
+    a.units = P.units;
+    a.pt_count = P.ptc;
+    a.pt_offset = P.pto;
+    a.out = o.d_out;
+    a.cap = o.cap;
+    const uint32_t n_units = (uint32_t)hb.units.size();
+    a.write = 0;
+    hipError_t e = launch_batch(a, hb.waves, n_units, s);
+    if (e == hipSuccess) e = launch_scan_counts(P.ptc, hb.entries, P.pto, P.bsum, s);
+    if (e == hipSuccess)
+        e = launch_batch_finalize(P.pairs, (uint32_t)hb.pairs.size(), P.pto, hb.entries, o.d_counts,
+                                  o.d_offsets, o.d_total, s);
+    if (e == hipSuccess && o.write && o.cap) {
+        a.write = 1;
+        e = launch_batch(a, hb.waves, n_units, s);
+    }
+    return e == hipSuccess ? EPSM_OK : hip_fail(e, "batch launch");
+}
+
 }  // namespace
+
+struct epsm_batch_plan_s {
+    HostBatch hb;               // sizes; units kept only for their count
+    BatchPtrs ptrs{};
+    epsm_batch_outputs out{};
+    uint8_t *mem = nullptr;
+    int device = -1;
+    std::mutex mutex;
+    std::map<hipStream_t, hipGraphExec_t> graphs;
+};
 
 extern "C" {
 
@@ -300,10 +478,113 @@ epsm_status epsm_count(epsm_plan_t plan, const uint8_t *d_text, uint64_t n, uint
     return run_search(plan, d_text, n, nullptr, 0, d_n_hits, (hipStream_t)stream, false);
 }
 
+
 epsm_status epsm_search_batch(const epsm_batch *batch, void *stream) {
-    (void)stream;
-    if (!batch) return fail(EPSM_EINVAL, "batch is NULL");
-    return fail(EPSM_EUNSUPPORTED, "batched search not built yet");
+    g_last_error.clear();
+    HostBatch hb;
+    epsm_status st = build_batch(batch, g_batch_waves, hb);
+    if (st != EPSM_OK) return st;
+    const BatchLayout L(hb);
+    uint8_t *ws = nullptr;
+    st = workspace_for((hipStream_t)stream, L.total, &ws);
+    if (st != EPSM_OK) return st;
+    st = upload_batch(hb, L, ws, (hipStream_t)stream);
+    if (st != EPSM_OK) return st;
+    const epsm_batch_outputs o{batch->d_out, batch->out_capacity, batch->d_counts, batch->d_offsets,
+                               batch->d_total, !(batch->flags & EPSM_BATCH_COUNT_ONLY)};
+    return run_batch(batch_ptrs(ws, L), hb, o, (hipStream_t)stream);
+}
+
+epsm_status epsm_batch_prepare(const epsm_batch *batch, epsm_batch_plan_t *out) {
+    g_last_error.clear();
+    if (!out) return fail(EPSM_EINVAL, "out is NULL");
+    *out = nullptr;
+    epsm_batch_plan_s *bp = new (std::nothrow) epsm_batch_plan_s();
+    if (!bp) return fail(EPSM_ENOMEM, "batch plan allocation");
+    epsm_status st = build_batch(batch, g_batch_waves, bp->hb);
+    if (st != EPSM_OK) {
+        delete bp;
+        return st;
+    }
+    const BatchLayout L(bp->hb);
+    hipError_t e = hipGetDevice(&bp->device);
+    if (e == hipSuccess) e = hipMalloc(&bp->mem, std::max<size_t>(L.total, 256));
+    if (e != hipSuccess) {
+        bp->mem = nullptr;
+        epsm_batch_destroy(bp);
+        return hip_fail(e, "batch plan device memory");
+    }
+    st = upload_batch(bp->hb, L, bp->mem, nullptr);
+    if (st != EPSM_OK) {
+        epsm_batch_destroy(bp);
+        return st;
+    }
+    bp->ptrs = batch_ptrs(bp->mem, L);
+    bp->out = {batch->d_out, batch->out_capacity, batch->d_counts, batch->d_offsets, batch->d_total,
+               !(batch->flags & EPSM_BATCH_COUNT_ONLY)};
+    // descriptors stay on the device; the host copies are no longer needed
+    bp->hb.texts.clear();
+    bp->hb.texts.shrink_to_fit();
+    bp->hb.order.clear();
+    bp->hb.order.shrink_to_fit();
+    bp->hb.units.shrink_to_fit();
+    *out = bp;
+    return EPSM_OK;
+}
+
+epsm_status epsm_batch_launch(epsm_batch_plan_t bp, void *stream) {
+    g_last_error.clear();
+    if (!bp) return fail(EPSM_EINVAL, "batch plan is NULL");
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    if (dev != bp->device) return fail(EPSM_EINVAL, "batch plan belongs to another device");
+    hipStream_t s = (hipStream_t)stream;
+    if (!s) return run_batch(bp->ptrs, bp->hb, bp->out, s);  // the null stream cannot be captured
+    std::lock_guard<std::mutex> lock(bp->mutex);
+    auto it = bp->graphs.find(s);
+    if (it == bp->graphs.end()) {
+        hipGraph_t g = nullptr;
+        e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
+        epsm_status st = run_batch(bp->ptrs, bp->hb, bp->out, s);
+        e = hipStreamEndCapture(s, &g);
+        if (st != EPSM_OK) {
+            if (g) (void)hipGraphDestroy(g);
+            return st;
+        }
+        if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+        hipGraphExec_t ge = nullptr;
+        e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (e != hipSuccess) return hip_fail(e, "hipGraphInstantiate");
+        it = bp->graphs.emplace(s, ge).first;
+    }
+    e = hipGraphLaunch(it->second, s);
+    return e == hipSuccess ? EPSM_OK : hip_fail(e, "hipGraphLaunch");
+}
+
+void epsm_batch_destroy(epsm_batch_plan_t bp) {
+    if (!bp) return;
+    for (auto &kv : bp->graphs) (void)hipGraphExecDestroy(kv.second);
+    if (bp->mem) (void)hipFree(bp->mem);
+    delete bp;
+}
+
+epsm_status epsm_batch_get_info(epsm_batch_plan_t bp, uint64_t *units, uint64_t *entries,
+                                uint32_t *tile_bytes) {
+    if (!bp) return fail(EPSM_EINVAL, "batch plan is NULL");
+    if (units) *units = bp->hb.units.size();
+    if (entries) *entries = bp->hb.entries;
+    if (tile_bytes) *tile_bytes = (uint32_t)(bp->hb.waves * kWavePiece);
+    return EPSM_OK;
+}
+
+epsm_status epsm_set_batch_config(uint32_t waves) {
+    g_last_error.clear();
+    if (!batch_waves_supported((int)waves)) return fail(EPSM_EUNSUPPORTED, "batch tile not built");
+    g_batch_waves = (int)waves;
+    return EPSM_OK;
 }
 
 epsm_status epsm_set_tile_config(uint32_t waves, uint32_t pieces) {

@@ -65,6 +65,54 @@ struct ScanArgs {
     DevPlan plan;
 };
 
+// ---- batched search -------------------------------------------------------
+// A unit is one tile of one text; its workgroup loads the tile once and runs
+// every pattern aimed at that text over it.
+
+struct BatchTextDesc {
+    const uint8_t *base;     // 16-byte aligned address at or below the text start
+    uint64_t delta;          // text start - base
+    uint64_t n;              // text length
+    uint64_t load_end;       // round_up(delta + n, 16)
+    uint32_t pair_begin;     // this text's pairs are pair_order[pair_begin, pair_end)
+    uint32_t pair_end;
+};
+
+struct BatchPairDesc {
+    DevPlan plan;
+    uint64_t cnt_base;       // first (pair, tile) entry of this pair
+    uint32_t text;
+    uint32_t tiles;          // entries of this pair: tiles of its text, 0 if m > n
+};
+
+struct BatchUnit {
+    uint32_t text;
+    uint32_t tile;
+};
+
+struct BatchArgs {
+    const BatchTextDesc *texts;
+    const BatchPairDesc *pairs;
+    const uint32_t *pair_order;
+    const BatchUnit *units;
+    uint32_t *pt_count;        // [entries] hits of each (pair, tile)
+    const uint64_t *pt_offset; // [entries + 1] exclusive prefix of pt_count (write pass)
+    int64_t *out;
+    uint64_t cap;
+    uint32_t write;
+};
+
+hipError_t launch_batch(const BatchArgs &a, int waves, uint32_t n_units, hipStream_t s);
+bool batch_waves_supported(int waves);
+// Exclusive scan of entries u32 counts into offsets[0..entries] (u64), using
+// block_sums (ceil(entries / kScanBlock) u64) as scratch.
+constexpr uint32_t kScanBlock = 4096;
+hipError_t launch_scan_counts(const uint32_t *counts, uint64_t entries, uint64_t *offsets,
+                              uint64_t *block_sums, hipStream_t s);
+hipError_t launch_batch_finalize(const BatchPairDesc *pairs, uint32_t n_pairs,
+                                 const uint64_t *offsets, uint64_t entries, uint64_t *counts,
+                                 uint64_t *pair_offsets, uint64_t *total, hipStream_t s);
+
 // Tile geometry of one kernel configuration.
 struct TileConfig {
     int waves;   // waves per workgroup

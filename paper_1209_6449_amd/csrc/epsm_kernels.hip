@@ -36,316 +36,9 @@
 // counts of its later tiles behind the writes of its earlier ones, which
 // serialises the chain, so workgroups are not persistent.  Count-only
 // searches skip the look-back.
-#include "epsm_internal.h"
+#include "epsm_device.h"
 
 namespace epsm {
-
-typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
-
-// gfx9-family raw buffer descriptor word 3 (32-bit data format, no swizzle).
-constexpr int kRsrcWord3 = 0x00020000;
-
-__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const uint8_t *p, uint32_t bytes) {
-    return __builtin_amdgcn_make_buffer_rsrc(const_cast<uint8_t *>(p), (short)0, (int)bytes,
-                                             kRsrcWord3);
-}
-
-__device__ __forceinline__ u32x4 load16(__amdgpu_buffer_rsrc_t r, uint32_t off) {
-    return __builtin_amdgcn_raw_buffer_load_b128(r, (int)off, 0, 0);
-}
-
-// Window of 4 text bytes starting at byte k of the lane's register run w.
-template <int N>
-__device__ __forceinline__ uint32_t window(const uint32_t (&w)[N], int k) {
-    const int q = k >> 2, r = k & 3;
-    return r == 0 ? w[q] : __builtin_amdgcn_alignbyte(w[q + 1], w[q], (uint32_t)r);
-}
-
-__device__ __forceinline__ uint64_t ballot(bool c) { return __builtin_amdgcn_ballot_w64(c); }
-__device__ __forceinline__ bool wave_any(bool c) { return ballot(c) != 0; }
-
-// Narrow a wave mask of candidates at lane byte k with pattern words
-// j0..nw-1 (each compare is one v_cmp whose result is the wave mask itself).
-// Stops as soon as no lane of the wave has a candidate left.  nw is the
-// template constant NW, or the plan's runtime value when NW == 0.
-template <int NWMAX, int NW, int N>
-__device__ __forceinline__ uint64_t verify_words(const uint32_t (&w)[N], int k, uint64_t b, int j0,
-                                                 const DevPlan &p) {
-#pragma unroll
-    for (int j = 0; j < NWMAX; ++j) {
-        const bool in_range = NW > 0 ? (j < NW) : (j < (int)p.nw);
-        if (j >= j0 && in_range && b != 0)
-            b &= ballot((window(w, k + 4 * j) & p.pmask[j]) == p.pw[j]);
-    }
-    return b;
-}
-
-// Per-lane 16-bit mask from the 16 wave masks: bit k of lane L is bit L of b[k].
-__device__ __forceinline__ uint32_t lanes_from_masks(const uint64_t (&b)[16]) {
-    uint32_t lm = 0;
-#pragma unroll
-    for (int k = 15; k >= 0; --k)
-        lm = lm + lm + (__builtin_amdgcn_inverse_ballot_w64(b[k]) ? 1u : 0u);
-    return lm;
-}
-
-// Direct variant: 16-bit hit mask of one lane piece (positions 0..15).
-// All 16 prefix compares come first and their wave masks are OR-ed once;
-// only a wave with some candidate narrows them with the remaining pattern
-// words and transposes them into per-lane masks.  Keeping the common path
-// free of per-position branches matters: the scalar unit issues one
-// instruction per SIMD every four cycles and was the bottleneck.
-template <int NL, int PK, int NW>
-__device__ __forceinline__ uint32_t direct_mask(const uint32_t (&w)[NL * 4 + 1], const DevPlan &p) {
-    constexpr int NWMAX = 4 * NL - 4;
-    uint64_t b[16];
-    uint64_t any = 0;
-#pragma unroll
-    for (int k = 0; k < 16; ++k) {
-        const int q = k >> 2, r = k & 3;
-        bool c;
-        if constexpr (PK == 1) {
-            c = ((w[q] >> (8 * r)) & 0xFFu) == p.pw[0];
-        } else if constexpr (PK == 2) {
-            c = (window(w, k) & 0xFFFFu) == p.pw[0];
-        } else if constexpr (PK == 3) {
-            // bytes k..k+2 of the run and a zero top byte in one v_perm
-            const uint32_t sel = (uint32_t)r | ((uint32_t)(r + 1) << 8) |
-                                 ((uint32_t)(r + 2) << 16) | (0x0Cu << 24);
-            c = __builtin_amdgcn_perm(w[q + 1], w[q], sel) == p.pw[0];
-        } else {
-            c = window(w, k) == p.pw[0];
-        }
-        b[k] = ballot(c);
-        any |= b[k];
-    }
-    if (any == 0) return 0u;
-    if constexpr (PK >= 4 && (NW == 0 || NW > 1)) {
-        any = 0;
-#pragma unroll
-        for (int k = 0; k < 16; ++k) {
-            if (b[k]) b[k] = verify_words<NWMAX, NW>(w, k, b[k], 1, p);
-            any |= b[k];
-        }
-        if (any == 0) return 0u;
-    }
-    return lanes_from_masks(b);
-}
-
-// Fingerprint variant: the lane hashes the blocks at its byte 0, 8 and 16
-// (the last one is the next lane's first block).  Table entry bit (8-j)
-// marks offset j, so the candidates relative to the lane start are
-// block0: bit 8 -> start 0; block8: bits 1..8 -> starts 1..8;
-// block16: bits 1..7 -> starts 9..15 (bit 8 = start 16 belongs to the next lane).
-template <int NL>
-__device__ __forceinline__ uint32_t fingerprint_mask(const uint32_t (&w)[NL * 4 + 1],
-                                                     const DevPlan &p, const uint16_t *tab) {
-    constexpr int NWMAX = 4 * NL - 4;
-    uint32_t v0 = 0, v1 = 0, v2 = 0;
-    if (!p.collide) {
-        v0 = fp_hash(w[0], w[1], p.hash_bits);
-        v1 = fp_hash(w[2], w[3], p.hash_bits);
-        v2 = fp_hash(w[4], w[5], p.hash_bits);
-    }
-    const uint32_t cm = ((uint32_t)tab[v0] >> 8) | (uint32_t)tab[v1] |
-                        (((uint32_t)tab[v2] << 8) & 0xFFFFu);
-    if (!wave_any(cm != 0)) return 0u;
-    uint64_t b[16];
-    uint64_t any = 0;
-#pragma unroll
-    for (int k = 0; k < 16; ++k) {
-        uint64_t bk = ballot((cm >> k) & 1u);
-        if (bk) bk = verify_words<NWMAX, 0>(w, k, bk, 0, p);
-        b[k] = bk;
-        any |= bk;
-    }
-    return any ? lanes_from_masks(b) : 0u;
-}
-
-// Start positions of the lane piece at base coordinate s0 that are valid
-// (delta <= s <= last), as a 16-bit mask.
-__device__ __forceinline__ uint32_t valid_mask(uint64_t s0, uint64_t delta, uint64_t last) {
-    uint32_t lo = 0, hi = 16;
-    if (delta > s0) lo = (delta - s0) > 16 ? 16u : (uint32_t)(delta - s0);
-    if (last < s0) hi = 0;
-    else if (last - s0 < 15) hi = (uint32_t)(last - s0) + 1;
-    return ((1u << hi) - 1u) & ~((1u << lo) - 1u);
-}
-
-// Exact check of pattern bytes [4*nw, m) for each candidate (patterns longer
-// than the register run); reads the text and pattern from global memory.
-__device__ __noinline__ uint32_t tail_check(uint32_t mk, uint64_t s0, const uint8_t *base,
-                                            const uint8_t *pattern, uint64_t m, uint32_t from) {
-    uint32_t keep = 0;
-    while (mk) {
-        const uint32_t k = __builtin_ctz(mk);
-        mk &= mk - 1;
-        const uint8_t *t = base + s0 + k;
-        bool ok = true;
-        for (uint64_t j = from; j < m; ++j) {
-            if (t[j] != pattern[j]) { ok = false; break; }
-        }
-        if (ok) keep |= 1u << k;
-    }
-    return keep;
-}
-
-__device__ __forceinline__ uint32_t wave_sum32(uint32_t v) {
-#pragma unroll
-    for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, kWave);
-    return v;
-}
-
-__device__ __forceinline__ uint64_t wave_sum64(uint64_t v) {
-#pragma unroll
-    for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, kWave);
-    return v;
-}
-
-__device__ __forceinline__ uint32_t wave_incl_scan32(uint32_t v, int lane) {
-#pragma unroll
-    for (int d = 1; d < kWave; d <<= 1) {
-        const uint32_t t = __shfl_up(v, d, kWave);
-        if (lane >= d) v += t;
-    }
-    return v;
-}
-
-__device__ __forceinline__ void status_store(uint64_t *p, uint64_t v) {
-    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-__device__ __forceinline__ uint64_t status_load(uint64_t *p) {
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-// Single-pass look-back, run by one full wave.  Publishes the tile's count,
-// then reads kLookWindow predecessor status words per step (kLookLoads per
-// lane, issued together, so one memory round trip per step) until an
-// inclusive prefix is found; publishes the tile's inclusive prefix and
-// returns the exclusive one.  The window bounds how fast the inclusive
-// frontier can advance (kLookWindow * tile bytes per round trip); measured,
-// a 256-entry window was no faster than 64 on 128 KiB tiles, so one load
-// per lane is used.
-// Every wait ends: a tile's aggregate is published before its own look-back,
-// and a tile only waits on lower-indexed workgroups, which in-order dispatch
-// has already started.  The poll bound only guarantees termination.
-constexpr int kLookLoads = 1;
-constexpr int kLookWindow = kLookLoads * kWave;
-
-__device__ __forceinline__ uint64_t poll_status(uint64_t *status, int64_t idx, uint32_t *fault) {
-    if (idx < 0) return kFlagInclusive;  // before tile 0: an inclusive zero
-    uint64_t st = status_load(&status[idx]);
-    uint32_t polls = 0;
-    while ((st >> 62) == 0) {
-        if (++polls == kSpinLimit) {
-            __hip_atomic_store(fault, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            return kFlagInclusive;
-        }
-        __builtin_amdgcn_s_sleep(1);
-        st = status_load(&status[idx]);
-    }
-    return st;
-}
-
-__device__ uint64_t look_back(uint64_t *status, uint32_t tile, uint64_t cnt, int lane,
-                              uint32_t *fault) {
-    if (tile == 0) {
-        if (lane == 0) status_store(&status[0], kFlagInclusive | cnt);
-        return 0;
-    }
-    if (lane == 0) status_store(&status[tile], kFlagAggregate | cnt);
-    uint64_t excl = 0;
-    int64_t top = (int64_t)tile - 1;
-    for (;;) {
-        // entry j*64 + lane of the window is tile top - (j*64 + lane)
-        uint64_t st[kLookLoads];
-#pragma unroll
-        for (int j = 0; j < kLookLoads; ++j) {
-            const int64_t idx = top - (j * kWave + lane);
-            st[j] = idx >= 0 ? status_load(&status[idx]) : kFlagInclusive;
-        }
-        bool found = false;
-#pragma unroll
-        for (int j = 0; j < kLookLoads; ++j) {
-            if (!found) {
-                if ((st[j] >> 62) == 0) st[j] = poll_status(status, top - (j * kWave + lane), fault);
-                const uint64_t incl = __ballot((st[j] >> 62) == 2);
-                const int first = incl ? __ffsll((unsigned long long)incl) - 1 : kWave;
-                excl += wave_sum64(lane <= first ? (st[j] & kValueMask) : 0);
-                found = incl != 0;
-            }
-        }
-        if (found) break;
-        top -= kLookWindow;
-    }
-    if (lane == 0) status_store(&status[tile], kFlagInclusive | (excl + cnt));
-    return excl;
-}
-
-// Positions staged per wave before they are written out (wave-relative
-// offsets; one piece adds at most 1024).
-constexpr uint32_t kStage = 1024;
-
-// Write stage[0..fill) as positions wave_pos0 + stage[j] to out[obase + j]
-// (entries at or past cap are dropped).  Lanes write consecutive entries.
-__device__ __forceinline__ void flush_stage(const uint32_t *stage, uint32_t fill, int64_t *out,
-                                            uint64_t cap, uint64_t obase, int64_t wave_pos0,
-                                            int lane) {
-    // the stage was filled by other lanes of this wave: order the LDS accesses
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    for (uint32_t j = lane; j < fill; j += kWave) {
-        const uint64_t idx = obase + j;
-        if (idx < cap) out[idx] = wave_pos0 + stage[j];
-    }
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-}
-
-template <int U, int NL>
-__device__ __forceinline__ void load_chunk(uint32_t (&w)[U][NL * 4 + 1], __amdgpu_buffer_rsrc_t r,
-                                           uint32_t off) {
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-#pragma unroll
-        for (int l = 0; l < NL; ++l) {
-            const u32x4 v = load16(r, off + u * kWavePiece + l * kPiece);
-            w[u][4 * l + 0] = v.x;
-            w[u][4 * l + 1] = v.y;
-            w[u][4 * l + 2] = v.z;
-            w[u][4 * l + 3] = v.w;
-        }
-        w[u][NL * 4] = 0;
-    }
-}
-
-// Hit masks of the U pieces of one chunk, parked in LDS (two 16-bit masks per
-// word); returns the lane's hit count.
-template <int U, int NL, int VAR, int PK, int NW, int PAIRS, int THREADS>
-__device__ __forceinline__ uint32_t process_chunk(const uint32_t (&w)[U][NL * 4 + 1], int c,
-                                                  const ScanArgs &a, const uint16_t *tab,
-                                                  uint64_t lane_start, bool edge, bool tail,
-                                                  uint32_t (*s_mask)[THREADS], int tid) {
-    uint32_t cnt = 0, lo = 0;
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-        uint32_t mk;
-        if constexpr (VAR == 1) mk = direct_mask<NL, PK, NW>(w[u], a.plan);
-        else mk = fingerprint_mask<NL>(w[u], a.plan, tab);
-        const int piece = c * U + u;
-        const uint64_t s0 = lane_start + (uint64_t)piece * kWavePiece;
-        // only the first tile holds starts below delta and only the last
-        // one holds starts past `last`
-        if (edge) mk &= valid_mask(s0, a.delta, a.last);
-        if (tail && wave_any(mk != 0))
-            mk = tail_check(mk, s0, a.base, a.plan.pattern, a.plan.m, 4u * a.plan.nw);
-        cnt += __popc(mk);
-        if (u & 1) s_mask[piece >> 1][tid] = lo | (mk << 16);
-        else lo = mk;
-    }
-    return cnt;
-}
 
 // Write phase of one tile, run by each wave on its own span: expand the
 // parked masks into wave-relative offsets staged in LDS (ascending), and

@@ -1,0 +1,160 @@
+"""Batched search: output identical to per-pair plain searches and to the oracle.
+
+Integer work: bit-exact equality of positions, counts and offsets.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def epsm():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1209_6449_amd as mod
+    mod.lib()
+    return mod
+
+
+def say(msg):
+    print(msg, flush=True)
+
+
+def make_batch(seed, n_texts=60, min_len=1, max_len=300_000, max_pat=40):
+    """Texts of log-uniform length (some empty / shorter than m), sigma 2/4/64,
+    patterns cut or random with m in [1, 40], pairs in shuffled order."""
+    rng = np.random.default_rng(seed)
+    texts, host, pairs = [], [], []
+    for i in range(n_texts):
+        if i % 17 == 0:
+            n = 0
+        else:
+            n = int(math.exp(rng.uniform(math.log(max(min_len, 1)), math.log(max_len))))
+        sigma = int(rng.choice([2, 4, 64]))
+        t = rng.integers(0, sigma, n).astype(np.uint8)
+        off = int(rng.integers(0, 16))  # unaligned starts
+        buf = torch.zeros(n + off + 1, dtype=torch.uint8, device="cuda")
+        if n:
+            buf[off:off + n] = torch.from_numpy(t).cuda()
+        texts.append(buf[off:off + n])
+        host.append(t)
+        for _ in range(int(rng.integers(1, max_pat))):
+            m = int(rng.integers(1, 41))
+            if n >= m and rng.random() < 0.6:
+                o = int(rng.integers(0, n - m + 1))
+                p = t[o:o + m].tobytes()
+            else:
+                p = rng.integers(0, sigma, m).astype(np.uint8).tobytes()
+            pairs.append((i, p))
+    order = rng.permutation(len(pairs))
+    pairs = [pairs[k] for k in order]
+    return texts, host, pairs
+
+
+@pytest.mark.parametrize("waves", [4, 8, 16])
+def test_batch_equals_plain_and_oracle(epsm, waves):
+    epsm.set_batch_config(waves)
+    texts, host, pairs = make_batch(seed=waves)
+    plans = [(ti, epsm.Plan(p)) for ti, p in pairs]
+    say(f"batch waves={waves} texts={len(texts)} pairs={len(pairs)}")
+    pos, counts, offsets = epsm.search_batch(texts, plans)
+    epsm.stream_check()
+    pos, counts, offsets = pos.cpu().numpy(), counts.cpu().numpy(), offsets.cpu().numpy()
+    assert offsets[0] == 0
+    assert np.array_equal(offsets[1:], np.cumsum(counts)[:-1])
+    for k, (ti, plan) in enumerate(plans):
+        got = pos[offsets[k]:offsets[k] + counts[k]]
+        exp = oracle.positions(host[ti], plan.pattern)
+        assert np.array_equal(got, exp), (k, ti, len(plan.pattern))
+        if k % 7 == 0:
+            plain = epsm.search(texts[ti], plan).cpu().numpy()
+            assert np.array_equal(plain, got)
+    epsm.set_batch_config(8)
+
+
+def test_count_only_batch(epsm):
+    texts, host, pairs = make_batch(seed=5, n_texts=30)
+    plans = [(ti, epsm.Plan(p)) for ti, p in pairs]
+    b = epsm.Batch(texts, plans, count_only=True)
+    say("count-only batch")
+    b.run()
+    counts = b.counts[:len(plans)].cpu().numpy()
+    for k, (ti, plan) in enumerate(plans):
+        assert counts[k] == oracle.count(host[ti], plan.pattern)
+    assert int(b.total.item()) == counts.sum()
+
+
+def test_truncated_batch_output_is_prefix(epsm):
+    texts, host, pairs = make_batch(seed=9, n_texts=20)
+    plans = [(ti, epsm.Plan(p)) for ti, p in pairs]
+    full, counts, offsets = epsm.search_batch(texts, plans)
+    total = full.numel()
+    for cap in (0, 1, total // 3, total - 1):
+        say(f"truncated batch cap={cap} of {total}")
+        out = torch.full((max(cap, 1),), -5, dtype=torch.int64, device="cuda")
+        b = epsm.Batch(texts, plans, out=out[:cap] if cap else None)
+        b.run()
+        assert torch.equal(b.counts[:len(plans)], counts)
+        assert torch.equal(b.offsets[:len(plans)], offsets)
+        assert int(b.total.item()) == total
+        if cap:
+            assert torch.equal(out[:cap], full[:cap])
+
+
+def test_prepared_batch_graph_replays(epsm):
+    """A prepared batch replays its captured graph; every replay is identical,
+    with eager work and synchronisation between replays."""
+    texts, host, pairs = make_batch(seed=13, n_texts=40)
+    plans = [(ti, epsm.Plan(p)) for ti, p in pairs]
+    ref, counts, offsets = epsm.search_batch(texts, plans)
+    total = ref.numel()
+    out = torch.full((max(total, 1),), -1, dtype=torch.int64, device="cuda")
+    b = epsm.Batch(texts, plans, out=out[:total] if total else None)
+    bp = epsm.BatchPlan(b)
+    info = bp.info()
+    assert info["units"] > 0 and info["entries"] >= info["units"]
+    stream = torch.cuda.Stream()
+    for r in range(4):
+        say(f"graph replay {r}")
+        out.fill_(-1)
+        b.counts.zero_()
+        torch.cuda.synchronize()
+        with torch.cuda.stream(stream):
+            bp.launch(stream)
+        stream.synchronize()
+        assert torch.equal(out[:total], ref)
+        assert torch.equal(b.counts[:len(plans)], counts)
+        assert torch.equal(b.offsets[:len(plans)], offsets)
+        # unrelated eager work between replays
+        x = torch.randn(1000, device="cuda").sum()
+        torch.cuda.synchronize()
+    bp.close()
+
+
+def test_batch_with_config4_shapes_small(epsm):
+    """A scaled-down config-4 batch (log-uniform lengths, sigma 4/64, 1-64
+    patterns, m uniform in [1, 32], half cut / half random)."""
+    bts = W.config4(n_texts=40, min_len=1 << 10, max_len=1 << 18)
+    texts = [W.gen_bytes(bt.spec, device="cuda") for bt in bts]
+    host = [t.cpu().numpy() for t in texts]
+    pairs = [(i, epsm.Plan(p)) for i, bt in enumerate(bts) for p in bt.patterns]
+    say(f"config4-small pairs={len(pairs)}")
+    pos, counts, offsets = epsm.search_batch(texts, pairs)
+    pos, counts, offsets = pos.cpu().numpy(), counts.cpu().numpy(), offsets.cpu().numpy()
+    for k, (ti, plan) in enumerate(pairs):
+        exp = oracle.positions(host[ti], plan.pattern)
+        assert np.array_equal(pos[offsets[k]:offsets[k] + counts[k]], exp), k
+
+
+def test_empty_batch(epsm):
+    say("empty batch")
+    b = epsm.Batch([], [], count_only=False)
+    b.run()
+    assert int(b.total.item()) == 0
