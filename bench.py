@@ -14,6 +14,11 @@ by the workloads module; texts are resident in HBM before timing starts):
   zipf4g   4 GiB Zipf(1) English-like text, cut patterns m = 1..16, positions
            and count modes; plus the periodic text a^n with a^m (dense
            output, 8 bytes written per byte read at m = 1).
+  batch    10,000 texts, log-uniform lengths in [1 KiB, 16 MiB], sigma 4 or
+           64, 1..64 patterns each with m uniform in [1, 32] (half cut, half
+           random).  One step = the whole batch as one replay of a prepared,
+           graph-captured batch; compared with one epsm_search per pair on
+           the same texts (identical output checked on the device).
 
 value = logical text bytes scanned per second over the timed steps (GB/s,
 1 GB = 1e9 B).  roofline = the positions-mode scan kernel: algorithmic bytes
@@ -54,7 +59,8 @@ def parse_args():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="sweep1g", choices=["sweep1g", "zipf4g"])
+    ap.add_argument("--workload", default="sweep1g", choices=["sweep1g", "zipf4g", "batch"])
+    ap.add_argument("--batch-texts", type=int, default=10_000, help="texts in the batch workload")
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="CPU time budget of the oracle baseline (0 disables it)")
     ap.add_argument("--threads", type=int, default=0, help="oracle threads (0 = all host cores)")
@@ -100,6 +106,93 @@ def build_zipf4g(torch, W, epsm):
                           "4 GiB a^n with a^m (m=1..16); positions+count modes",
               "text_bytes": 1 << 32, "ms": list(range(1, 17)), "searches_per_step": len(cases)}
     return texts, [spec, per], cases, config
+
+
+def run_batch_workload(args, torch, W, epsm):
+    """Config-4 batch: batched graph replay vs per-instance plain searches."""
+    import ctypes
+    bts = W.config4(n_texts=args.batch_texts)
+    log(f"generating {len(bts)} batch texts on the GPU")
+    texts = [W.gen_bytes(bt.spec, device="cuda") for bt in bts]
+    torch.cuda.synchronize()
+    text_bytes = sum(t.numel() for t in texts)
+    pairs_host = [(i, epsm.Plan(p, epsm.PLAN_HOST_ONLY)) for i, bt in enumerate(bts) for p in bt.patterns]
+    logical = sum(texts[i].numel() for i, _ in pairs_host)
+    log(f"{len(pairs_host)} pairs, {text_bytes / 2**30:.2f} GiB of text, {logical / 2**30:.1f} GiB logical")
+
+    # size with a count-only batch, then prepare the full batch (untimed)
+    b0 = epsm.Batch(texts, pairs_host, count_only=True)
+    b0.run()
+    total = int(b0.total.item())
+    counts = b0.counts[:len(pairs_host)].clone()
+    log(f"{total} positions in total")
+    out_b = torch.empty(max(total, 1), dtype=torch.int64, device="cuda")
+    batch = epsm.Batch(texts, pairs_host, out=out_b[:total] if total else None)
+    bp = epsm.BatchPlan(batch)
+    info = bp.info()
+    stream = torch.cuda.current_stream()
+    for _ in range(args.warmup):
+        bp.launch(stream)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record()
+    for _ in range(args.steps):
+        bp.launch(stream)
+    e1.record()
+    torch.cuda.synchronize()
+    batched_s = (time.perf_counter() - t0) / args.steps
+    batched_gpu_ms = e0.elapsed_time(e1) / args.steps
+    epsm.stream_check()
+    if not torch.equal(batch.counts[:len(pairs_host)], counts):
+        raise AssertionError("batched counts differ from the count-only batch")
+
+    # one-shot form (descriptors built and uploaded inside the call)
+    t0 = time.perf_counter()
+    batch.run()
+    torch.cuda.synchronize()
+    oneshot_s = time.perf_counter() - t0
+
+    # per-instance plain searches: one epsm_search per pair into its slice
+    log("creating device plans for the per-instance baseline")
+    dev_plans = {}
+    for _, p in pairs_host:
+        if id(p) not in dev_plans:
+            dev_plans[id(p)] = epsm.Plan(p.pattern)
+    out_p = torch.full((max(total, 1),), -1, dtype=torch.int64, device="cuda")
+    hits = torch.zeros(len(pairs_host), dtype=torch.int64, device="cuda")
+    offs = batch.offsets[:len(pairs_host)].cpu().tolist()
+    cnts = counts.cpu().tolist()
+    L = epsm.lib()
+    sh = stream.cuda_stream or None
+    base_out, base_hits = out_p.data_ptr(), hits.data_ptr()
+    calls = [(dev_plans[id(p)].handle, texts[i].data_ptr() if texts[i].numel() else None, texts[i].numel(),
+              base_out + 8 * offs[k] if cnts[k] else None, cnts[k], base_hits + 8 * k)
+             for k, (i, p) in enumerate(pairs_host)]
+    fn = L.epsm_search
+    torch.cuda.synchronize()
+    log(f"timing {len(calls)} per-instance searches")
+    t0 = time.perf_counter()
+    for c in calls:
+        st = fn(c[0], c[1], c[2], c[3], c[4], c[5], sh)
+        if st:
+            raise epsm.EpsmError(st, "epsm_search")
+    torch.cuda.synchronize()
+    plain_s = time.perf_counter() - t0
+    epsm.stream_check()
+    identical = bool(torch.equal(out_p[:total], out_b[:total])) and bool(torch.equal(hits, counts))
+    if not identical:
+        raise AssertionError("batched output differs from the per-instance searches")
+    config = {"workload": f"batch: {len(bts)} texts log-uniform [1 KiB, 16 MiB], sigma 4|64, "
+                          "1-64 patterns per text, m uniform [1,32], half cut / half random",
+              "texts": len(bts), "pairs": len(pairs_host), "text_bytes": text_bytes,
+              "logical_bytes": logical, "positions": total, "batch_units": info["units"],
+              "batch_entries": info["entries"], "batch_tile_bytes": info["tile_bytes"]}
+    extra = {"batched_ms": round(batched_s * 1e3, 3), "batched_gpu_ms": round(batched_gpu_ms, 3),
+             "oneshot_ms": round(oneshot_s * 1e3, 3), "plain_ms": round(plain_s * 1e3, 3),
+             "speedup_vs_plain": round(plain_s / batched_s, 2),
+             "plain_gbs": round(logical / plain_s / 1e9, 1), "identical_output": identical}
+    return logical, batched_s, config, extra
 
 
 def cpu_baseline(torch, texts, cases, seconds: float, threads: int):
@@ -163,6 +256,17 @@ def main():
     import workloads as W
 
     torch.cuda.set_device(0)
+    if args.workload == "batch":
+        logical, step_s, config, extra = run_batch_workload(args, torch, W, epsm)
+        result = {
+            "metric": METRIC, "value": round(logical / step_s / 1e9, 1), "unit": "GB/s",
+            "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+            "ms_per_step": round(step_s * 1e3, 3), "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": "u8", "data": "synthetic", "config": config,
+            "batch": extra, "roofline": None, "cpu_baseline": None,
+        }
+        print(json.dumps(result), flush=True)
+        return
     build = build_sweep1g if args.workload == "sweep1g" else build_zipf4g
     texts, specs, cases, config = build(torch, W, epsm)
     torch.cuda.synchronize()

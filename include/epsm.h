@@ -166,8 +166,10 @@ typedef struct {
  * entries at or beyond out_capacity are not written (counts and offsets are
  * always complete).  With EPSM_BATCH_COUNT_ONLY only counts, offsets and
  * total are produced.  Output is identical to calling epsm_search per pair.
- * All plans must live on the current device.  The host arrays are read
- * before the call returns.
+ * Device plans must live on the current device.  The host arrays are read
+ * before the call returns.  Plans may be host-only (EPSM_PLAN_HOST_ONLY): the
+ * batch then carries their tables to the device itself, which avoids one
+ * device allocation and copy per plan.
  */
 epsm_status epsm_search_batch(const epsm_batch *batch, void *stream);
 

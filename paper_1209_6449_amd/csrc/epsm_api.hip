@@ -25,8 +25,7 @@ struct epsm_plan_s {
     DevPlan dev{};                // pointers filled for device plans
     uint32_t flags = 0;
     int device = -1;
-    uint8_t *d_pattern = nullptr;
-    uint16_t *d_table = nullptr;
+    uint8_t *d_pattern = nullptr;  // device block: pattern, then table
 };
 
 // Where a batch writes its results.
@@ -197,17 +196,23 @@ struct HostBatch {
     std::vector<BatchPairDesc> pairs;
     std::vector<uint32_t> order;
     std::vector<BatchUnit> units;
+    // device data of host-only plans (fingerprint tables, long patterns),
+    // uploaded with the descriptors; per pair the blob offsets (or kNoBlob)
+    std::vector<uint8_t> blob;
+    std::vector<uint64_t> blob_table, blob_pattern;
     uint64_t entries = 0;
     int waves = 8;
 };
+constexpr uint64_t kNoBlob = ~uint64_t(0);
 
 // Byte layout of the device copy of a batch: descriptors, then the
 // (pair, tile) counts, their offsets and the scan's block sums.
 struct BatchLayout {
-    size_t texts, pairs, order, units, ptc, pto, bsum, total;
+    size_t blob, texts, pairs, order, units, ptc, pto, bsum, total;
     explicit BatchLayout(const HostBatch &hb) {
         auto up = [](size_t x) { return (x + 255) & ~size_t(255); };
         size_t at = 0;
+        blob = at; at += up(hb.blob.size());
         texts = at; at += up(hb.texts.size() * sizeof(BatchTextDesc));
         pairs = at; at += up(hb.pairs.size() * sizeof(BatchPairDesc));
         order = at; at += up(hb.order.size() * sizeof(uint32_t));
@@ -269,8 +274,9 @@ epsm_status build_batch(const epsm_batch *b, int waves, HostBatch &hb) {
     for (uint32_t k = 0; k < b->n_pairs; ++k) {
         const epsm_pair_ref &pr = b->pairs[k];
         if (pr.text >= b->n_texts) return fail(EPSM_EINVAL, "pair refers to a text out of range");
-        epsm_status st = check_plan(pr.plan);
-        if (st != EPSM_OK) return st;
+        if (!pr.plan) return fail(EPSM_EINVAL, "pair has a NULL plan");
+        if (pr.plan->device >= 0 && pr.plan->device != dev)
+            return fail(EPSM_EINVAL, "plan belongs to another device");
         BatchPairDesc &d = hb.pairs[k];
         d.plan = pr.plan->dev;
         d.text = pr.text;
@@ -280,6 +286,33 @@ epsm_status build_batch(const epsm_batch *b, int waves, HostBatch &hb) {
         if (d.tiles) text_pairs[pr.text]++;
     }
     hb.entries = entries;
+    // host-only plans: their table and (for the tail check) pattern travel
+    // in the batch's own device buffer, one copy per distinct plan
+    hb.blob_table.assign(b->n_pairs, kNoBlob);
+    hb.blob_pattern.assign(b->n_pairs, kNoBlob);
+    std::map<epsm_plan_t, std::pair<uint64_t, uint64_t>> placed;
+    for (uint32_t k = 0; k < b->n_pairs; ++k) {
+        epsm_plan_t pl = b->pairs[k].plan;
+        if (pl->device >= 0 || !hb.pairs[k].tiles) continue;
+        auto it = placed.find(pl);
+        if (it == placed.end()) {
+            uint64_t tab = kNoBlob, pat = kNoBlob;
+            if (!pl->table.empty()) {
+                tab = hb.blob.size();
+                const uint8_t *src = (const uint8_t *)pl->table.data();
+                hb.blob.insert(hb.blob.end(), src, src + pl->table.size() * sizeof(uint16_t));
+                hb.blob.resize((hb.blob.size() + 15) & ~size_t(15), 0);
+            }
+            if (pl->dev.m > 4u * pl->dev.nw) {
+                pat = hb.blob.size();
+                hb.blob.insert(hb.blob.end(), pl->pattern.begin(), pl->pattern.end());
+                hb.blob.resize((hb.blob.size() + 15) & ~size_t(15), 0);
+            }
+            it = placed.emplace(pl, std::make_pair(tab, pat)).first;
+        }
+        hb.blob_table[k] = it->second.first;
+        hb.blob_pattern[k] = it->second.second;
+    }
     // pairs grouped by text (pair order kept within a text)
     std::vector<uint32_t> start(b->n_texts + 1, 0);
     for (uint32_t i = 0; i < b->n_texts; ++i) start[i + 1] = start[i] + text_pairs[i];
@@ -301,12 +334,19 @@ epsm_status build_batch(const epsm_batch *b, int waves, HostBatch &hb) {
     return EPSM_OK;
 }
 
-epsm_status upload_batch(const HostBatch &hb, const BatchLayout &L, uint8_t *dev, hipStream_t s) {
+epsm_status upload_batch(HostBatch &hb, const BatchLayout &L, uint8_t *dev, hipStream_t s) {
     const BatchPtrs P = batch_ptrs(dev, L);
+    for (size_t k = 0; k < hb.pairs.size(); ++k) {  // point host-only plans at the blob copy
+        if (hb.blob_table[k] != kNoBlob)
+            hb.pairs[k].plan.table = (const uint16_t *)(dev + L.blob + hb.blob_table[k]);
+        if (hb.blob_pattern[k] != kNoBlob)
+            hb.pairs[k].plan.pattern = dev + L.blob + hb.blob_pattern[k];
+    }
     hipError_t e = hipSuccess;
     auto put = [&](void *dst, const void *src, size_t bytes) {
         if (e == hipSuccess && bytes) e = hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, s);
     };
+    put(dev + L.blob, hb.blob.data(), hb.blob.size());
     put(P.texts, hb.texts.data(), hb.texts.size() * sizeof(BatchTextDesc));
     put(P.pairs, hb.pairs.data(), hb.pairs.size() * sizeof(BatchPairDesc));
     put(P.order, hb.order.data(), hb.order.size() * sizeof(uint32_t));
@@ -420,23 +460,22 @@ epsm_status epsm_plan(const uint8_t *pattern, uint64_t m, uint32_t flags, epsm_p
             delete p;
             return hip_fail(e, "hipGetDevice");
         }
+        // one device block: [pattern, zero padded to 16 bytes][table]
         const size_t pat_bytes = (m + 15) & ~uint64_t(15);
-        e = hipMalloc(&p->d_pattern, pat_bytes);
-        if (e == hipSuccess) e = hipMemset(p->d_pattern, 0, pat_bytes);
-        if (e == hipSuccess) e = hipMemcpy(p->d_pattern, pattern, m, hipMemcpyHostToDevice);
-        if (e == hipSuccess && fingerprint) {
-            e = hipMalloc(&p->d_table, p->table.size() * sizeof(uint16_t));
-            if (e == hipSuccess)
-                e = hipMemcpy(p->d_table, p->table.data(), p->table.size() * sizeof(uint16_t),
-                              hipMemcpyHostToDevice);
-        }
+        const size_t tab_bytes = p->table.size() * sizeof(uint16_t);
+        std::vector<uint8_t> staging(pat_bytes + tab_bytes, 0);
+        std::memcpy(staging.data(), pattern, m);
+        if (tab_bytes) std::memcpy(staging.data() + pat_bytes, p->table.data(), tab_bytes);
+        e = hipMalloc(&p->d_pattern, staging.size());
+        if (e == hipSuccess)
+            e = hipMemcpy(p->d_pattern, staging.data(), staging.size(), hipMemcpyHostToDevice);
         if (e != hipSuccess) {
-            epsm_status s = hip_fail(e, "plan device copy");
+            epsm_status st = hip_fail(e, "plan device copy");
             epsm_plan_destroy(p);
-            return s;
+            return st;
         }
         d.pattern = p->d_pattern;
-        d.table = p->d_table;
+        d.table = tab_bytes ? (const uint16_t *)(p->d_pattern + pat_bytes) : nullptr;
     }
     *out = p;
     return EPSM_OK;
@@ -445,7 +484,6 @@ epsm_status epsm_plan(const uint8_t *pattern, uint64_t m, uint32_t flags, epsm_p
 void epsm_plan_destroy(epsm_plan_t plan) {
     if (!plan) return;
     if (plan->d_pattern) (void)hipFree(plan->d_pattern);
-    if (plan->d_table) (void)hipFree(plan->d_table);
     delete plan;
 }
 
@@ -527,6 +565,8 @@ epsm_status epsm_batch_prepare(const epsm_batch *batch, epsm_batch_plan_t *out) 
     bp->hb.texts.shrink_to_fit();
     bp->hb.order.clear();
     bp->hb.order.shrink_to_fit();
+    bp->hb.blob.clear();
+    bp->hb.blob.shrink_to_fit();
     bp->hb.units.shrink_to_fit();
     *out = bp;
     return EPSM_OK;

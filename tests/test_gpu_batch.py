@@ -158,3 +158,42 @@ def test_empty_batch(epsm):
     b = epsm.Batch([], [], count_only=False)
     b.run()
     assert int(b.total.item()) == 0
+
+
+def test_host_only_and_mixed_plans(epsm):
+    """Host-only plans travel inside the batch; output is unchanged."""
+    texts, host, pairs = make_batch(seed=21, n_texts=30)
+    mixed = []
+    for k, (ti, p) in enumerate(pairs):
+        flags = epsm.PLAN_HOST_ONLY if k % 3 else 0
+        if k % 5 == 0 and len(p) >= 15:
+            flags |= epsm.PLAN_FORCE_FINGERPRINT
+        if k % 11 == 0 and len(p) >= 15:
+            flags |= epsm.PLAN_FORCE_FINGERPRINT | epsm.PLAN_COLLIDE
+        mixed.append((ti, epsm.Plan(p, flags)))
+    # the same plan object in several pairs is uploaded once
+    mixed += [mixed[0], mixed[1], mixed[0]]
+    say(f"mixed host/device plans pairs={len(mixed)}")
+    pos, counts, offsets = epsm.search_batch(texts, mixed)
+    pos, counts, offsets = pos.cpu().numpy(), counts.cpu().numpy(), offsets.cpu().numpy()
+    for k, (ti, plan) in enumerate(mixed):
+        exp = oracle.positions(host[ti], plan.pattern)
+        assert np.array_equal(pos[offsets[k]:offsets[k] + counts[k]], exp), k
+
+
+def test_long_patterns_in_batch(epsm):
+    """m > 32 needs the tail check against the pattern in device memory."""
+    rng = np.random.default_rng(77)
+    t = rng.integers(0, 2, 200_000).astype(np.uint8)
+    text = torch.from_numpy(t).cuda()
+    pats = []
+    for m in (33, 40, 64, 100, 300):
+        o = int(rng.integers(0, t.size - m))
+        pats.append(t[o:o + m].tobytes())
+        pats.append((b"\x00\x01" * 200)[:m])
+    plans = [(0, epsm.Plan(p, epsm.PLAN_HOST_ONLY if i % 2 else 0)) for i, p in enumerate(pats)]
+    say("long patterns in batch")
+    pos, counts, offsets = epsm.search_batch([text], plans)
+    pos, counts, offsets = pos.cpu().numpy(), counts.cpu().numpy(), offsets.cpu().numpy()
+    for k, (ti, plan) in enumerate(plans):
+        assert np.array_equal(pos[offsets[k]:offsets[k] + counts[k]], oracle.positions(t, plan.pattern)), k
