@@ -207,6 +207,73 @@ epsm_status epsm_batch_get_info(epsm_batch_plan_t bp, uint64_t *units, uint64_t 
  * batch calls.  Output never depends on the choice. */
 epsm_status epsm_set_batch_config(uint32_t waves);
 
+/* ---- serving: continuous batching over resident texts ------------------- */
+
+/*
+ * A server keeps texts resident in device memory (the caller owns them and
+ * keeps them alive) and answers queries: a text id plus a set of patterns,
+ * every occurrence of every pattern as in epsm_search.  A scheduler thread
+ * forms micro-batches from the queue of submitted queries as stream slots
+ * and device memory free up, so queries that arrive while others are on the
+ * device are admitted and run concurrently with them (continuous batching).
+ * Device memory for a micro-batch's work and output is admitted against
+ * hbm_budget; a query never fails for lack of budget: it waits, and work
+ * larger than the whole budget runs when nothing else holds device memory.
+ * Results are identical to searching each pattern alone.
+ */
+typedef struct epsm_server_s *epsm_server_t;
+
+typedef struct {
+    uint32_t slots;              /* micro-batches in flight, one HIP stream each (0 = 4, max 16) */
+    uint32_t max_batch_queries;  /* queries per micro-batch (0 = 64) */
+    uint64_t max_batch_entries;  /* (pattern, text tile) entries per micro-batch (0 = 2^25) */
+    uint64_t hbm_budget;         /* device bytes for micro-batch work and outputs (0 = 16 GiB) */
+    uint32_t flags;              /* reserved, must be 0 */
+} epsm_server_config;
+
+typedef struct {
+    uint64_t query_id;
+    uint32_t text_id;
+    uint32_t n_patterns;
+    int32_t status;              /* epsm_status of the query */
+    uint32_t batch_queries;      /* queries that shared its micro-batch */
+    uint64_t total;              /* positions over all its patterns */
+    const uint64_t *counts;      /* host [n_patterns] */
+    const uint64_t *offsets;     /* host [n_patterns]: pattern k's positions start here */
+    const int64_t *positions;    /* host [total], ascending within each pattern */
+    double submit_time;          /* server clock (seconds since creation) */
+    double start_time;           /* its micro-batch was formed */
+    double done_time;            /* its results were in host memory */
+} epsm_query_result;
+
+typedef struct {
+    uint64_t submitted, completed, in_flight, queued, batches;
+    uint64_t bytes_reserved, bytes_peak;  /* admitted device memory now / at most */
+} epsm_server_stats;
+
+/* Create a server on the current device (cfg may be NULL for defaults). */
+epsm_status epsm_server_create(const epsm_server_config *cfg, epsm_server_t *out);
+/* Register a resident text (device pointer, any alignment); returns its id. */
+epsm_status epsm_server_add_text(epsm_server_t s, const uint8_t *d_text, uint64_t n,
+                                 uint32_t *text_id);
+/* Queue a query: n_patterns patterns given back to back in host memory
+ * (copied), lengths[k] bytes each.  Thread safe; returns immediately. */
+epsm_status epsm_server_submit(epsm_server_t s, uint32_t text_id, const uint8_t *patterns,
+                               const uint64_t *lengths, uint32_t n_patterns, uint64_t *query_id);
+/* Take up to max completed queries (in completion order), waiting up to
+ * wait_us microseconds for the first one.  The result arrays stay valid
+ * until epsm_server_release(query_id). */
+epsm_status epsm_server_poll(epsm_server_t s, epsm_query_result *out, uint32_t max,
+                             uint32_t *n_out, uint32_t wait_us);
+/* Free a completed query's results. */
+epsm_status epsm_server_release(epsm_server_t s, uint64_t query_id);
+/* Server clock in seconds (the time base of the result timestamps). */
+double epsm_server_now(epsm_server_t s);
+epsm_status epsm_server_get_stats(epsm_server_t s, epsm_server_stats *st);
+/* Stop the scheduler, wait for in-flight work and free the server; queries
+ * not yet started complete with EPSM_EDEVICE. */
+void epsm_server_destroy(epsm_server_t s);
+
 /* ---- workspace and diagnostics -------------------------------------------- */
 
 /* Make sure the workspace tied to `stream` can serve texts of up to max_n

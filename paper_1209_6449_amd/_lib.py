@@ -66,6 +66,39 @@ class Batch(ctypes.Structure):
     ]
 
 
+class ServerConfig(ctypes.Structure):
+    _fields_ = [
+        ("slots", ctypes.c_uint32),
+        ("max_batch_queries", ctypes.c_uint32),
+        ("max_batch_entries", ctypes.c_uint64),
+        ("hbm_budget", ctypes.c_uint64),
+        ("flags", ctypes.c_uint32),
+    ]
+
+
+class QueryResult(ctypes.Structure):
+    _fields_ = [
+        ("query_id", ctypes.c_uint64),
+        ("text_id", ctypes.c_uint32),
+        ("n_patterns", ctypes.c_uint32),
+        ("status", ctypes.c_int32),
+        ("batch_queries", ctypes.c_uint32),
+        ("total", ctypes.c_uint64),
+        ("counts", ctypes.POINTER(ctypes.c_uint64)),
+        ("offsets", ctypes.POINTER(ctypes.c_uint64)),
+        ("positions", ctypes.POINTER(ctypes.c_int64)),
+        ("submit_time", ctypes.c_double),
+        ("start_time", ctypes.c_double),
+        ("done_time", ctypes.c_double),
+    ]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_uint64) for k in
+                ("submitted", "completed", "in_flight", "queued", "batches", "bytes_reserved",
+                 "bytes_peak")]
+
+
 # name -> (restype, argtypes); every symbol include/epsm.h declares
 SIGNATURES = {
     "epsm_plan": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint32,
@@ -91,6 +124,18 @@ SIGNATURES = {
     "epsm_reserve": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint64]),
     "epsm_release": (None, []),
     "epsm_stream_check": (ctypes.c_int, [ctypes.c_void_p]),
+    "epsm_server_create": (ctypes.c_int, [ctypes.POINTER(ServerConfig), ctypes.POINTER(ctypes.c_void_p)]),
+    "epsm_server_add_text": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64,
+                                            ctypes.POINTER(ctypes.c_uint32)]),
+    "epsm_server_submit": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint32, ctypes.c_void_p,
+                                          ctypes.c_void_p, ctypes.c_uint32,
+                                          ctypes.POINTER(ctypes.c_uint64)]),
+    "epsm_server_poll": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(QueryResult), ctypes.c_uint32,
+                                        ctypes.POINTER(ctypes.c_uint32), ctypes.c_uint32]),
+    "epsm_server_release": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64]),
+    "epsm_server_now": (ctypes.c_double, [ctypes.c_void_p]),
+    "epsm_server_get_stats": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ServerStats)]),
+    "epsm_server_destroy": (None, [ctypes.c_void_p]),
     "epsm_last_error": (ctypes.c_char_p, []),
     "epsm_status_string": (ctypes.c_char_p, [ctypes.c_int]),
     "epsm_version": (ctypes.c_int, []),

@@ -12,33 +12,12 @@
 #include <string>
 #include <vector>
 
-#include "../../include/epsm.h"
-#include "epsm_internal.h"
+#include "epsm_host.h"
 
 using namespace epsm;
 
-struct epsm_batch_plan_s;
-
-struct epsm_plan_s {
-    std::vector<uint8_t> pattern;
-    std::vector<uint16_t> table;  // host copy, fingerprint only
-    DevPlan dev{};                // pointers filled for device plans
-    uint32_t flags = 0;
-    int device = -1;
-    uint8_t *d_pattern = nullptr;  // device block: pattern, then table
-};
-
-// Where a batch writes its results.
-struct epsm_batch_outputs {
-    int64_t *d_out;
-    uint64_t cap;
-    uint64_t *d_counts;
-    uint64_t *d_offsets;
-    uint64_t *d_total;
-    bool write;
-};
-
-namespace {
+namespace epsm {
+namespace host {
 
 thread_local std::string g_last_error;
 
@@ -191,68 +170,29 @@ epsm_status run_search(epsm_plan_t plan, const uint8_t *d_text, uint64_t n, int6
 
 int g_batch_waves = 8;  // batch tile = g_batch_waves KiB
 
-struct HostBatch {
-    std::vector<BatchTextDesc> texts;
-    std::vector<BatchPairDesc> pairs;
-    std::vector<uint32_t> order;
-    std::vector<BatchUnit> units;
-    // device data of host-only plans (fingerprint tables, long patterns),
-    // uploaded with the descriptors; per pair the blob offsets (or kNoBlob)
-    std::vector<uint8_t> blob;
-    std::vector<uint64_t> blob_table, blob_pattern;
-    uint64_t entries = 0;
-    int waves = 8;
-};
-constexpr uint64_t kNoBlob = ~uint64_t(0);
-
-// Byte layout of the device copy of a batch: descriptors, then the
-// (pair, tile) counts, their offsets and the scan's block sums.
-struct BatchLayout {
-    size_t blob, texts, pairs, order, units, ptc, pto, bsum, total;
-    explicit BatchLayout(const HostBatch &hb) {
-        auto up = [](size_t x) { return (x + 255) & ~size_t(255); };
-        size_t at = 0;
-        blob = at; at += up(hb.blob.size());
-        texts = at; at += up(hb.texts.size() * sizeof(BatchTextDesc));
-        pairs = at; at += up(hb.pairs.size() * sizeof(BatchPairDesc));
-        order = at; at += up(hb.order.size() * sizeof(uint32_t));
-        units = at; at += up(hb.units.size() * sizeof(BatchUnit));
-        ptc = at; at += up(hb.entries * sizeof(uint32_t));
-        pto = at; at += up((hb.entries + 1) * sizeof(uint64_t));
-        bsum = at; at += up(((hb.entries + kScanBlock - 1) / kScanBlock + 1) * sizeof(uint64_t));
-        total = at;
-    }
-};
-
-struct BatchPtrs {
-    BatchTextDesc *texts;
-    BatchPairDesc *pairs;
-    uint32_t *order;
-    BatchUnit *units;
-    uint32_t *ptc;
-    uint64_t *pto;
-    uint64_t *bsum;
-};
-
 BatchPtrs batch_ptrs(uint8_t *base, const BatchLayout &L) {
     return {(BatchTextDesc *)(base + L.texts), (BatchPairDesc *)(base + L.pairs),
             (uint32_t *)(base + L.order), (BatchUnit *)(base + L.units), (uint32_t *)(base + L.ptc),
             (uint64_t *)(base + L.pto), (uint64_t *)(base + L.bsum)};
 }
 
-epsm_status build_batch(const epsm_batch *b, int waves, HostBatch &hb) {
+epsm_status build_batch(const epsm_batch *b, int waves, HostBatch &hb, bool check_outputs) {
     if (!b) return fail(EPSM_EINVAL, "batch is NULL");
     if (b->flags & ~EPSM_BATCH_COUNT_ONLY) return fail(EPSM_EINVAL, "unknown batch flags");
     if (b->n_texts && !b->texts) return fail(EPSM_EINVAL, "texts is NULL");
     if (b->n_pairs && !b->pairs) return fail(EPSM_EINVAL, "pairs is NULL");
-    if (b->n_pairs && (!b->d_counts || !b->d_offsets))
-        return fail(EPSM_EINVAL, "d_counts and d_offsets are required");
-    const bool write = !(b->flags & EPSM_BATCH_COUNT_ONLY);
-    if (write && b->out_capacity && !b->d_out) return fail(EPSM_EINVAL, "d_out is NULL with out_capacity > 0");
+    if (check_outputs) {
+        if (b->n_pairs && (!b->d_counts || !b->d_offsets))
+            return fail(EPSM_EINVAL, "d_counts and d_offsets are required");
+        const bool write = !(b->flags & EPSM_BATCH_COUNT_ONLY);
+        if (write && b->out_capacity && !b->d_out)
+            return fail(EPSM_EINVAL, "d_out is NULL with out_capacity > 0");
+    }
     int dev = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
     const uint64_t tile_bytes = (uint64_t)waves * kWavePiece;
+    hb = HostBatch();  // callers may reuse a HostBatch: start from empty vectors
     hb.waves = waves;
     hb.texts.assign(b->n_texts, BatchTextDesc{});
     std::vector<uint32_t> text_tiles(b->n_texts, 0), text_pairs(b->n_texts, 0);
@@ -357,9 +297,29 @@ epsm_status upload_batch(HostBatch &hb, const BatchLayout &L, uint8_t *dev, hipS
     return e == hipSuccess ? EPSM_OK : hip_fail(e, "batch descriptor upload");
 }
 
-// The kernel sequence of one batch (stream ordered, no host round trip).
-epsm_status run_batch(const BatchPtrs &P, const HostBatch &hb, const epsm_batch_outputs &o,
-                      hipStream_t s) {
+// The kernel sequence of one batch (stream ordered, no host round trip):
+// count pass, scan, per-pair counts/offsets, then the write pass.
+epsm_status run_batch_count(const BatchPtrs &P, const HostBatch &hb, const epsm_batch_outputs &o,
+                            hipStream_t s) {
+    BatchArgs a{};
+    a.texts = P.texts;
+    a.pairs = P.pairs;
+    a.pair_order = P.order;
+    a.units = P.units;
+    a.pt_count = P.ptc;
+    a.pt_offset = P.pto;
+    a.write = 0;
+    hipError_t e = launch_batch(a, hb.waves, (uint32_t)hb.units.size(), s);
+    if (e == hipSuccess) e = launch_scan_counts(P.ptc, hb.entries, P.pto, P.bsum, s);
+    if (e == hipSuccess)
+        e = launch_batch_finalize(P.pairs, (uint32_t)hb.pairs.size(), P.pto, hb.entries, o.d_counts,
+                                  o.d_offsets, o.d_total, s);
+    return e == hipSuccess ? EPSM_OK : hip_fail(e, "batch launch (count)");
+}
+
+epsm_status run_batch_write(const BatchPtrs &P, const HostBatch &hb, const epsm_batch_outputs &o,
+                            hipStream_t s) {
+    if (!o.write || !o.cap) return EPSM_OK;
     BatchArgs a{};
     a.texts = P.texts;
     a.pairs = P.pairs;
@@ -369,21 +329,23 @@ epsm_status run_batch(const BatchPtrs &P, const HostBatch &hb, const epsm_batch_
     a.pt_offset = P.pto;
     a.out = o.d_out;
     a.cap = o.cap;
-    const uint32_t n_units = (uint32_t)hb.units.size();
-    a.write = 0;
-    hipError_t e = launch_batch(a, hb.waves, n_units, s);
-    if (e == hipSuccess) e = launch_scan_counts(P.ptc, hb.entries, P.pto, P.bsum, s);
-    if (e == hipSuccess)
-        e = launch_batch_finalize(P.pairs, (uint32_t)hb.pairs.size(), P.pto, hb.entries, o.d_counts,
-                                  o.d_offsets, o.d_total, s);
-    if (e == hipSuccess && o.write && o.cap) {
-        a.write = 1;
-        e = launch_batch(a, hb.waves, n_units, s);
-    }
-    return e == hipSuccess ? EPSM_OK : hip_fail(e, "batch launch");
+    a.write = 1;
+    hipError_t e = launch_batch(a, hb.waves, (uint32_t)hb.units.size(), s);
+    return e == hipSuccess ? EPSM_OK : hip_fail(e, "batch launch (write)");
 }
 
-}  // namespace
+epsm_status run_batch(const BatchPtrs &P, const HostBatch &hb, const epsm_batch_outputs &o,
+                      hipStream_t s) {
+    epsm_status st = run_batch_count(P, hb, o, s);
+    return st == EPSM_OK ? run_batch_write(P, hb, o, s) : st;
+}
+
+int batch_waves() { return g_batch_waves; }
+
+}  // namespace host
+}  // namespace epsm
+
+using namespace epsm::host;
 
 struct epsm_batch_plan_s {
     HostBatch hb;               // sizes; units kept only for their count
@@ -520,7 +482,7 @@ epsm_status epsm_count(epsm_plan_t plan, const uint8_t *d_text, uint64_t n, uint
 epsm_status epsm_search_batch(const epsm_batch *batch, void *stream) {
     g_last_error.clear();
     HostBatch hb;
-    epsm_status st = build_batch(batch, g_batch_waves, hb);
+    epsm_status st = build_batch(batch, g_batch_waves, hb, true);
     if (st != EPSM_OK) return st;
     const BatchLayout L(hb);
     uint8_t *ws = nullptr;
@@ -539,7 +501,7 @@ epsm_status epsm_batch_prepare(const epsm_batch *batch, epsm_batch_plan_t *out) 
     *out = nullptr;
     epsm_batch_plan_s *bp = new (std::nothrow) epsm_batch_plan_s();
     if (!bp) return fail(EPSM_ENOMEM, "batch plan allocation");
-    epsm_status st = build_batch(batch, g_batch_waves, bp->hb);
+    epsm_status st = build_batch(batch, g_batch_waves, bp->hb, true);
     if (st != EPSM_OK) {
         delete bp;
         return st;

@@ -1,0 +1,97 @@
+// Host-side internals of the library shared by its translation units (the
+// C ABI in epsm_api.hip and the serving engine in epsm_serve.hip).
+#pragma once
+
+#include <map>
+#include <string>
+#include <vector>
+
+#include "../../include/epsm.h"
+#include "epsm_internal.h"
+
+struct epsm_plan_s {
+    std::vector<uint8_t> pattern;
+    std::vector<uint16_t> table;  // host copy, fingerprint only
+    epsm::DevPlan dev{};          // pointers filled for device plans
+    uint32_t flags = 0;
+    int device = -1;
+    uint8_t *d_pattern = nullptr;  // device block: pattern, then table
+};
+
+// Where a batch writes its results.
+struct epsm_batch_outputs {
+    int64_t *d_out;
+    uint64_t cap;
+    uint64_t *d_counts;
+    uint64_t *d_offsets;
+    uint64_t *d_total;
+    bool write;
+};
+
+
+namespace epsm {
+namespace host {
+
+epsm_status fail(epsm_status s, const std::string &msg);
+epsm_status hip_fail(hipError_t e, const char *what);
+epsm_status check_plan(epsm_plan_t plan);
+
+struct HostBatch {
+    std::vector<BatchTextDesc> texts;
+    std::vector<BatchPairDesc> pairs;
+    std::vector<uint32_t> order;
+    std::vector<BatchUnit> units;
+    // device data of host-only plans (fingerprint tables, long patterns),
+    // uploaded with the descriptors; per pair the blob offsets (or kNoBlob)
+    std::vector<uint8_t> blob;
+    std::vector<uint64_t> blob_table, blob_pattern;
+    uint64_t entries = 0;
+    int waves = 8;
+};
+constexpr uint64_t kNoBlob = ~uint64_t(0);
+
+// Byte layout of the device copy of a batch: descriptors, then the
+// (pair, tile) counts, their offsets and the scan's block sums.
+struct BatchLayout {
+    size_t blob, texts, pairs, order, units, ptc, pto, bsum, total;
+    explicit BatchLayout(const HostBatch &hb) {
+        auto up = [](size_t x) { return (x + 255) & ~size_t(255); };
+        size_t at = 0;
+        blob = at; at += up(hb.blob.size());
+        texts = at; at += up(hb.texts.size() * sizeof(BatchTextDesc));
+        pairs = at; at += up(hb.pairs.size() * sizeof(BatchPairDesc));
+        order = at; at += up(hb.order.size() * sizeof(uint32_t));
+        units = at; at += up(hb.units.size() * sizeof(BatchUnit));
+        ptc = at; at += up(hb.entries * sizeof(uint32_t));
+        pto = at; at += up((hb.entries + 1) * sizeof(uint64_t));
+        bsum = at; at += up(((hb.entries + kScanBlock - 1) / kScanBlock + 1) * sizeof(uint64_t));
+        total = at;
+    }
+};
+
+struct BatchPtrs {
+    BatchTextDesc *texts;
+    BatchPairDesc *pairs;
+    uint32_t *order;
+    BatchUnit *units;
+    uint32_t *ptc;
+    uint64_t *pto;
+    uint64_t *bsum;
+};
+
+BatchPtrs batch_ptrs(uint8_t *base, const BatchLayout &L);
+// Validate a batch and build its work descriptors (check_outputs: require
+// the output pointers of the epsm_batch).
+epsm_status build_batch(const epsm_batch *b, int waves, HostBatch &hb, bool check_outputs);
+// Copy descriptors (and host-only plan data) to `dev`; synchronises `s`.
+epsm_status upload_batch(HostBatch &hb, const BatchLayout &L, uint8_t *dev, hipStream_t s);
+epsm_status run_batch_count(const BatchPtrs &P, const HostBatch &hb, const epsm_batch_outputs &o,
+                            hipStream_t s);
+epsm_status run_batch_write(const BatchPtrs &P, const HostBatch &hb, const epsm_batch_outputs &o,
+                            hipStream_t s);
+epsm_status run_batch(const BatchPtrs &P, const HostBatch &hb, const epsm_batch_outputs &o,
+                      hipStream_t s);
+int batch_waves();
+
+}  // namespace host
+}  // namespace epsm

@@ -130,3 +130,25 @@ def test_host_only_plan_is_rejected_by_search():
     st = L.epsm_search(plan.handle, ctypes.addressof(dummy), 8, None, 0, ctypes.addressof(dummy), None)
     assert st == _lib.EPSM_EINVAL
     assert b"host-only" in L.epsm_last_error()
+
+
+def test_server_null_arguments():
+    L = epsm.lib()
+    out = ctypes.c_void_p()
+    assert L.epsm_server_create(None, None) == _lib.EPSM_EINVAL
+    assert L.epsm_server_add_text(None, None, 0, None) == _lib.EPSM_EINVAL
+    assert L.epsm_server_submit(None, 0, None, None, 0, None) == _lib.EPSM_EINVAL
+    n = ctypes.c_uint32()
+    assert L.epsm_server_poll(None, None, 0, ctypes.byref(n), 0) == _lib.EPSM_EINVAL
+    assert L.epsm_server_release(None, 1) == _lib.EPSM_EINVAL
+    assert L.epsm_server_get_stats(None, None) == _lib.EPSM_EINVAL
+    assert L.epsm_server_now(None) == 0.0
+    L.epsm_server_destroy(None)
+
+
+def test_batch_plan_null_arguments():
+    L = epsm.lib()
+    assert L.epsm_batch_prepare(None, None) == _lib.EPSM_EINVAL
+    assert L.epsm_batch_launch(None, None) == _lib.EPSM_EINVAL
+    assert L.epsm_batch_get_info(None, None, None, None) == _lib.EPSM_EINVAL
+    L.epsm_batch_destroy(None)
