@@ -43,7 +43,8 @@ sys.path.insert(0, ROOT)
 
 METRIC = "text GB/s scanned & fraction of HBM peak, batched vs plain; p99 query latency"
 HBM_PEAK_GBS = 8000.0
-KERNEL_SOURCES = ["paper_1209_6449_amd/csrc/epsm_kernels.hip", "paper_1209_6449_amd/csrc/epsm_internal.h"]
+KERNEL_SOURCES = ["paper_1209_6449_amd/csrc/epsm_kernels.hip", "paper_1209_6449_amd/csrc/epsm_device.h",
+                  "paper_1209_6449_amd/csrc/epsm_internal.h"]
 
 
 def kernel_hash() -> str:
@@ -70,6 +71,9 @@ def parse_args():
                     help="CPU time budget of the oracle baseline (0 disables it)")
     ap.add_argument("--threads", type=int, default=0, help="oracle threads (0 = all host cores)")
     ap.add_argument("--detail", action="store_true", help="per-search timings on stderr")
+    ap.add_argument("--positions-only", action="store_true",
+                    help="profiling aid: only the positions-mode searches, outputs sized to n "
+                         "(no count pass), so every scan dispatch is a positions-mode one")
     return ap.parse_args()
 
 
@@ -340,10 +344,16 @@ def main():
     # size outputs with a count pass (untimed)
     hits = torch.zeros(1, dtype=torch.int64, device="cuda")
     max_hits = 1
-    for c in cases:
-        epsm.count_into(c.plan, texts[c.text_idx], hits)
-        c.count = int(hits.item())
-        max_hits = max(max_hits, c.count)
+    if args.positions_only:
+        cases = [c for c in cases if c.mode == "positions"]
+        for c in cases:
+            c.count = texts[c.text_idx].numel()  # capacity bound; counts come from the searches
+        max_hits = max(c.count for c in cases)
+    else:
+        for c in cases:
+            epsm.count_into(c.plan, texts[c.text_idx], hits)
+            c.count = int(hits.item())
+            max_hits = max(max_hits, c.count)
     log(f"{len(cases)} searches, largest output {max_hits} positions")
     out = torch.empty(max_hits, dtype=torch.int64, device="cuda")
     step_bytes = sum(texts[c.text_idx].numel() for c in cases)
@@ -378,8 +388,12 @@ def main():
     elapsed = t1 - t0
 
     # spot-check the last positions search against its count
-    if int(hits.item()) != cases[-1].count:
+    if not args.positions_only and int(hits.item()) != cases[-1].count:
         raise AssertionError("count mismatch after timing")
+    if args.positions_only:
+        print(json.dumps({"positions_only": True, "dispatches_per_step": len(cases),
+                          "text_bytes_per_step": step_bytes}), flush=True)
+        return
 
     pos_ms = sum(e0.elapsed_time(e1) for e0, e1 in events)
     if args.detail:

@@ -1,0 +1,163 @@
+"""Summaries of rocprofv3 runs for the profiles/ directory.
+
+    # a device copy of known size, to calibrate FETCH_SIZE / WRITE_SIZE
+    python -m paper_1209_6449_amd.rocprof_summary calibrate --bytes 1073741824
+    # kernel statistics of a --kernel-trace --stats run
+    python -m paper_1209_6449_amd.rocprof_summary stats DIR --command "..." --out FILE
+    # HBM traffic per dispatch of a kernel from two --pmc runs (FETCH_SIZE,
+    # WRITE_SIZE), scaled by the same counters on the calibration copy
+    python -m paper_1209_6449_amd.rocprof_summary traffic --fetch DIR --write DIR \
+        --calib-fetch DIR --calib-write DIR --calib-bytes N --kernel scan_kernel \
+        --workload sweep1g --command "..." --out-json FILE --out-txt FILE
+"""
+from __future__ import annotations
+
+import argparse
+import csv
+import glob
+import hashlib
+import json
+import os
+import statistics
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+KERNEL_SOURCES = ["paper_1209_6449_amd/csrc/epsm_kernels.hip", "paper_1209_6449_amd/csrc/epsm_device.h",
+                  "paper_1209_6449_amd/csrc/epsm_internal.h"]
+
+
+def kernel_hash() -> str:
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def _find(directory: str, suffix: str) -> str:
+    hits = sorted(glob.glob(os.path.join(directory, "**", f"*{suffix}"), recursive=True))
+    if not hits:
+        raise FileNotFoundError(f"no *{suffix} under {directory}")
+    return hits[0]
+
+
+def counter_per_dispatch(directory: str, counter: str, kernel_sub: str) -> list[float]:
+    """Counter value of every dispatch whose kernel name contains kernel_sub."""
+    rows = csv.DictReader(open(_find(directory, "counter_collection.csv")))
+    vals = {}
+    for r in rows:
+        if r["Counter_Name"] != counter or kernel_sub not in r["Kernel_Name"]:
+            continue
+        d = r["Dispatch_Id"]
+        vals[d] = vals.get(d, 0.0) + float(r["Counter_Value"])
+    return [vals[k] for k in sorted(vals, key=int)]
+
+
+def cmd_calibrate(args):
+    import torch
+    n = args.bytes
+    src = torch.ones(n, dtype=torch.uint8, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(args.reps):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"calibration_copy_bytes": n, "reps": args.reps}), flush=True)
+
+
+def cmd_stats(args):
+    rows = list(csv.DictReader(open(_find(args.dir, "kernel_stats.csv"))))
+    lines = [f"# rocprofv3 kernel statistics", f"command: {args.command}", "",
+             f"{'calls':>7} {'avg_us':>10} {'total_ms':>10} {'pct':>6}  kernel"]
+    for r in sorted(rows, key=lambda r: -float(r["TotalDurationNs"])):
+        name = r["Name"]
+        if len(name) > 110:
+            name = name[:107] + "..."
+        lines.append(f"{int(r['Calls']):7d} {float(r['AverageNs']) / 1e3:10.2f} "
+                     f"{float(r['TotalDurationNs']) / 1e6:10.3f} {float(r['Percentage']):6.2f}  {name}")
+    if args.kernel:
+        sel = [r for r in rows if args.kernel in r["Name"]]
+        calls = sum(int(r["Calls"]) for r in sel)
+        total = sum(float(r["TotalDurationNs"]) for r in sel)
+        if calls:
+            lines += ["", f"all instances of {args.kernel}: {calls} calls, {total / 1e6:.3f} ms, "
+                          f"average {total / calls / 1e3:.2f} us per dispatch"]
+    text = "\n".join(lines) + "\n"
+    with open(args.out, "w") as f:
+        f.write(text)
+    print(text)
+
+
+def cmd_traffic(args):
+    # calibration: what each counter reads for a copy of calib_bytes (KiB units)
+    cf = counter_per_dispatch(args.calib_fetch, "FETCH_SIZE", args.calib_kernel)
+    cw = counter_per_dispatch(args.calib_write, "WRITE_SIZE", args.calib_kernel)
+    if not cf or not cw:
+        raise SystemExit("calibration dispatches not found")
+    fetch_factor = args.calib_bytes / (statistics.median(cf) * 1024.0)
+    write_factor = args.calib_bytes / (statistics.median(cw) * 1024.0)
+    f = counter_per_dispatch(args.fetch, "FETCH_SIZE", args.kernel)
+    w = counter_per_dispatch(args.write, "WRITE_SIZE", args.kernel)
+    if not f or not w or len(f) != len(w):
+        raise SystemExit(f"kernel dispatches not found or unequal ({len(f)} vs {len(w)})")
+    fetch_b = [x * 1024.0 * fetch_factor for x in f]
+    write_b = [x * 1024.0 * write_factor for x in w]
+    per = statistics.mean(a + b for a, b in zip(fetch_b, write_b))
+    out = {
+        "workload": args.workload,
+        "kernel": args.kernel,
+        "kernel_hash": kernel_hash(),
+        "dispatches": len(f),
+        "fetch_bytes_per_launch": round(statistics.mean(fetch_b)),
+        "write_bytes_per_launch": round(statistics.mean(write_b)),
+        "bytes_per_launch": round(per),
+        "calibration": {"copy_bytes": args.calib_bytes, "fetch_factor": round(fetch_factor, 4),
+                        "write_factor": round(write_factor, 4),
+                        "copy_fetch_kib": statistics.median(cf), "copy_write_kib": statistics.median(cw)},
+        "command": args.command,
+    }
+    with open(args.out_json, "w") as fh:
+        json.dump(out, fh, indent=1)
+    text = (f"# HBM traffic of {args.kernel} ({args.workload})\n"
+            f"command: {args.command}\n\n"
+            f"dispatches: {len(f)}\n"
+            f"FETCH_SIZE mean per dispatch: {statistics.mean(f):.0f} KiB raw -> "
+            f"{out['fetch_bytes_per_launch']} B after calibration\n"
+            f"WRITE_SIZE mean per dispatch: {statistics.mean(w):.0f} KiB raw -> "
+            f"{out['write_bytes_per_launch']} B after calibration\n"
+            f"traffic per dispatch: {out['bytes_per_launch']} B\n"
+            f"calibration: a {args.calib_bytes}-byte device copy reads FETCH_SIZE "
+            f"{statistics.median(cf):.0f} KiB and WRITE_SIZE {statistics.median(cw):.0f} KiB "
+            f"(factors {fetch_factor:.4f}, {write_factor:.4f})\n"
+            f"kernel source hash: {out['kernel_hash']}\n")
+    with open(args.out_txt, "w") as fh:
+        fh.write(text)
+    print(text)
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    c = sub.add_parser("calibrate")
+    c.add_argument("--bytes", type=int, default=1 << 30)
+    c.add_argument("--reps", type=int, default=3)
+    s = sub.add_parser("stats")
+    s.add_argument("dir")
+    s.add_argument("--command", required=True)
+    s.add_argument("--out", required=True)
+    s.add_argument("--kernel", default="", help="also aggregate all kernels whose name contains this")
+    t = sub.add_parser("traffic")
+    for k in ("fetch", "write", "calib_fetch", "calib_write"):
+        t.add_argument("--" + k.replace("_", "-"), dest=k, required=True)
+    t.add_argument("--calib-bytes", type=int, default=1 << 30)
+    t.add_argument("--calib-kernel", default="copy")
+    t.add_argument("--kernel", default="scan_kernel")
+    t.add_argument("--workload", default="sweep1g")
+    t.add_argument("--command", required=True)
+    t.add_argument("--out-json", required=True)
+    t.add_argument("--out-txt", required=True)
+    args = ap.parse_args(argv)
+    {"calibrate": cmd_calibrate, "stats": cmd_stats, "traffic": cmd_traffic}[args.cmd](args)
+
+
+if __name__ == "__main__":
+    main(sys.argv[1:])
