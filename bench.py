@@ -71,6 +71,9 @@ def parse_args():
                     help="CPU time budget of the oracle baseline (0 disables it)")
     ap.add_argument("--threads", type=int, default=0, help="oracle threads (0 = all host cores)")
     ap.add_argument("--detail", action="store_true", help="per-search timings on stderr")
+    ap.add_argument("--tuning", default="auto",
+                    help="'auto': the per-user or packaged autotune table of this device, if any; "
+                         "'none': built-in tiles; else a cache path")
     ap.add_argument("--positions-only", action="store_true",
                     help="profiling aid: only the positions-mode searches, outputs sized to n "
                          "(no count pass), so every scan dispatch is a positions-mode one")
@@ -299,6 +302,17 @@ def load_traffic(workload: str):
     return d
 
 
+def apply_tuning(choice: str, epsm) -> str:
+    from paper_1209_6449_amd import autotune
+    if choice == "none":
+        return "built-in tiles"
+    if choice == "auto":
+        path = autotune.apply_default(log)
+        return os.path.relpath(path, ROOT) if path else "built-in tiles"
+    autotune.apply(autotune.load(choice))
+    return choice
+
+
 def main():
     args = parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -313,6 +327,7 @@ def main():
     import workloads as W
 
     torch.cuda.set_device(0)
+    tuning = apply_tuning(args.tuning, epsm)
     if args.workload == "serve":
         points, stats, config = run_serve_workload(args, torch, W, epsm)
         top = points[-1]  # 0.8 x saturation
@@ -320,7 +335,7 @@ def main():
             "metric": METRIC, "value": top["gbs"], "unit": "GB/s", "n_gpus": 1, "steps": 1,
             "warmup": 0, "ms_per_step": round(top["wall_s"] * 1e3, 3), "higher_is_better": True,
             "scaling": "weak", "vs_baseline": None, "dtype": "u8", "data": "synthetic",
-            "config": config, "serve": {"points": points, "p50_ms": top["p50_ms"],
+            "config": dict(config, tuning=tuning), "serve": {"points": points, "p50_ms": top["p50_ms"],
                                         "p99_ms": top["p99_ms"], "server_stats": stats},
             "roofline": None, "cpu_baseline": None,
         }
@@ -332,7 +347,7 @@ def main():
             "metric": METRIC, "value": round(logical / step_s / 1e9, 1), "unit": "GB/s",
             "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
             "ms_per_step": round(step_s * 1e3, 3), "higher_is_better": True, "scaling": "weak",
-            "vs_baseline": None, "dtype": "u8", "data": "synthetic", "config": config,
+            "vs_baseline": None, "dtype": "u8", "data": "synthetic", "config": dict(config, tuning=tuning),
             "batch": extra, "roofline": None, "cpu_baseline": None,
         }
         print(json.dumps(result), flush=True)
@@ -433,7 +448,7 @@ def main():
         "vs_baseline": None,
         "dtype": "u8",
         "data": "synthetic",
-        "config": config,
+        "config": dict(config, tuning=tuning),
         "roofline": roofline,
     }
     if args.cpu_seconds > 0:

@@ -73,6 +73,12 @@ typedef struct epsm_plan_s *epsm_plan_t;
 #define EPSM_VARIANT_DIRECT 1u
 #define EPSM_VARIANT_FINGERPRINT 2u
 
+/* Kernel classes of single-text searches (the key of the tune table). */
+#define EPSM_CLASS_BYTES 0u        /* direct variant, m <= 3: byte compares */
+#define EPSM_CLASS_WORDS 1u        /* direct variant, m >= 4: packed-word compares */
+#define EPSM_CLASS_FINGERPRINT 2u  /* fingerprint variant (Section 3.4) */
+#define EPSM_N_CLASSES 3u
+
 /* Longest pattern this build accepts. */
 #define EPSM_MAX_M 4096u
 
@@ -104,6 +110,7 @@ typedef struct {
                                 bucket v; NULL for the direct variant.  Owned by
                                 the plan. */
     int32_t device;          /* HIP device of the device tables, -1 if host only */
+    uint32_t kernel_class;   /* EPSM_CLASS_* of the plan's scan kernel */
 } epsm_plan_info;
 
 /* Copy the plan's description to *info (host memory). */
@@ -181,6 +188,35 @@ epsm_status epsm_search_batch(const epsm_batch *batch, void *stream);
  * 4x16, 16x8, 16x16; others return EPSM_EUNSUPPORTED.  Process-wide; not thread safe
  * against concurrent searches.  Output never depends on the choice. */
 epsm_status epsm_set_tile_config(uint32_t waves, uint32_t pieces);
+
+/* The tile configurations built into the library, default first: writes up
+ * to `capacity` of them to waves[i] / pieces[i] (either may be NULL) and
+ * returns how many are built. */
+uint32_t epsm_tile_configs(uint32_t *waves, uint32_t *pieces, uint32_t capacity);
+
+/* One row of the tune table: searches of plans of class `kernel_class`, in
+ * mode `count_only` (0: epsm_search, 1: epsm_count), over texts of n <=
+ * n_max bytes use the tile waves x pieces. */
+typedef struct {
+    uint32_t kernel_class;   /* EPSM_CLASS_* */
+    uint32_t count_only;     /* 0 or 1 */
+    uint64_t n_max;          /* bytes */
+    uint32_t waves;          /* a built tile, see epsm_tile_configs */
+    uint32_t pieces;
+} epsm_tune_entry;
+
+/* Install the tune table (copied; at most 256 rows): a single-text search
+ * uses the first row, in array order, that matches its class, mode and
+ * length, and the tile of epsm_set_tile_config when none does.  count == 0
+ * clears the table.  EPSM_EINVAL for an unknown class or mode,
+ * EPSM_EUNSUPPORTED for a tile that is not built; the old table is kept on
+ * error.  Process-wide; output never depends on the table. */
+epsm_status epsm_set_tune_table(const epsm_tune_entry *entries, uint32_t count);
+
+/* Fingerprint width k (Section 3.4) for plans made later without
+ * EPSM_PLAN_HASH_BITS; 8 <= k <= 14, 0 restores the default 11.
+ * Process-wide; output never depends on k. */
+epsm_status epsm_set_default_hash_bits(uint32_t k);
 
 /*
  * Prepared batches, for callers that run the same batch structure many times

@@ -16,13 +16,14 @@ import ctypes
 import torch
 
 from . import _lib
-from ._lib import (BATCH_COUNT_ONLY, MAX_M, PLAN_COLLIDE, PLAN_FORCE_DIRECT,  # noqa: F401
-                   PLAN_FORCE_FINGERPRINT, PLAN_HASH_BITS, PLAN_HOST_ONLY, VARIANT_DIRECT,
-                   VARIANT_FINGERPRINT)
+from ._lib import (BATCH_COUNT_ONLY, CLASS_BYTES, CLASS_FINGERPRINT, CLASS_WORDS,  # noqa: F401
+                   MAX_M, N_CLASSES, PLAN_COLLIDE, PLAN_FORCE_DIRECT, PLAN_FORCE_FINGERPRINT,
+                   PLAN_HASH_BITS, PLAN_HOST_ONLY, VARIANT_DIRECT, VARIANT_FINGERPRINT)
 
 __all__ = ["EpsmError", "Plan", "search", "count", "search_into", "count_into", "reserve",
            "stream_check", "lib", "library_path", "Batch", "BatchPlan", "search_batch",
-           "set_tile_config", "set_batch_config"]
+           "set_tile_config", "set_batch_config", "tile_configs", "set_tune_table",
+           "set_default_hash_bits"]
 
 
 def lib():
@@ -84,7 +85,7 @@ class Plan:
         return {
             "m": inf.m, "variant": inf.variant, "flags": inf.flags, "hash_bits": inf.hash_bits,
             "prefix_words": inf.prefix_words, "words": list(inf.words), "masks": list(inf.masks),
-            "table": table, "device": inf.device,
+            "table": table, "device": inf.device, "kernel_class": inf.kernel_class,
         }
 
     def close(self) -> None:
@@ -262,6 +263,28 @@ def search_batch(texts, pairs, stream=None):
     b1.run(stream)
     n = len(pairs)
     return out[:total], b1.counts[:n], b1.offsets[:n]
+
+
+def tile_configs() -> list[tuple[int, int]]:
+    """Built (waves, pieces) tile configurations, default first."""
+    n = lib().epsm_tile_configs(None, None, 0)
+    w = (ctypes.c_uint32 * n)()
+    p = (ctypes.c_uint32 * n)()
+    lib().epsm_tile_configs(w, p, n)
+    return [(w[i], p[i]) for i in range(n)]
+
+
+def set_tune_table(entries) -> None:
+    """Install the tile table (epsm_set_tune_table): an iterable of
+    (kernel_class, count_only, n_max, waves, pieces); first match wins."""
+    rows = [tuple(int(x) for x in e) for e in entries]
+    arr = (_lib.TuneEntry * max(len(rows), 1))(*[_lib.TuneEntry(*r) for r in rows])
+    _check(lib().epsm_set_tune_table(arr, len(rows)), "epsm_set_tune_table")
+
+
+def set_default_hash_bits(k: int) -> None:
+    """Fingerprint width for plans made later without PLAN_HASH_BITS (0: 11)."""
+    _check(lib().epsm_set_default_hash_bits(k), "epsm_set_default_hash_bits")
 
 
 def set_batch_config(waves: int) -> None:

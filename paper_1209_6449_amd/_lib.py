@@ -25,6 +25,10 @@ def PLAN_HASH_BITS(k: int) -> int:
 
 VARIANT_DIRECT = 1
 VARIANT_FINGERPRINT = 2
+CLASS_BYTES = 0
+CLASS_WORDS = 1
+CLASS_FINGERPRINT = 2
+N_CLASSES = 3
 BATCH_COUNT_ONLY = 0x1
 MAX_M = 4096
 
@@ -40,7 +44,13 @@ class PlanInfo(ctypes.Structure):
         ("masks", ctypes.c_uint32 * 8),
         ("table", ctypes.POINTER(ctypes.c_uint16)),
         ("device", ctypes.c_int32),
+        ("kernel_class", ctypes.c_uint32),
     ]
+
+
+class TuneEntry(ctypes.Structure):
+    _fields_ = [("kernel_class", ctypes.c_uint32), ("count_only", ctypes.c_uint32),
+                ("n_max", ctypes.c_uint64), ("waves", ctypes.c_uint32), ("pieces", ctypes.c_uint32)]
 
 
 class TextRef(ctypes.Structure):
@@ -115,6 +125,10 @@ SIGNATURES = {
     "epsm_search_batch": (ctypes.c_int, [ctypes.POINTER(Batch), ctypes.c_void_p]),
     "epsm_set_tile_config": (ctypes.c_int, [ctypes.c_uint32, ctypes.c_uint32]),
     "epsm_set_batch_config": (ctypes.c_int, [ctypes.c_uint32]),
+    "epsm_tile_configs": (ctypes.c_uint32, [ctypes.POINTER(ctypes.c_uint32),
+                                            ctypes.POINTER(ctypes.c_uint32), ctypes.c_uint32]),
+    "epsm_set_tune_table": (ctypes.c_int, [ctypes.POINTER(TuneEntry), ctypes.c_uint32]),
+    "epsm_set_default_hash_bits": (ctypes.c_int, [ctypes.c_uint32]),
     "epsm_batch_prepare": (ctypes.c_int, [ctypes.POINTER(Batch), ctypes.POINTER(ctypes.c_void_p)]),
     "epsm_batch_launch": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
     "epsm_batch_destroy": (None, [ctypes.c_void_p]),

@@ -1,0 +1,334 @@
+"""Autotuner for the scan kernels: picks, per kernel class, mode and text
+length, the fastest built workgroup tile whose output is bit-identical to the
+default tile's; then the fingerprint width k (Section 3.4 uses k = 11) and the
+batch tile the same way.
+
+The result is a JSON cache keyed by the device (architecture and CU count)
+and the library version; apply() installs it through the C ABI
+(epsm_set_tune_table, epsm_set_default_hash_bits, epsm_set_batch_config).
+Output never depends on the choice: every timed variant is compared with the
+default's output before it may win.
+
+    python -m paper_1209_6449_amd.autotune --out tune.json        # on the GPU
+    import paper_1209_6449_amd.autotune as at; at.apply(at.load("tune.json"))
+
+Inputs are seeded and synthetic: uniform random texts over 4 and 64 byte codes
+with patterns cut from them (so every pattern occurs), at several lengths.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import statistics
+import sys
+import time
+
+import torch
+
+from . import (CLASS_BYTES, CLASS_FINGERPRINT, CLASS_WORDS, PLAN_HASH_BITS, PLAN_HOST_ONLY, Batch, Plan,
+               count_into, lib, search_into, set_batch_config, set_default_hash_bits,
+               set_tile_config, set_tune_table, stream_check, tile_configs)
+
+CACHE_VERSION = 1
+HERE = os.path.dirname(os.path.abspath(__file__))
+PACKAGED_DIR = os.path.join(HERE, "tuned")
+
+# Pattern lengths timed for each kernel class.
+CLASS_MS = {CLASS_BYTES: (1, 2, 3), CLASS_WORDS: (4, 8, 15), CLASS_FINGERPRINT: (16, 32)}
+CLASS_NAMES = {CLASS_BYTES: "bytes", CLASS_WORDS: "words", CLASS_FINGERPRINT: "fingerprint"}
+SIGMAS = (4, 64)
+DEFAULT_SIZES = (1 << 20, 1 << 24, 1 << 28, 1 << 30)
+HASH_BITS = tuple(range(8, 15))
+BATCH_WAVES = (4, 8, 16)
+NO_LIMIT = (1 << 64) - 1
+
+
+def device_key(device: int = 0) -> dict:
+    prop = torch.cuda.get_device_properties(device)
+    arch = getattr(prop, "gcnArchName", "") or ""
+    return {"arch": arch.split(":")[0], "cus": int(prop.multi_processor_count), "name": prop.name}
+
+
+def default_cache_path(key: dict | None = None) -> str:
+    key = key or device_key()
+    base = os.environ.get("EPSM_TUNE_CACHE_DIR",
+                          os.path.join(os.path.expanduser("~"), ".cache", "epsm"))
+    return os.path.join(base, f"tune_{key['arch']}_{key['cus']}cu.json")
+
+
+def packaged_path(key: dict | None = None) -> str:
+    key = key or device_key()
+    return os.path.join(PACKAGED_DIR, f"{key['arch']}_{key['cus']}cu.json")
+
+
+# ---------------------------------------------------------------------------
+# timing
+
+
+def _time_ms(fn, reps: int) -> float:
+    """Median of `reps` event-timed calls on the current stream (after one warmup)."""
+    fn()
+    times = []
+    for _ in range(reps):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        fn()
+        e1.record()
+        e1.synchronize()
+        times.append(e0.elapsed_time(e1))
+    return statistics.median(times)
+
+
+def _text(n: int, sigma: int, seed: int) -> torch.Tensor:
+    g = torch.Generator(device="cuda")
+    g.manual_seed(seed)
+    return torch.randint(0, sigma, (n,), dtype=torch.uint8, device="cuda", generator=g)
+
+
+def _cut(text: torch.Tensor, m: int, seed: int) -> bytes:
+    off = (seed * 2654435761) % (text.numel() - m + 1)
+    return bytes(text[off:off + m].cpu().numpy())
+
+
+class _Case:
+    """One (text, pattern) search with its reference output from the default tile."""
+
+    def __init__(self, text: torch.Tensor, pattern: bytes, flags: int = 0):
+        self.text = text
+        self.plan = Plan(pattern, flags)
+        self.hits = torch.zeros(1, dtype=torch.int64, device="cuda")
+        count_into(self.plan, text, self.hits)
+        self.count = int(self.hits.item())
+        self.out = torch.empty(max(self.count, 1), dtype=torch.int64, device="cuda")
+        self.ref = None
+
+    def run(self, count_only: bool) -> None:
+        if count_only:
+            count_into(self.plan, self.text, self.hits)
+        else:
+            search_into(self.plan, self.text, self.out, self.hits)
+
+    def output(self, count_only: bool):
+        self.run(count_only)
+        torch.cuda.synchronize()
+        c = int(self.hits.item())
+        return (c, None) if count_only else (c, self.out[:c].clone())
+
+    def same_as(self, ref, got) -> bool:
+        if ref[0] != got[0]:
+            return False
+        return ref[1] is None or torch.equal(ref[1], got[1])
+
+
+def _check_identical(cases, count_only: bool, refs, what: str) -> None:
+    for i, c in enumerate(cases):
+        got = c.output(count_only)
+        if not c.same_as(refs[i], got):
+            raise RuntimeError(f"{what}: output differs from the default's "
+                               f"(m={c.plan.m}, count {got[0]} vs {refs[i][0]})")
+
+
+def tune_tiles(sizes=DEFAULT_SIZES, reps: int = 5, log=print) -> tuple[list, dict]:
+    """Per (class, mode, size): the fastest identical tile.  Returns the tune
+    table rows (class, count_only, n_max, waves, pieces) and the timings."""
+    tiles = tile_configs()
+    default = tiles[0]
+    rows, timings = [], {}
+    sizes = sorted(sizes)
+    for si, n in enumerate(sizes):
+        n_max = NO_LIMIT if si == len(sizes) - 1 else int((n * sizes[si + 1]) ** 0.5)
+        texts = [_text(n, s, seed=1000 * si + s) for s in SIGMAS]
+        for cls, ms in CLASS_MS.items():
+            cases = [_Case(t, _cut(t, m, seed=m + 7 * k))
+                     for k, t in enumerate(texts) for m in ms if m <= n]
+            for count_only in (False, True):
+                set_tile_config(*default)
+                set_tune_table([])
+                refs = [c.output(count_only) for c in cases]
+                best, best_ms = None, None
+                per = {}
+                for tile in tiles:
+                    set_tile_config(*tile)
+                    _check_identical(cases, count_only, refs, f"tile {tile}")
+                    ms_total = sum(_time_ms(lambda c=c: c.run(count_only), reps) for c in cases)
+                    per[f"{tile[0]}x{tile[1]}"] = round(ms_total, 4)
+                    if best_ms is None or ms_total < best_ms:
+                        best, best_ms = tile, ms_total
+                key = f"{CLASS_NAMES[cls]}/{'count' if count_only else 'positions'}/{n}"
+                timings[key] = per
+                log(f"[autotune] {key}: best {best[0]}x{best[1]} "
+                    f"({best_ms:.3f} ms vs default {per[f'{default[0]}x{default[1]}']:.3f} ms)")
+                rows.append((cls, int(count_only), n_max, best[0], best[1]))
+            del cases
+        del texts
+        torch.cuda.empty_cache()
+    set_tile_config(*default)
+    stream_check()
+    return rows, timings
+
+
+def tune_hash_bits(rows, n: int = 1 << 28, reps: int = 5, log=print) -> tuple[int, dict]:
+    """Fingerprint width k: least total time over both modes at length n with
+    the tuned tiles; every k must give the default's output."""
+    set_tune_table(rows)
+    texts = [_text(n, s, seed=77 + s) for s in SIGMAS]
+    pats = [_cut(t, m, seed=m + 3 * k) for k, t in enumerate(texts) for m in CLASS_MS[CLASS_FINGERPRINT]]
+    pairs = [(texts[i // len(CLASS_MS[CLASS_FINGERPRINT])], p) for i, p in enumerate(pats)]
+    base = [_Case(t, p) for t, p in pairs]
+    refs = {co: [c.output(co) for c in base] for co in (False, True)}
+    per, best, best_ms = {}, 11, None
+    for k in HASH_BITS:
+        cases = [_Case(t, p, PLAN_HASH_BITS(k)) for t, p in pairs]
+        total = 0.0
+        for co in (False, True):
+            _check_identical(cases, co, refs[co], f"hash bits {k}")
+            total += sum(_time_ms(lambda c=c: c.run(co), reps) for c in cases)
+        per[str(k)] = round(total, 4)
+        if best_ms is None or total < best_ms:
+            best, best_ms = k, total
+    log(f"[autotune] fingerprint width: best k={best} ({best_ms:.3f} ms vs k=11 {per['11']:.3f} ms)")
+    stream_check()
+    return best, per
+
+
+def tune_batch(n_texts: int = 400, max_len: int = 1 << 22, reps: int = 3, log=print) -> tuple[int, dict]:
+    """Batch tile (KiB per text tile): least time of a prepared-free batch
+    call over seeded texts of log-uniform length with 1..32 patterns each."""
+    import random
+    r = random.Random(4242)
+    texts, pairs = [], []
+    for i in range(n_texts):
+        n = int(2 ** r.uniform(10, max_len.bit_length() - 1))
+        t = _text(n, 4 if i % 2 else 64, seed=5000 + i)
+        texts.append(t)
+        for j in range(r.randint(1, 32)):
+            m = min(n, r.randint(1, 32))
+            pairs.append((i, Plan(_cut(t, m, seed=i * 131 + j), PLAN_HOST_ONLY)))
+    set_batch_config(BATCH_WAVES[1])
+    b0 = Batch(texts, pairs, count_only=True)
+    b0.run()
+    total = int(b0.total.item())
+    out = torch.empty(max(total, 1), dtype=torch.int64, device="cuda")
+    ref = None
+    per, best, best_ms = {}, BATCH_WAVES[1], None
+    for w in BATCH_WAVES:
+        set_batch_config(w)
+        b = Batch(texts, pairs, out=out)
+        b.run()
+        torch.cuda.synchronize()
+        got = (out[:total].clone(), b.counts[:len(pairs)].clone())
+        if ref is None:
+            ref = got
+        elif not (torch.equal(ref[0], got[0]) and torch.equal(ref[1], got[1])):
+            raise RuntimeError(f"batch tile {w}: output differs")
+        t = _time_ms(b.run, reps)
+        per[str(w)] = round(t, 4)
+        if best_ms is None or t < best_ms:
+            best, best_ms = w, t
+    set_batch_config(BATCH_WAVES[1])
+    log(f"[autotune] batch tile: best {best} KiB ({best_ms:.3f} ms, {len(pairs)} pairs)")
+    stream_check()
+    return best, per
+
+
+def tune(sizes=DEFAULT_SIZES, reps: int = 5, batch: bool = True, log=print) -> dict:
+    t0 = time.time()
+    rows, tile_t = tune_tiles(sizes, reps, log)
+    k, k_t = tune_hash_bits(rows, n=min(max(sizes), 1 << 28), reps=reps, log=log)
+    bw, b_t = tune_batch(log=log) if batch else (BATCH_WAVES[1], {})
+    return {
+        "version": CACHE_VERSION,
+        "library_version": int(lib().epsm_version()),
+        "device": device_key(),
+        "tiles_built": [list(t) for t in tile_configs()],
+        "table": [list(r) for r in rows],
+        "hash_bits": k,
+        "batch_waves": bw,
+        "timings_ms": {"tiles": tile_t, "hash_bits": k_t, "batch_waves": b_t},
+        "sizes": list(sizes),
+        "seconds": round(time.time() - t0, 1),
+    }
+
+
+# ---------------------------------------------------------------------------
+# cache
+
+
+def save(cache: dict, path: str) -> None:
+    os.makedirs(os.path.dirname(os.path.abspath(path)), exist_ok=True)
+    tmp = path + ".tmp"
+    with open(tmp, "w") as f:
+        json.dump(cache, f, indent=1)
+    os.replace(tmp, path)
+
+
+def load(path: str) -> dict:
+    with open(path) as f:
+        return json.load(f)
+
+
+def matches(cache: dict, key: dict | None = None) -> bool:
+    """The cache was made for this device and a library with the same tiles."""
+    if cache.get("version") != CACHE_VERSION:
+        return False
+    dev = cache.get("device", {})
+    if key is not None and (dev.get("arch") != key["arch"] or dev.get("cus") != key["cus"]):
+        return False
+    built = [list(t) for t in tile_configs()]
+    return all(list(r[3:5]) in built for r in cache.get("table", []))
+
+
+def apply(cache: dict) -> None:
+    """Install a cache's tile table, fingerprint width and batch tile."""
+    set_tune_table([tuple(r) for r in cache.get("table", [])])
+    set_default_hash_bits(int(cache.get("hash_bits", 0)))
+    set_batch_config(int(cache.get("batch_waves", BATCH_WAVES[1])))
+
+
+def reset() -> None:
+    """Back to the built-in defaults."""
+    set_tune_table([])
+    set_default_hash_bits(0)
+    set_batch_config(BATCH_WAVES[1])
+    set_tile_config(*tile_configs()[0])
+
+
+def apply_default(log=None) -> str | None:
+    """Apply the user cache, else the packaged table, for the current device,
+    if one matches; returns the path applied (None: built-in defaults)."""
+    key = device_key()
+    for path in (default_cache_path(key), packaged_path(key)):
+        if os.path.exists(path):
+            cache = load(path)
+            if matches(cache, key):
+                apply(cache)
+                if log:
+                    log(f"[autotune] applied {path}")
+                return path
+    return None
+
+
+def main(argv=None) -> int:
+    ap = argparse.ArgumentParser(description="Tune the scan tiles, fingerprint width and batch tile.")
+    ap.add_argument("--out", default=None, help="cache path (default: the per-user cache)")
+    ap.add_argument("--sizes", default=",".join(str(s) for s in DEFAULT_SIZES),
+                    help="text lengths in bytes, comma separated")
+    ap.add_argument("--reps", type=int, default=5)
+    ap.add_argument("--no-batch", action="store_true")
+    args = ap.parse_args(argv)
+    if not torch.cuda.is_available():
+        print("autotune needs a GPU", file=sys.stderr)
+        return 2
+    sizes = tuple(int(s) for s in args.sizes.split(","))
+    log = lambda s: print(s, flush=True)  # noqa: E731
+    cache = tune(sizes, args.reps, batch=not args.no_batch, log=log)
+    path = args.out or default_cache_path()
+    save(cache, path)
+    log(f"[autotune] wrote {path} in {cache['seconds']} s")
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -37,7 +37,37 @@ constexpr uint32_t kKnownPlanFlags = EPSM_PLAN_HOST_ONLY | EPSM_PLAN_FORCE_DIREC
 constexpr uint32_t kDefaultHashBits = 11;  // k = 11 in Section 3.4
 
 // Default tile: 8 waves x 16 KiB per wave = 128 KiB per workgroup tile.
+// The tune table (first matching entry wins) overrides it per kernel class,
+// mode and text length.
+std::mutex g_tune_mutex;
 TileConfig g_tile = {8, 16};
+std::vector<epsm_tune_entry> g_tune;
+uint32_t g_default_hash_bits = kDefaultHashBits;
+constexpr uint32_t kMaxTuneEntries = 256;
+
+uint32_t kernel_class(const DevPlan &d) {
+    if (d.variant == EPSM_VARIANT_FINGERPRINT) return EPSM_CLASS_FINGERPRINT;
+    return (d.nl == 2 && d.pk < 4) ? EPSM_CLASS_BYTES : EPSM_CLASS_WORDS;
+}
+
+TileConfig tile_for(const DevPlan &d, bool count_only, uint64_t n) {
+    const uint32_t cls = kernel_class(d), mode = count_only ? 1u : 0u;
+    std::lock_guard<std::mutex> lock(g_tune_mutex);
+    for (const epsm_tune_entry &e : g_tune)
+        if (e.kernel_class == cls && e.count_only == mode && n <= e.n_max)
+            return {(int)e.waves, (int)e.pieces};
+    return g_tile;
+}
+
+// Smallest built tile: sizes the look-back status words of epsm_reserve so
+// that any tile the table may pick fits.
+uint64_t min_tile_bytes() {
+    TileConfig cfg[16];
+    const int n = std::min(built_tile_configs(cfg, 16), 16);
+    uint64_t b = ~0ull;
+    for (int i = 0; i < n; ++i) b = std::min<uint64_t>(b, (uint64_t)cfg[i].bytes());
+    return b;
+}
 
 // ---- workspace: count bins and look-back status words, one buffer per stream ----
 struct Workspace {
@@ -138,7 +168,8 @@ epsm_status run_search(epsm_plan_t plan, const uint8_t *d_text, uint64_t n, int6
     a.n_hits = d_n_hits;
     a.write = write ? 1 : 0;
     a.plan = plan->dev;
-    const uint64_t tile_bytes = (uint64_t)g_tile.bytes();
+    const TileConfig tile = tile_for(plan->dev, !write, n);
+    const uint64_t tile_bytes = (uint64_t)tile.bytes();
     const uint64_t tiles = (a.last + 1 + tile_bytes - 1) / tile_bytes;
     if (tiles > 0x7FFFFFFFull) return fail(EPSM_EUNSUPPORTED, "text too long for the tile grid");
     a.num_tiles = (uint32_t)tiles;
@@ -156,7 +187,7 @@ epsm_status run_search(epsm_plan_t plan, const uint8_t *d_text, uint64_t n, int6
     hipError_t e = launch_zero_u64((uint64_t *)ws, ws_bytes / 8, stream);
     if (e != hipSuccess) return hip_fail(e, "launch(zero)");
 
-    e = launch_scan(a, g_tile, (int)tiles, stream);
+    e = launch_scan(a, tile, (int)tiles, stream);
     if (e != hipSuccess) return hip_fail(e, "launch(scan)");
     if (!write) {
         e = launch_sum_bins(a.bins, d_n_hits, stream);
@@ -375,7 +406,10 @@ epsm_status epsm_plan(const uint8_t *pattern, uint64_t m, uint32_t flags, epsm_p
     if ((flags & EPSM_PLAN_FORCE_DIRECT) && (flags & EPSM_PLAN_FORCE_FINGERPRINT))
         return fail(EPSM_EINVAL, "FORCE_DIRECT and FORCE_FINGERPRINT are exclusive");
     uint32_t k = (flags >> 8) & 0xF;
-    if (k == 0) k = kDefaultHashBits;
+    if (k == 0) {
+        std::lock_guard<std::mutex> lock(g_tune_mutex);
+        k = g_default_hash_bits;
+    }
     if (k < 8 || k > 14) return fail(EPSM_EINVAL, "hash bits must be in [8, 14]");
 
     bool fingerprint = m >= 16;
@@ -463,6 +497,7 @@ epsm_status epsm_plan_get_info(epsm_plan_t plan, epsm_plan_info *info) {
     }
     info->table = plan->table.empty() ? nullptr : plan->table.data();
     info->device = plan->device;
+    info->kernel_class = kernel_class(d);
     return EPSM_OK;
 }
 
@@ -593,13 +628,49 @@ epsm_status epsm_set_tile_config(uint32_t waves, uint32_t pieces) {
     g_last_error.clear();
     TileConfig c{(int)waves, (int)pieces};
     if (!tile_config_supported(c)) return fail(EPSM_EUNSUPPORTED, "tile configuration not built");
+    std::lock_guard<std::mutex> lock(g_tune_mutex);
     g_tile = c;
+    return EPSM_OK;
+}
+
+uint32_t epsm_tile_configs(uint32_t *waves, uint32_t *pieces, uint32_t capacity) {
+    TileConfig cfg[16];
+    const int n = std::min(built_tile_configs(cfg, 16), 16);
+    for (int i = 0; i < n && (uint32_t)i < capacity; ++i) {
+        if (waves) waves[i] = (uint32_t)cfg[i].waves;
+        if (pieces) pieces[i] = (uint32_t)cfg[i].pieces;
+    }
+    return (uint32_t)n;
+}
+
+epsm_status epsm_set_tune_table(const epsm_tune_entry *entries, uint32_t count) {
+    g_last_error.clear();
+    if (count && !entries) return fail(EPSM_EINVAL, "entries is NULL");
+    if (count > kMaxTuneEntries) return fail(EPSM_EINVAL, "too many tune entries");
+    for (uint32_t i = 0; i < count; ++i) {
+        const epsm_tune_entry &e = entries[i];
+        if (e.kernel_class >= EPSM_N_CLASSES) return fail(EPSM_EINVAL, "unknown kernel class");
+        if (e.count_only > 1) return fail(EPSM_EINVAL, "count_only must be 0 or 1");
+        if (!tile_config_supported({(int)e.waves, (int)e.pieces}))
+            return fail(EPSM_EUNSUPPORTED, "tile configuration not built");
+    }
+    std::lock_guard<std::mutex> lock(g_tune_mutex);
+    g_tune.assign(entries, entries + count);
+    return EPSM_OK;
+}
+
+epsm_status epsm_set_default_hash_bits(uint32_t k) {
+    g_last_error.clear();
+    if (k == 0) k = kDefaultHashBits;
+    if (k < 8 || k > 14) return fail(EPSM_EINVAL, "hash bits must be in [8, 14]");
+    std::lock_guard<std::mutex> lock(g_tune_mutex);
+    g_default_hash_bits = k;
     return EPSM_OK;
 }
 
 epsm_status epsm_reserve(void *stream, uint64_t max_n, uint64_t max_units) {
     g_last_error.clear();
-    const uint64_t tiles = max_n / (uint64_t)g_tile.bytes() + 2 + max_units;
+    const uint64_t tiles = max_n / min_tile_bytes() + 2 + max_units;
     uint8_t *ws = nullptr;
     return workspace_for((hipStream_t)stream, kCountBins * sizeof(uint64_t) + tiles * sizeof(uint64_t),
                          &ws);

@@ -127,5 +127,8 @@ hipError_t launch_sum_bins(const uint64_t *bins, uint64_t *out, hipStream_t s);
 hipError_t launch_scan(const ScanArgs &a, TileConfig cfg, int grid, hipStream_t s);
 int scan_blocks_per_cu(TileConfig cfg, const DevPlan &p);
 bool tile_config_supported(TileConfig cfg);
+// The tile configurations compiled into the library, default first; returns
+// how many there are (writes at most capacity of them).
+int built_tile_configs(TileConfig *out, int capacity);
 
 }  // namespace epsm

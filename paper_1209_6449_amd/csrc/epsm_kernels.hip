@@ -217,13 +217,25 @@ static ScanFn pick(const DevPlan &p) {
     }
 }
 
+// Built tiles, default first.  4x32 has the default's 128 KiB tile with half
+// the LDS per workgroup (masks and stages of 4 waves), so about twice as many
+// workgroups fit on a CU.
+static const TileConfig kBuiltTiles[] = {{8, 16}, {8, 8}, {4, 16}, {4, 32}, {16, 8}, {16, 16}};
+
 static ScanFn pick_fn(TileConfig cfg, const DevPlan &p) {
     if (cfg.waves == 8 && cfg.pieces == 16) return pick<8, 16>(p);
     if (cfg.waves == 8 && cfg.pieces == 8) return pick<8, 8>(p);
     if (cfg.waves == 4 && cfg.pieces == 16) return pick<4, 16>(p);
+    if (cfg.waves == 4 && cfg.pieces == 32) return pick<4, 32>(p);
     if (cfg.waves == 16 && cfg.pieces == 8) return pick<16, 8>(p);
     if (cfg.waves == 16 && cfg.pieces == 16) return pick<16, 16>(p);
     return nullptr;
+}
+
+int built_tile_configs(TileConfig *out, int capacity) {
+    const int n = (int)(sizeof(kBuiltTiles) / sizeof(kBuiltTiles[0]));
+    for (int i = 0; i < n && i < capacity; ++i) out[i] = kBuiltTiles[i];
+    return n;
 }
 
 bool tile_config_supported(TileConfig cfg) {

@@ -152,3 +152,83 @@ def test_batch_plan_null_arguments():
     assert L.epsm_batch_launch(None, None) == _lib.EPSM_EINVAL
     assert L.epsm_batch_get_info(None, None, None, None) == _lib.EPSM_EINVAL
     L.epsm_batch_destroy(None)
+
+
+# ---- tuning: built tiles, tune table, default fingerprint width -------------
+
+def test_tile_configs_listed_and_accepted():
+    tiles = epsm.tile_configs()
+    assert tiles[0] == (8, 16) and (4, 32) in tiles and len(set(tiles)) == len(tiles)
+    for w, p in tiles:
+        epsm.set_tile_config(w, p)
+    epsm.set_tile_config(*tiles[0])
+    with pytest.raises(epsm.EpsmError) as e:
+        epsm.set_tile_config(3, 16)
+    assert e.value.status == _lib.EPSM_EUNSUPPORTED
+
+
+@pytest.mark.parametrize("m,flags,cls", [
+    (1, 0, epsm.CLASS_BYTES), (3, 0, epsm.CLASS_BYTES), (4, 0, epsm.CLASS_WORDS),
+    (15, 0, epsm.CLASS_WORDS), (16, 0, epsm.CLASS_FINGERPRINT), (40, 0, epsm.CLASS_FINGERPRINT),
+    (20, epsm.PLAN_FORCE_DIRECT, epsm.CLASS_WORDS), (15, epsm.PLAN_FORCE_FINGERPRINT, epsm.CLASS_FINGERPRINT),
+])
+def test_kernel_class_of_plan(m, flags, cls):
+    assert host_plan(bytes((3 * i + 1) % 256 for i in range(m)), flags)["kernel_class"] == cls
+
+
+def test_tune_table_validation():
+    tiles = epsm.tile_configs()
+    ok = [(epsm.CLASS_WORDS, 0, 1 << 20, *tiles[1]), (epsm.CLASS_FINGERPRINT, 1, (1 << 64) - 1, *tiles[0])]
+    epsm.set_tune_table(ok)
+    for bad, status in [((3, 0, 1, 8, 16), _lib.EPSM_EINVAL),          # unknown class
+                        ((0, 2, 1, 8, 16), _lib.EPSM_EINVAL),          # unknown mode
+                        ((0, 0, 1, 8, 12), _lib.EPSM_EUNSUPPORTED)]:   # tile not built
+        with pytest.raises(epsm.EpsmError) as e:
+            epsm.set_tune_table(ok + [bad])
+        assert e.value.status == status
+    with pytest.raises(epsm.EpsmError) as e:
+        epsm.set_tune_table([ok[0]] * 257)
+    assert e.value.status == _lib.EPSM_EINVAL
+    L = epsm.lib()
+    assert L.epsm_set_tune_table(None, 1) == _lib.EPSM_EINVAL
+    assert L.epsm_set_tune_table(None, 0) == _lib.EPSM_OK
+    epsm.set_tune_table([])
+
+
+def test_default_hash_bits():
+    p = bytes(range(30))
+    try:
+        epsm.set_default_hash_bits(13)
+        assert host_plan(p)["hash_bits"] == 13
+        assert len(host_plan(p)["table"]) == 1 << 13
+        assert host_plan(p, epsm.PLAN_HASH_BITS(9))["hash_bits"] == 9   # explicit k wins
+        assert host_plan(p[:10])["hash_bits"] == 0                       # direct variant
+        for k in (7, 15):
+            with pytest.raises(epsm.EpsmError):
+                epsm.set_default_hash_bits(k)
+        assert host_plan(p)["hash_bits"] == 13                           # kept on error
+    finally:
+        epsm.set_default_hash_bits(0)
+    assert host_plan(p)["hash_bits"] == 11
+
+
+def test_autotune_cache_round_trip(tmp_path):
+    from paper_1209_6449_amd import autotune
+    tiles = epsm.tile_configs()
+    cache = {"version": autotune.CACHE_VERSION, "device": {"arch": "gfx950", "cus": 256},
+             "table": [[epsm.CLASS_BYTES, 0, 1 << 24, *tiles[3]], [epsm.CLASS_WORDS, 1, (1 << 64) - 1, *tiles[2]]],
+             "hash_bits": 12, "batch_waves": 16}
+    path = str(tmp_path / "t.json")
+    autotune.save(cache, path)
+    got = autotune.load(path)
+    assert got == cache
+    assert autotune.matches(got, {"arch": "gfx950", "cus": 256})
+    assert not autotune.matches(got, {"arch": "gfx942", "cus": 304})
+    assert not autotune.matches(dict(got, table=[[0, 0, 1, 8, 12]]))
+    assert not autotune.matches(dict(got, version=0))
+    try:
+        autotune.apply(got)
+        assert host_plan(bytes(range(20)))["hash_bits"] == 12
+    finally:
+        autotune.reset()
+    assert host_plan(bytes(range(20)))["hash_bits"] == 11

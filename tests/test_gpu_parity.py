@@ -209,3 +209,30 @@ def test_positions_are_sound_and_increasing_random(epsm):
         else:
             p = rng.integers(0, sigma, m).astype(np.uint8).tobytes()
         check(epsm, text, p, offset=int(rng.integers(0, 16)), label=f"random{i}")
+
+
+def _tiles():
+    import paper_1209_6449_amd as mod
+    try:
+        return mod.tile_configs()
+    except Exception:  # library missing: the fixture reports it
+        return [(8, 16)]
+
+
+@pytest.mark.parametrize("tile", _tiles())
+def test_every_built_tile_matches_oracle(epsm, tile):
+    """Each built workgroup tile, at lengths around its own tile size, with
+    dense (sigma 2) and sparse (sigma 64) texts, on all three kernel classes."""
+    w, p = tile
+    tb = w * p * 1024
+    epsm.set_tile_config(w, p)
+    try:
+        rng = np.random.default_rng(w * 100 + p)
+        for n in (tb - 1, tb, tb + 1, 2 * tb + 977, 5 * tb + 13):
+            for sigma in (2, 64):
+                text = rng.integers(0, sigma, n).astype(np.uint8)
+                for m in (1, 3, 4, 9, 16, 33):
+                    off = int(rng.integers(0, n - m + 1))
+                    check(epsm, text, text[off:off + m].tobytes(), label=f"tile {w}x{p} sigma {sigma}")
+    finally:
+        epsm.set_tile_config(8, 16)

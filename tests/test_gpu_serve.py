@@ -40,7 +40,9 @@ def test_mix_equals_alone_and_oracle(env):
         for t in texts:
             srv.add_text(t)
         say(f"mixed stream of {len(queries)} queries")
-        mixed, lat, wall = serve.run_queries(srv, queries)
+        # arrivals 20x faster than the recorded stream (8000 queries/s) so that
+        # queries queue up behind each other and share micro-batches
+        mixed, lat, wall = serve.run_queries(srv, queries, rate_scale=20.0)
         assert all(o.status == 0 for o in mixed)
         st = srv.stats()
         assert st["completed"] == len(queries)
