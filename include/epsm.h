@@ -129,7 +129,10 @@ uint32_t epsm_fingerprint(uint32_t lo, uint32_t hi, uint32_t k, int collide);
  * *d_n_hits (device, uint64) receives the full count.  d_out may be NULL if
  * out_capacity == 0.  n == 0 or m > n gives count 0.  Uses a library-owned
  * workspace tied to the stream (grown on demand; growing allocates device
- * memory, so reserve with epsm_reserve before capturing a graph).
+ * memory, so reserve with epsm_reserve before capturing a graph).  Long
+ * texts with a small out_capacity are searched in two phases (see
+ * EPSM_WRITE_AUTO), whose workspace is about n/8 bytes; others in a single
+ * pass.
  */
 epsm_status epsm_search(epsm_plan_t plan, const uint8_t *d_text, uint64_t n,
                         int64_t *d_out, uint64_t out_capacity,
@@ -194,21 +197,37 @@ epsm_status epsm_set_tile_config(uint32_t waves, uint32_t pieces);
  * returns how many are built. */
 uint32_t epsm_tile_configs(uint32_t *waves, uint32_t *pieces, uint32_t capacity);
 
+/* Write strategies of epsm_search (the order of the output is the same).
+ * SINGLE_PASS: each tile learns its output offset from a decoupled look-back
+ * over the counts of the tiles before it and writes its own positions; a tile
+ * may wait for its predecessors.  TWO_PHASE: each tile parks its hits in a
+ * slot of the workspace (a list of offsets, or its hit masks when the list
+ * would be longer) without waiting, and a second kernel writes the positions;
+ * fastest for sparse output.  AUTO: two-phase for texts of at least 32 tiles
+ * with out_capacity <= n / 32 (the capacity bounds the positions written),
+ * else single pass. */
+#define EPSM_WRITE_AUTO 0u
+#define EPSM_WRITE_SINGLE_PASS 1u
+#define EPSM_WRITE_TWO_PHASE 2u
+
 /* One row of the tune table: searches of plans of class `kernel_class`, in
  * mode `count_only` (0: epsm_search, 1: epsm_count), over texts of n <=
- * n_max bytes use the tile waves x pieces. */
+ * n_max bytes use the tile waves x pieces and write strategy `strategy`
+ * (ignored by counts). */
 typedef struct {
     uint32_t kernel_class;   /* EPSM_CLASS_* */
     uint32_t count_only;     /* 0 or 1 */
     uint64_t n_max;          /* bytes */
     uint32_t waves;          /* a built tile, see epsm_tile_configs */
     uint32_t pieces;
+    uint32_t strategy;       /* EPSM_WRITE_* */
 } epsm_tune_entry;
 
 /* Install the tune table (copied; at most 256 rows): a single-text search
  * uses the first row, in array order, that matches its class, mode and
- * length, and the tile of epsm_set_tile_config when none does.  count == 0
- * clears the table.  EPSM_EINVAL for an unknown class or mode,
+ * length, and the tile of epsm_set_tile_config with EPSM_WRITE_AUTO when
+ * none does.  count == 0 clears the table.  EPSM_EINVAL for an unknown
+ * class, mode or strategy,
  * EPSM_EUNSUPPORTED for a tile that is not built; the old table is kept on
  * error.  Process-wide; output never depends on the table. */
 epsm_status epsm_set_tune_table(const epsm_tune_entry *entries, uint32_t count);

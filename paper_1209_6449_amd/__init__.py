@@ -18,7 +18,8 @@ import torch
 from . import _lib
 from ._lib import (BATCH_COUNT_ONLY, CLASS_BYTES, CLASS_FINGERPRINT, CLASS_WORDS,  # noqa: F401
                    MAX_M, N_CLASSES, PLAN_COLLIDE, PLAN_FORCE_DIRECT, PLAN_FORCE_FINGERPRINT,
-                   PLAN_HASH_BITS, PLAN_HOST_ONLY, VARIANT_DIRECT, VARIANT_FINGERPRINT)
+                   PLAN_HASH_BITS, PLAN_HOST_ONLY, VARIANT_DIRECT, VARIANT_FINGERPRINT,
+                   WRITE_AUTO, WRITE_SINGLE_PASS, WRITE_TWO_PHASE)
 
 __all__ = ["EpsmError", "Plan", "search", "count", "search_into", "count_into", "reserve",
            "stream_check", "lib", "library_path", "Batch", "BatchPlan", "search_batch",
@@ -276,8 +277,9 @@ def tile_configs() -> list[tuple[int, int]]:
 
 def set_tune_table(entries) -> None:
     """Install the tile table (epsm_set_tune_table): an iterable of
-    (kernel_class, count_only, n_max, waves, pieces); first match wins."""
-    rows = [tuple(int(x) for x in e) for e in entries]
+    (kernel_class, count_only, n_max, waves, pieces[, strategy]); first match
+    wins; strategy defaults to WRITE_AUTO."""
+    rows = [tuple(int(x) for x in e) + ((WRITE_AUTO,) if len(e) == 5 else ()) for e in entries]
     arr = (_lib.TuneEntry * max(len(rows), 1))(*[_lib.TuneEntry(*r) for r in rows])
     _check(lib().epsm_set_tune_table(arr, len(rows)), "epsm_set_tune_table")
 

@@ -25,6 +25,9 @@ def PLAN_HASH_BITS(k: int) -> int:
 
 VARIANT_DIRECT = 1
 VARIANT_FINGERPRINT = 2
+WRITE_AUTO = 0
+WRITE_SINGLE_PASS = 1
+WRITE_TWO_PHASE = 2
 CLASS_BYTES = 0
 CLASS_WORDS = 1
 CLASS_FINGERPRINT = 2
@@ -50,7 +53,8 @@ class PlanInfo(ctypes.Structure):
 
 class TuneEntry(ctypes.Structure):
     _fields_ = [("kernel_class", ctypes.c_uint32), ("count_only", ctypes.c_uint32),
-                ("n_max", ctypes.c_uint64), ("waves", ctypes.c_uint32), ("pieces", ctypes.c_uint32)]
+                ("n_max", ctypes.c_uint64), ("waves", ctypes.c_uint32), ("pieces", ctypes.c_uint32),
+                ("strategy", ctypes.c_uint32)]
 
 
 class TextRef(ctypes.Structure):

@@ -1,7 +1,7 @@
 """Autotuner for the scan kernels: picks, per kernel class, mode and text
-length, the fastest built workgroup tile whose output is bit-identical to the
-default tile's; then the fingerprint width k (Section 3.4 uses k = 11) and the
-batch tile the same way.
+length, the fastest built workgroup tile (and, for positions, write
+strategy) whose output is bit-identical to the default's; then the
+fingerprint width k (Section 3.4 uses k = 11) and the batch tile the same way.
 
 The result is a JSON cache keyed by the device (architecture and CU count)
 and the library version; apply() installs it through the C ABI
@@ -26,9 +26,10 @@ import time
 
 import torch
 
-from . import (CLASS_BYTES, CLASS_FINGERPRINT, CLASS_WORDS, PLAN_HASH_BITS, PLAN_HOST_ONLY, Batch, Plan,
-               count_into, lib, search_into, set_batch_config, set_default_hash_bits,
-               set_tile_config, set_tune_table, stream_check, tile_configs)
+from . import (CLASS_BYTES, CLASS_FINGERPRINT, CLASS_WORDS, PLAN_HASH_BITS, PLAN_HOST_ONLY,
+               WRITE_AUTO, WRITE_SINGLE_PASS, WRITE_TWO_PHASE, Batch, Plan, count_into, lib,
+               search_into, set_batch_config, set_default_hash_bits, set_tile_config,
+               set_tune_table, stream_check, tile_configs)
 
 CACHE_VERSION = 1
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -37,6 +38,7 @@ PACKAGED_DIR = os.path.join(HERE, "tuned")
 # Pattern lengths timed for each kernel class.
 CLASS_MS = {CLASS_BYTES: (1, 2, 3), CLASS_WORDS: (4, 8, 15), CLASS_FINGERPRINT: (16, 32)}
 CLASS_NAMES = {CLASS_BYTES: "bytes", CLASS_WORDS: "words", CLASS_FINGERPRINT: "fingerprint"}
+STRATEGY_NAMES = {WRITE_AUTO: "auto", WRITE_SINGLE_PASS: "single", WRITE_TWO_PHASE: "two-phase"}
 SIGMAS = (4, 64)
 DEFAULT_SIZES = (1 << 20, 1 << 24, 1 << 28, 1 << 30)
 HASH_BITS = tuple(range(8, 15))
@@ -131,8 +133,9 @@ def _check_identical(cases, count_only: bool, refs, what: str) -> None:
 
 
 def tune_tiles(sizes=DEFAULT_SIZES, reps: int = 5, log=print) -> tuple[list, dict]:
-    """Per (class, mode, size): the fastest identical tile.  Returns the tune
-    table rows (class, count_only, n_max, waves, pieces) and the timings."""
+    """Per (class, mode, size): the fastest identical tile and, for positions,
+    write strategy.  Returns the tune table rows (class, count_only, n_max,
+    waves, pieces, strategy) and the timings."""
     tiles = tile_configs()
     default = tiles[0]
     rows, timings = [], {}
@@ -144,26 +147,30 @@ def tune_tiles(sizes=DEFAULT_SIZES, reps: int = 5, log=print) -> tuple[list, dic
             cases = [_Case(t, _cut(t, m, seed=m + 7 * k))
                      for k, t in enumerate(texts) for m in ms if m <= n]
             for count_only in (False, True):
+                strategies = ((WRITE_AUTO,) if count_only
+                              else (WRITE_AUTO, WRITE_SINGLE_PASS, WRITE_TWO_PHASE))
                 set_tile_config(*default)
                 set_tune_table([])
                 refs = [c.output(count_only) for c in cases]
-                best, best_ms = None, None
-                per = {}
+                best, best_ms, per = None, None, {}
                 for tile in tiles:
-                    set_tile_config(*tile)
-                    _check_identical(cases, count_only, refs, f"tile {tile}")
-                    ms_total = sum(_time_ms(lambda c=c: c.run(count_only), reps) for c in cases)
-                    per[f"{tile[0]}x{tile[1]}"] = round(ms_total, 4)
-                    if best_ms is None or ms_total < best_ms:
-                        best, best_ms = tile, ms_total
+                    for strategy in strategies:
+                        set_tune_table([(cls, int(count_only), NO_LIMIT, *tile, strategy)])
+                        name = f"{tile[0]}x{tile[1]}" + ("" if count_only else f"/{STRATEGY_NAMES[strategy]}")
+                        _check_identical(cases, count_only, refs, name)
+                        ms_total = sum(_time_ms(lambda c=c: c.run(count_only), reps) for c in cases)
+                        per[name] = round(ms_total, 4)
+                        if best_ms is None or ms_total < best_ms:
+                            best, best_ms = (tile, strategy, name), ms_total
                 key = f"{CLASS_NAMES[cls]}/{'count' if count_only else 'positions'}/{n}"
                 timings[key] = per
-                log(f"[autotune] {key}: best {best[0]}x{best[1]} "
-                    f"({best_ms:.3f} ms vs default {per[f'{default[0]}x{default[1]}']:.3f} ms)")
-                rows.append((cls, int(count_only), n_max, best[0], best[1]))
+                log(f"[autotune] {key}: best {best[2]} ({best_ms:.3f} ms; "
+                    + ", ".join(f"{k} {v:.3f}" for k, v in per.items()) + ")")
+                rows.append((cls, int(count_only), n_max, best[0][0], best[0][1], best[1]))
             del cases
         del texts
         torch.cuda.empty_cache()
+    set_tune_table([])
     set_tile_config(*default)
     stream_check()
     return rows, timings

@@ -50,24 +50,56 @@ uint32_t kernel_class(const DevPlan &d) {
     return (d.nl == 2 && d.pk < 4) ? EPSM_CLASS_BYTES : EPSM_CLASS_WORDS;
 }
 
-TileConfig tile_for(const DevPlan &d, bool count_only, uint64_t n) {
+// EPSM_WRITE_AUTO: two phases (no tile waits on another) for searches of at
+// least kTwoPhaseMinTiles tiles whose output capacity is at most one
+// position per 32 text bytes, so that the average tile parks a short list;
+// otherwise a single pass: short texts save the second kernel, and dense
+// outputs are written while other tiles are still reading.
+constexpr uint64_t kTwoPhaseMinTiles = 32;
+constexpr uint64_t kTwoPhaseMaxDensity = 32;  // text bytes per output position
+
+struct SearchChoice {
+    TileConfig tile;
+    uint32_t strategy;  // EPSM_WRITE_*: AUTO resolved by the caller
+};
+
+SearchChoice choice_for(const DevPlan &d, bool count_only, uint64_t n) {
     const uint32_t cls = kernel_class(d), mode = count_only ? 1u : 0u;
     std::lock_guard<std::mutex> lock(g_tune_mutex);
     for (const epsm_tune_entry &e : g_tune)
         if (e.kernel_class == cls && e.count_only == mode && n <= e.n_max)
-            return {(int)e.waves, (int)e.pieces};
-    return g_tile;
+            return {{(int)e.waves, (int)e.pieces}, e.strategy};
+    return {g_tile, EPSM_WRITE_AUTO};
 }
 
-// Smallest built tile: sizes the look-back status words of epsm_reserve so
-// that any tile the table may pick fits.
-uint64_t min_tile_bytes() {
-    TileConfig cfg[16];
-    const int n = std::min(built_tile_configs(cfg, 16), 16);
-    uint64_t b = ~0ull;
-    for (int i = 0; i < n; ++i) b = std::min<uint64_t>(b, (uint64_t)cfg[i].bytes());
-    return b;
+// Device workspace of one search: [count bins][look-back status words] or
+// [count bins][group sums][wave counts][slots].
+struct SearchWorkspace {
+    size_t bins = 0, status = 0, gsum = 0, wcnt = 0, slots = 0, total = 0, zeroed = 0;
+};
+
+SearchWorkspace search_workspace(uint64_t tiles, TileConfig tile, uint32_t write) {
+    SearchWorkspace w;
+    size_t at = kCountBins * sizeof(uint64_t);
+    if (write == kWriteLookBack) {
+        w.status = at;
+        at += tiles * sizeof(uint64_t);
+        w.zeroed = at;
+    } else if (write == kWriteTwoPhase) {
+        w.gsum = at;
+        at += ((tiles + kGroupTiles - 1) / kGroupTiles) * sizeof(uint64_t);
+        w.zeroed = at;
+        w.wcnt = at;
+        at += ((tiles * (uint64_t)tile.waves * sizeof(uint32_t)) + 255) & ~size_t(255);
+        w.slots = at;
+        at += tiles * (uint64_t)tile.bytes() / 32 * sizeof(uint32_t);
+    } else {
+        w.zeroed = at;
+    }
+    w.total = at;
+    return w;
 }
+
 
 // ---- workspace: count bins and look-back status words, one buffer per stream ----
 struct Workspace {
@@ -166,33 +198,42 @@ epsm_status run_search(epsm_plan_t plan, const uint8_t *d_text, uint64_t n, int6
     a.out = d_out;
     a.cap = write ? cap : 0;
     a.n_hits = d_n_hits;
-    a.write = write ? 1 : 0;
     a.plan = plan->dev;
-    const TileConfig tile = tile_for(plan->dev, !write, n);
+    const SearchChoice ch = choice_for(plan->dev, !write, n);
+    const TileConfig tile = ch.tile;
     const uint64_t tile_bytes = (uint64_t)tile.bytes();
     const uint64_t tiles = (a.last + 1 + tile_bytes - 1) / tile_bytes;
     if (tiles > 0x7FFFFFFFull) return fail(EPSM_EUNSUPPORTED, "text too long for the tile grid");
     a.num_tiles = (uint32_t)tiles;
+    if (!write)
+        a.write = kWriteNone;
+    else if (ch.strategy == EPSM_WRITE_AUTO)
+        a.write = tiles >= kTwoPhaseMinTiles && cap <= n / kTwoPhaseMaxDensity ? kWriteTwoPhase
+                                                                             : kWriteLookBack;
+    else
+        a.write = ch.strategy == EPSM_WRITE_TWO_PHASE ? kWriteTwoPhase : kWriteLookBack;
 
+    const SearchWorkspace L = search_workspace(tiles, tile, a.write);
     uint8_t *ws = nullptr;
-    // workspace: [count bins][look-back status words]
-    const size_t bins_bytes = kCountBins * sizeof(uint64_t);
-    const size_t ws_bytes = bins_bytes + (write ? (size_t)tiles * sizeof(uint64_t) : 0);
-    st = workspace_for(stream, ws_bytes, &ws);
+    st = workspace_for(stream, L.total, &ws);
     if (st != EPSM_OK) return st;
     a.bins = (uint64_t *)ws;
-    a.status = (uint64_t *)(ws + bins_bytes);
+    a.status = (uint64_t *)(ws + L.status);
+    a.gsum = (uint64_t *)(ws + L.gsum);
+    a.wcnt = (uint32_t *)(ws + L.wcnt);
+    a.slots = (uint32_t *)(ws + L.slots);
     a.fault = fault_word(stream);
     if (!a.fault) return fail(EPSM_ENOMEM, "fault word allocation");
-    hipError_t e = launch_zero_u64((uint64_t *)ws, ws_bytes / 8, stream);
+    hipError_t e = launch_zero_u64((uint64_t *)ws, L.zeroed / 8, stream);
     if (e != hipSuccess) return hip_fail(e, "launch(zero)");
 
     e = launch_scan(a, tile, (int)tiles, stream);
     if (e != hipSuccess) return hip_fail(e, "launch(scan)");
-    if (!write) {
+    if (a.write == kWriteNone)
         e = launch_sum_bins(a.bins, d_n_hits, stream);
-        if (e != hipSuccess) return hip_fail(e, "launch(sum_bins)");
-    }
+    else if (a.write == kWriteTwoPhase)
+        e = launch_expand(a, tile, stream);
+    if (e != hipSuccess) return hip_fail(e, "launch(sum_bins/expand)");
     return EPSM_OK;
 }
 
@@ -651,6 +692,7 @@ epsm_status epsm_set_tune_table(const epsm_tune_entry *entries, uint32_t count) 
         const epsm_tune_entry &e = entries[i];
         if (e.kernel_class >= EPSM_N_CLASSES) return fail(EPSM_EINVAL, "unknown kernel class");
         if (e.count_only > 1) return fail(EPSM_EINVAL, "count_only must be 0 or 1");
+        if (e.strategy > EPSM_WRITE_TWO_PHASE) return fail(EPSM_EINVAL, "unknown write strategy");
         if (!tile_config_supported({(int)e.waves, (int)e.pieces}))
             return fail(EPSM_EUNSUPPORTED, "tile configuration not built");
     }
@@ -670,10 +712,17 @@ epsm_status epsm_set_default_hash_bits(uint32_t k) {
 
 epsm_status epsm_reserve(void *stream, uint64_t max_n, uint64_t max_units) {
     g_last_error.clear();
-    const uint64_t tiles = max_n / min_tile_bytes() + 2 + max_units;
+    // the largest workspace any built tile and write strategy needs for max_n
+    TileConfig cfg[16];
+    const int nc = std::min(built_tile_configs(cfg, 16), 16);
+    size_t need = 0;
+    for (int i = 0; i < nc; ++i) {
+        const uint64_t tiles = max_n / (uint64_t)cfg[i].bytes() + 2 + max_units;
+        need = std::max(need, search_workspace(tiles, cfg[i], kWriteLookBack).total);
+        need = std::max(need, search_workspace(tiles, cfg[i], kWriteTwoPhase).total);
+    }
     uint8_t *ws = nullptr;
-    return workspace_for((hipStream_t)stream, kCountBins * sizeof(uint64_t) + tiles * sizeof(uint64_t),
-                         &ws);
+    return workspace_for((hipStream_t)stream, need, &ws);
 }
 
 void epsm_release(void) {

@@ -271,6 +271,17 @@ __device__ __forceinline__ void flush_stage(const uint32_t *stage, uint32_t fill
     __builtin_amdgcn_wave_barrier();
 }
 
+// Write stage[0..fill) as dst[j] = add + stage[j] (tile-relative offsets of
+// a two-phase slot list).  Lanes write consecutive entries.
+__device__ __forceinline__ void flush_list(const uint32_t *stage, uint32_t fill, uint32_t *dst,
+                                           uint32_t add, int lane) {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    for (uint32_t j = lane; j < fill; j += kWave) dst[j] = add + stage[j];
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
 template <int U, int NL>
 __device__ __forceinline__ void load_chunk(uint32_t (&w)[U][NL * 4 + 1], __amdgpu_buffer_rsrc_t r,
                                            uint32_t off) {

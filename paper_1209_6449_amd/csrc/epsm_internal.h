@@ -60,10 +60,27 @@ struct ScanArgs {
     uint64_t *status;        // [num_tiles] look-back words, zeroed before launch
     uint64_t *bins;          // [kCountBins] count-only partial sums, zeroed before launch
     uint32_t *fault;         // set to 1 if a bounded wait gave up (never expected)
+    uint32_t *wcnt;          // two-phase: [num_tiles * waves] hits of each wave of each tile
+    uint64_t *gsum;          // two-phase: [ceil(num_tiles / kGroupTiles)] hits per tile group, zeroed
+    uint32_t *slots;         // two-phase: [num_tiles * tile_bytes / 32] list or masks per tile
     uint32_t num_tiles;
-    uint32_t write;          // 0: count only
+    uint32_t write;          // kWriteNone, kWriteLookBack or kWriteTwoPhase
+    uint32_t expand_tiles;   // two-phase: tiles per expand workgroup, 1..kExpandTiles
     DevPlan plan;
 };
+
+// Write strategies of epsm_search.  Single pass: each tile learns its output
+// offset from a decoupled look-back and writes its positions itself.  Two
+// phase: each tile parks its hits in its own slot (an ascending list of tile
+// offsets if they fit in tile_bytes / 32 words, else its raw hit masks) and
+// publishes its per-wave counts; a second kernel turns slots into positions.
+constexpr uint32_t kWriteNone = 0;
+constexpr uint32_t kWriteLookBack = 1;
+constexpr uint32_t kWriteTwoPhase = 2;
+// Tiles per group sum, and the most tiles per expand workgroup, of the
+// two-phase write.
+constexpr uint32_t kGroupTiles = 64;
+constexpr uint32_t kExpandTiles = 8;
 
 // ---- batched search -------------------------------------------------------
 // A unit is one tile of one text; its workgroup loads the tile once and runs
@@ -125,6 +142,8 @@ hipError_t launch_zero_u64(uint64_t *p, uint64_t count, hipStream_t s);
 hipError_t launch_set_u64(uint64_t *p, uint64_t value, hipStream_t s);
 hipError_t launch_sum_bins(const uint64_t *bins, uint64_t *out, hipStream_t s);
 hipError_t launch_scan(const ScanArgs &a, TileConfig cfg, int grid, hipStream_t s);
+// Second phase of a two-phase search: slots -> positions, and *n_hits.
+hipError_t launch_expand(ScanArgs a, TileConfig cfg, hipStream_t s);
 int scan_blocks_per_cu(TileConfig cfg, const DevPlan &p);
 bool tile_config_supported(TileConfig cfg);
 // The tile configurations compiled into the library, default first; returns

@@ -24,40 +24,50 @@
 // 0..7 and m >= 15 every occurrence is hit by exactly one (block, offset)
 // pair.  Candidates are then verified against the whole pattern.
 //
-// Output.  Each lane parks a 16-bit hit mask per piece in LDS.  Workgroup b
-// owns tile b; it publishes the tile's count and a single-pass decoupled
-// look-back over the predecessors' status words gives its exclusive prefix,
-// so positions are written in ascending order in one pass over the text.
-// Measured constraints shape the schedule: a device-scope atomic on one
-// address serialises its callers (one every ~12 ns), so no tile counter is
-// used; the inclusive-prefix frontier advances by one look-back window per
-// memory round trip, so tiles are large (64 * 128 KiB per round trip);
-// and a persistent workgroup that walks several consecutive tiles delays the
-// counts of its later tiles behind the writes of its earlier ones, which
-// serialises the chain, so workgroups are not persistent.  Count-only
-// searches skip the look-back.
+// Output.  Each lane parks a 16-bit hit mask per piece in LDS; positions
+// leave in ascending order in one of two ways.  Single pass: workgroup b
+// owns tile b, publishes the tile's count, and a decoupled look-back over
+// the predecessors' status words gives its exclusive prefix, so it writes
+// its positions itself.  Two phase: the tile parks its hits in its own
+// workspace slot (an ascending list of tile offsets when there are at most
+// tile/32 of them, else the raw masks), stores its per-wave counts and adds
+// its count to a group sum, and never waits; a second kernel computes each
+// tile's offset from the sums and expands the slots.  Measured on 1 GiB
+// texts, the look-back costs about a quarter of the scan rate even when no
+// position is written (a waiting workgroup issues no loads), while the two
+// phase scan runs at the count-only rate; single pass stays ahead for dense
+// output, whose writes it overlaps with other tiles' reads.
+// Other measured constraints: a device-scope atomic on one address
+// serialises its callers (one every ~12 ns), so no tile counter is used; the
+// look-back's inclusive frontier advances by one window per memory round
+// trip, so tiles are large (64 * 128 KiB per round trip); and a persistent
+// workgroup that walks several consecutive tiles delays the counts of its
+// later tiles behind the writes of its earlier ones, which serialises the
+// chain, so workgroups are not persistent.  Count-only searches add tile
+// counts into 256 bins.
 #include "epsm_device.h"
 
 namespace epsm {
 
-// Write phase of one tile, run by each wave on its own span: expand the
-// parked masks into wave-relative offsets staged in LDS (ascending), and
-// flush the stage with consecutive lanes writing consecutive int64 entries.
-template <int PIECES, int THREADS>
-__device__ __forceinline__ void write_tile(const uint32_t (*s_mask)[THREADS], uint32_t *stage,
-                                           const ScanArgs &a, uint64_t obase, int64_t wave_pos0,
-                                           int tid, int lane) {
-    uint32_t fill = 0;
+// Expand the 16-bit hit masks of one wave's span (piece i of lane L at
+// masks[i / 2][tid], half i % 2) into ascending wave-relative offsets staged
+// in LDS; sink(stage, fill, done) consumes each full stage, `done` being the
+// number of entries consumed before it.  Used on LDS masks by the scan and on
+// a slot's masks in global memory by the two-phase expand.
+template <int PIECES, int THREADS, class Sink>
+__device__ __forceinline__ void expand_masks(const uint32_t (*masks)[THREADS], uint32_t *stage,
+                                             int tid, int lane, Sink sink) {
+    uint32_t fill = 0, done = 0;
 #pragma unroll 1
     for (int piece = 0; piece < PIECES; ++piece) {
-        const uint32_t mk = (s_mask[piece >> 1][tid] >> ((piece & 1) * 16)) & 0xFFFFu;
+        const uint32_t mk = (masks[piece >> 1][tid] >> ((piece & 1) * 16)) & 0xFFFFu;
         const uint32_t c = __popc(mk);
         if (!wave_any(c != 0)) continue;
         const uint32_t incl = wave_incl_scan32(c, lane);
         const uint32_t tot = __shfl(incl, kWave - 1, kWave);
         if (fill + tot > kStage) {
-            flush_stage(stage, fill, a.out, a.cap, obase, wave_pos0, lane);
-            obase += fill;
+            sink(stage, fill, done);
+            done += fill;
             fill = 0;
         }
         uint32_t at = fill + incl - c;
@@ -70,7 +80,18 @@ __device__ __forceinline__ void write_tile(const uint32_t (*s_mask)[THREADS], ui
         }
         fill += tot;
     }
-    if (fill) flush_stage(stage, fill, a.out, a.cap, obase, wave_pos0, lane);
+    if (fill) sink(stage, fill, done);
+}
+
+// Positions of one wave's span to out[obase ...] (entries past cap dropped).
+template <int PIECES, int THREADS>
+__device__ __forceinline__ void write_tile(const uint32_t (*masks)[THREADS], uint32_t *stage,
+                                           const ScanArgs &a, uint64_t obase, int64_t wave_pos0,
+                                           int tid, int lane) {
+    expand_masks<PIECES, THREADS>(masks, stage, tid, lane,
+                                  [&](const uint32_t *st, uint32_t fill, uint32_t done) {
+                                      flush_stage(st, fill, a.out, a.cap, obase + done, wave_pos0, lane);
+                                  });
 }
 
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t tile_rsrc(const ScanArgs &a, uint64_t tile_start) {
@@ -132,11 +153,35 @@ __global__ __launch_bounds__(WAVES * kWave, 4) void scan_kernel(ScanArgs a) {
 #pragma unroll
     for (int i = 0; i < WAVES; ++i) tile_cnt += s_wcnt[i];
 
-    if (!a.write) {
+    if (a.write == kWriteNone) {
         // count only: no ordering needed; spread the adds over kCountBins words
         if (tid == 0 && tile_cnt)
             atomicAdd((unsigned long long *)&a.bins[tile & (kCountBins - 1)],
                       (unsigned long long)tile_cnt);
+        return;
+    }
+    if (a.write == kWriteTwoPhase) {
+        // park the hits in the tile's slot; nothing waits on other tiles
+        constexpr uint32_t kSlotWords = kTile / 32;  // = words of s_mask
+        if (lane == 0) a.wcnt[(size_t)tile * WAVES + wave] = wtot;
+        if (tid == 0 && tile_cnt)
+            atomicAdd((unsigned long long *)&a.gsum[tile / kGroupTiles], (unsigned long long)tile_cnt);
+        if (tile_cnt == 0) return;
+        uint32_t *slot = a.slots + (size_t)tile * kSlotWords;
+        if (tile_cnt > kSlotWords) {
+            const uint32_t *src = &s_mask[0][0];
+            for (uint32_t i = tid; i < kSlotWords; i += kThreads) slot[i] = src[i];
+            return;
+        }
+        if (wtot == 0) return;
+        uint32_t before = 0;
+        for (int i = 0; i < wave; ++i) before += s_wcnt[i];
+        uint32_t *dst = slot + before;
+        const uint32_t wave_off = (uint32_t)wave * kWaveSpan;
+        expand_masks<kPieces, kThreads>(s_mask, s_stage[wave], tid, lane,
+                                        [&](const uint32_t *st, uint32_t fill, uint32_t done) {
+                                            flush_list(st, fill, dst + done, wave_off, lane);
+                                        });
         return;
     }
     if (wave == 0) {
@@ -152,6 +197,105 @@ __global__ __launch_bounds__(WAVES * kWave, 4) void scan_kernel(ScanArgs a) {
     for (int i = 0; i < wave; ++i) obase += s_wcnt[i];
     const int64_t wave_pos0 = (int64_t)(tile_start + (uint64_t)wave * kWaveSpan) - (int64_t)a.delta;
     write_tile<kPieces, kThreads>(s_mask, s_stage[wave], a, obase, wave_pos0, tid, lane);
+}
+
+// Second phase of a two-phase search.  Workgroup b expands tiles [b * E,
+// +E), E = a.expand_tiles <= kExpandTiles: the output offset of its first
+// tile is the sum of the group sums before it plus the wave counts of the
+// earlier tiles of its group; then each tile's slot becomes positions, a
+// list by a plain copy, masks through the same staged expansion as the scan.  All
+// counts are loaded up front and the masks of the next dense tile are
+// loaded while the current one is expanded, so the chain of dependent
+// memory round trips per workgroup stays short.  The workgroup of the last
+// tile writes the total count.
+template <int WAVES, int PIECES>
+__global__ __launch_bounds__(WAVES * kWave) void expand_kernel(ScanArgs a) {
+    constexpr int kThreads = WAVES * kWave;
+    constexpr uint32_t kWaveSpan = PIECES * kWavePiece;
+    constexpr uint32_t kTile = WAVES * kWaveSpan;
+    constexpr uint32_t kSlotWords = kTile / 32;
+    constexpr int kPairs = PIECES / 2;  // mask words per lane and tile
+    static_assert(kExpandTiles * WAVES <= kThreads, "one wave count per thread");
+    __shared__ uint32_t s_stage[WAVES][kStage];
+    __shared__ uint32_t s_mk[WAVES][kPairs][kWave];
+    __shared__ uint32_t s_wc[kExpandTiles][WAVES];
+    __shared__ uint32_t s_tot[kExpandTiles];
+    __shared__ uint64_t s_part[WAVES];
+    const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
+    const uint32_t first = blockIdx.x * a.expand_tiles;  // num_tiles < 2^31
+    const uint32_t cnt = min(first + a.expand_tiles, a.num_tiles) - first;
+
+    // prefix of the first tile (group sums, then the group's earlier tiles)
+    // and the wave counts and totals of this workgroup's tiles
+    const uint32_t g0 = first / kGroupTiles;
+    uint64_t v = 0;
+    for (uint32_t g = tid; g < g0; g += kThreads) v += a.gsum[g];
+    for (uint64_t i = (uint64_t)g0 * kGroupTiles * WAVES + tid; i < (uint64_t)first * WAVES; i += kThreads)
+        v += a.wcnt[i];
+    if (tid < kExpandTiles * WAVES)
+        (&s_wc[0][0])[tid] = (uint32_t)tid < cnt * WAVES ? a.wcnt[(uint64_t)first * WAVES + tid] : 0;
+    if (tid < kExpandTiles) {
+        uint32_t t = 0;
+        if ((uint32_t)tid < cnt)
+            for (int w = 0; w < WAVES; ++w) t += a.wcnt[((uint64_t)first + tid) * WAVES + w];
+        s_tot[tid] = t;
+    }
+    v = wave_sum64(v);
+    if (lane == 0) s_part[wave] = v;
+    __syncthreads();
+    uint64_t pos = 0;
+#pragma unroll
+    for (int i = 0; i < WAVES; ++i) pos += s_part[i];
+
+    auto next_dense = [&](uint32_t i) {
+        while (i < cnt && s_tot[i] <= kSlotWords) ++i;
+        return i;
+    };
+    auto load_masks = [&](uint32_t i, uint32_t (&dst)[kPairs]) {
+        const uint32_t *slot = a.slots + ((uint64_t)first + i) * kSlotWords;
+#pragma unroll
+        for (int p = 0; p < kPairs; ++p) dst[p] = slot[p * kThreads + tid];
+    };
+    uint32_t pre[kPairs];
+    uint32_t nd = next_dense(0);
+    if (nd < cnt) load_masks(nd, pre);
+
+#pragma unroll 1
+    for (uint32_t i = 0; i < cnt; ++i) {
+        const uint32_t tot = s_tot[i];
+        if (tot == 0) continue;
+        const uint64_t t = (uint64_t)first + i;
+        const int64_t tile_pos0 = (int64_t)(t * kTile) - (int64_t)a.delta;
+        if (tot <= kSlotWords) {
+            const uint32_t *slot = a.slots + t * kSlotWords;
+            for (uint32_t j0 = 0; j0 < tot; j0 += 4 * kThreads) {
+                uint32_t r[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const uint32_t j = j0 + u * kThreads + tid;
+                    r[u] = j < tot ? slot[j] : 0;
+                }
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const uint32_t j = j0 + u * kThreads + tid;
+                    if (j < tot && pos + j < a.cap) a.out[pos + j] = tile_pos0 + r[u];
+                }
+            }
+        } else {
+            // tile i is the dense tile whose masks are in pre
+#pragma unroll
+            for (int p = 0; p < kPairs; ++p) s_mk[wave][p][lane] = pre[p];
+            nd = next_dense(i + 1);
+            if (nd < cnt) load_masks(nd, pre);
+            uint32_t before = 0;
+            for (int w = 0; w < wave; ++w) before += s_wc[i][w];
+            if (s_wc[i][wave])
+                write_tile<PIECES, kWave>(s_mk[wave], s_stage[wave], a, pos + before,
+                                          tile_pos0 + (int64_t)wave * kWaveSpan, lane, lane);
+        }
+        pos += tot;
+    }
+    if (first + cnt == a.num_tiles && tid == 0) *a.n_hits = pos;
 }
 
 // Sum of the count bins into *out (one workgroup of kCountBins threads).
@@ -258,6 +402,27 @@ int scan_blocks_per_cu(TileConfig cfg, const DevPlan &p) {
                                                      table_bytes(p)) != hipSuccess)
         return 0;
     return blocks;
+}
+
+typedef void (*ExpandFn)(ScanArgs);
+
+static ExpandFn pick_expand(TileConfig cfg) {
+    if (cfg.waves == 8 && cfg.pieces == 16) return expand_kernel<8, 16>;
+    if (cfg.waves == 8 && cfg.pieces == 8) return expand_kernel<8, 8>;
+    if (cfg.waves == 4 && cfg.pieces == 16) return expand_kernel<4, 16>;
+    if (cfg.waves == 4 && cfg.pieces == 32) return expand_kernel<4, 32>;
+    if (cfg.waves == 16 && cfg.pieces == 8) return expand_kernel<16, 8>;
+    if (cfg.waves == 16 && cfg.pieces == 16) return expand_kernel<16, 16>;
+    return nullptr;
+}
+
+hipError_t launch_expand(ScanArgs a, TileConfig cfg, hipStream_t s) {
+    ExpandFn fn = pick_expand(cfg);
+    if (!fn) return hipErrorInvalidValue;
+    a.expand_tiles = kExpandTiles;
+    const uint32_t grid = (a.num_tiles + a.expand_tiles - 1) / a.expand_tiles;
+    hipLaunchKernelGGL(fn, dim3(grid), dim3(cfg.waves * kWave), 0, s, a);
+    return hipGetLastError();
 }
 
 hipError_t launch_scan(const ScanArgs &a, TileConfig cfg, int grid, hipStream_t s) {

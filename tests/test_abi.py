@@ -182,7 +182,8 @@ def test_tune_table_validation():
     epsm.set_tune_table(ok)
     for bad, status in [((3, 0, 1, 8, 16), _lib.EPSM_EINVAL),          # unknown class
                         ((0, 2, 1, 8, 16), _lib.EPSM_EINVAL),          # unknown mode
-                        ((0, 0, 1, 8, 12), _lib.EPSM_EUNSUPPORTED)]:   # tile not built
+                        ((0, 0, 1, 8, 12), _lib.EPSM_EUNSUPPORTED),    # tile not built
+                        ((0, 0, 1, 8, 16, 3), _lib.EPSM_EINVAL)]:      # unknown strategy
         with pytest.raises(epsm.EpsmError) as e:
             epsm.set_tune_table(ok + [bad])
         assert e.value.status == status

@@ -219,20 +219,76 @@ def _tiles():
         return [(8, 16)]
 
 
+def force(epsm, tile, strategy):
+    """Every search (all classes) on `tile` with write strategy `strategy`."""
+    epsm.set_tune_table([(c, 0, (1 << 64) - 1, *tile, strategy) for c in range(epsm.N_CLASSES)]
+                        + [(c, 1, (1 << 64) - 1, *tile, 0) for c in range(epsm.N_CLASSES)])
+
+
+@pytest.mark.parametrize("strategy", [1, 2], ids=["single_pass", "two_phase"])
 @pytest.mark.parametrize("tile", _tiles())
-def test_every_built_tile_matches_oracle(epsm, tile):
-    """Each built workgroup tile, at lengths around its own tile size, with
-    dense (sigma 2) and sparse (sigma 64) texts, on all three kernel classes."""
+def test_every_built_tile_matches_oracle(epsm, tile, strategy):
+    """Each built workgroup tile and write strategy, at lengths around its own
+    tile size, with dense (sigma 2: hit masks parked) and sparse (sigma 64:
+    offset lists parked) texts, on all three kernel classes."""
     w, p = tile
     tb = w * p * 1024
-    epsm.set_tile_config(w, p)
+    force(epsm, tile, strategy)
     try:
         rng = np.random.default_rng(w * 100 + p)
-        for n in (tb - 1, tb, tb + 1, 2 * tb + 977, 5 * tb + 13):
+        for n in (tb - 1, tb, tb + 1, 2 * tb + 977, 9 * tb + 13):
             for sigma in (2, 64):
                 text = rng.integers(0, sigma, n).astype(np.uint8)
                 for m in (1, 3, 4, 9, 16, 33):
                     off = int(rng.integers(0, n - m + 1))
-                    check(epsm, text, text[off:off + m].tobytes(), label=f"tile {w}x{p} sigma {sigma}")
+                    check(epsm, text, text[off:off + m].tobytes(),
+                          label=f"tile {w}x{p} strategy {strategy} sigma {sigma}")
     finally:
-        epsm.set_tile_config(8, 16)
+        epsm.set_tune_table([])
+
+
+@pytest.mark.parametrize("strategy", [1, 2], ids=["single_pass", "two_phase"])
+def test_write_strategies_many_groups(epsm, strategy):
+    """64 KiB tiles over 9 MiB + a ragged tail: several 64-tile count groups
+    and 8-tile expand workgroups; mixed densities along the text (a dense
+    run, a sparse run), unaligned start, truncated output."""
+    force(epsm, (8, 8), strategy)
+    try:
+        n = 9 * (1 << 20) + 4097
+        rng = np.random.default_rng(77)
+        text = rng.integers(0, 64, n).astype(np.uint8)
+        text[(3 << 20):(3 << 20) + 300_000] = rng.integers(0, 2, 300_000)  # dense stretch
+        for m, offset in ((1, 0), (2, 5), (5, 11), (17, 3)):
+            check(epsm, text, bytes(text[(3 << 20) + 1000:(3 << 20) + 1000 + m]), offset=offset,
+                  label=f"groups strategy {strategy}")
+        t = to_gpu(text, 7)
+        p = bytes(text[(3 << 20) + 50:(3 << 20) + 51])
+        exp = oracle.positions(text, p)
+        for cap in (0, 1, exp.size // 3, exp.size - 1):
+            out = torch.full((cap + 4,), -1, dtype=torch.int64, device="cuda")
+            hits = torch.zeros(1, dtype=torch.int64, device="cuda")
+            plan = epsm.Plan(p)
+            epsm.search_into(plan, t, out[:cap], hits)
+            torch.cuda.synchronize()
+            assert int(hits.item()) == exp.size
+            got = out.cpu().numpy()
+            assert np.array_equal(got[:cap], exp[:cap]) and (got[cap:] == -1).all(), cap
+        epsm.stream_check()
+    finally:
+        epsm.set_tune_table([])
+
+
+def test_unary_text_two_phase_closed_form(epsm):
+    """a^n with a^m under the two-phase write: every tile parks masks."""
+    force(epsm, (8, 16), 2)
+    try:
+        n = 5 * (1 << 20) + 3
+        t = torch.full((n,), ord("a"), dtype=torch.uint8, device="cuda")
+        for m in (1, 7, 16, 31):
+            say(f"unary two-phase m={m}")
+            got = epsm.search(t, b"a" * m)
+            assert got.numel() == n - m + 1
+            assert torch.equal(got, torch.arange(n - m + 1, dtype=torch.int64, device="cuda"))
+        epsm.stream_check()
+    finally:
+        epsm.set_tune_table([])
