@@ -22,8 +22,11 @@ import statistics
 import sys
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+# what decides the traffic of a search: the kernels, the host's choice of
+# tile and write strategy, and the packaged tune table
 KERNEL_SOURCES = ["paper_1209_6449_amd/csrc/epsm_kernels.hip", "paper_1209_6449_amd/csrc/epsm_device.h",
-                  "paper_1209_6449_amd/csrc/epsm_internal.h"]
+                  "paper_1209_6449_amd/csrc/epsm_internal.h", "paper_1209_6449_amd/csrc/epsm_api.hip",
+                  "paper_1209_6449_amd/tuned/gfx950_256cu.json"]
 
 
 def kernel_hash() -> str:
@@ -75,12 +78,22 @@ def cmd_stats(args):
         lines.append(f"{int(r['Calls']):7d} {float(r['AverageNs']) / 1e3:10.2f} "
                      f"{float(r['TotalDurationNs']) / 1e6:10.3f} {float(r['Percentage']):6.2f}  {name}")
     if args.kernel:
-        sel = [r for r in rows if args.kernel in r["Name"]]
-        calls = sum(int(r["Calls"]) for r in sel)
-        total = sum(float(r["TotalDurationNs"]) for r in sel)
-        if calls:
-            lines += ["", f"all instances of {args.kernel}: {calls} calls, {total / 1e6:.3f} ms, "
-                          f"average {total / calls / 1e3:.2f} us per dispatch"]
+        names = args.kernel.split(",")
+        per_unit = 0.0
+        units = None
+        lines.append("")
+        for k in names:
+            sel = [r for r in rows if k in r["Name"]]
+            calls = sum(int(r["Calls"]) for r in sel)
+            total = sum(float(r["TotalDurationNs"]) for r in sel)
+            if units is None:
+                units = calls  # the first kernel counts the units (one dispatch each)
+            if calls:
+                lines.append(f"all instances of {k}: {calls} calls, {total / 1e6:.3f} ms, "
+                             f"average {total / calls / 1e3:.2f} us per dispatch")
+                per_unit += total / max(units, 1)
+        if len(names) > 1 and units:
+            lines.append(f"per {names[0]} dispatch, {' + '.join(names)}: {per_unit / 1e3:.2f} us")
     text = "\n".join(lines) + "\n"
     with open(args.out, "w") as f:
         f.write(text)
@@ -95,10 +108,23 @@ def cmd_traffic(args):
         raise SystemExit("calibration dispatches not found")
     fetch_factor = args.calib_bytes / (statistics.median(cf) * 1024.0)
     write_factor = args.calib_bytes / (statistics.median(cw) * 1024.0)
-    f = counter_per_dispatch(args.fetch, "FETCH_SIZE", args.kernel)
-    w = counter_per_dispatch(args.write, "WRITE_SIZE", args.kernel)
-    if not f or not w or len(f) != len(w):
-        raise SystemExit(f"kernel dispatches not found or unequal ({len(f)} vs {len(w)})")
+    # per unit: all dispatches of the listed kernels over the number of
+    # dispatches of the first one (e.g. per scan: scan + expand + zero)
+    names = args.kernel.split(",")
+    f_all, w_all, units = 0.0, 0.0, None
+    for k in names:
+        f = counter_per_dispatch(args.fetch, "FETCH_SIZE", k)
+        w = counter_per_dispatch(args.write, "WRITE_SIZE", k)
+        if len(f) != len(w):
+            raise SystemExit(f"{k}: unequal dispatch counts ({len(f)} vs {len(w)})")
+        if units is None:
+            units = len(f)
+            if not units:
+                raise SystemExit(f"no dispatches of {k}")
+        f_all += sum(f)
+        w_all += sum(w)
+    f = [f_all / units]
+    w = [w_all / units]
     fetch_b = [x * 1024.0 * fetch_factor for x in f]
     write_b = [x * 1024.0 * write_factor for x in w]
     per = statistics.mean(a + b for a, b in zip(fetch_b, write_b))
@@ -106,7 +132,7 @@ def cmd_traffic(args):
         "workload": args.workload,
         "kernel": args.kernel,
         "kernel_hash": kernel_hash(),
-        "dispatches": len(f),
+        "dispatches": units,
         "fetch_bytes_per_launch": round(statistics.mean(fetch_b)),
         "write_bytes_per_launch": round(statistics.mean(write_b)),
         "bytes_per_launch": round(per),
@@ -119,7 +145,7 @@ def cmd_traffic(args):
         json.dump(out, fh, indent=1)
     text = (f"# HBM traffic of {args.kernel} ({args.workload})\n"
             f"command: {args.command}\n\n"
-            f"dispatches: {len(f)}\n"
+            f"units (dispatches of {names[0]}): {units}\n"
             f"FETCH_SIZE mean per dispatch: {statistics.mean(f):.0f} KiB raw -> "
             f"{out['fetch_bytes_per_launch']} B after calibration\n"
             f"WRITE_SIZE mean per dispatch: {statistics.mean(w):.0f} KiB raw -> "
@@ -144,13 +170,16 @@ def main(argv=None):
     s.add_argument("dir")
     s.add_argument("--command", required=True)
     s.add_argument("--out", required=True)
-    s.add_argument("--kernel", default="", help="also aggregate all kernels whose name contains this")
+    s.add_argument("--kernel", default="",
+                   help="also aggregate the kernels whose names contain these (comma separated; "
+                        "the first counts the units)")
     t = sub.add_parser("traffic")
     for k in ("fetch", "write", "calib_fetch", "calib_write"):
         t.add_argument("--" + k.replace("_", "-"), dest=k, required=True)
     t.add_argument("--calib-bytes", type=int, default=1 << 30)
     t.add_argument("--calib-kernel", default="copy")
-    t.add_argument("--kernel", default="scan_kernel")
+    t.add_argument("--kernel", default="scan_kernel,expand_kernel,zero_u64",
+                   help="comma-separated kernel names; the first counts the units")
     t.add_argument("--workload", default="sweep1g")
     t.add_argument("--command", required=True)
     t.add_argument("--out-json", required=True)
