@@ -6,8 +6,8 @@
 // owns the contiguous PIECES KiB at w*PIECES KiB inside the tile and walks
 // it in chunks of U pieces, loading chunk c+1 while it computes chunk c.  In
 // piece i lane L owns the 16 start positions [i*1024 + 16L, +16).  Each lane
-// loads its 16 bytes plus the following 16 (32 for long patterns) with
-// dwordx4 buffer loads; the buffer descriptor's record count clamps reads at
+// loads its 16 bytes plus the following 16 (32 for direct compares of
+// patterns longer than 16 bytes) with dwordx4 buffer loads; the buffer descriptor's record count clamps reads at
 // the 16-byte-rounded text end, so the (m-1)-byte halo past a piece (Section
 // 3.3's reason for wsblend) is just the next bytes of the same coalesced
 // stream.
@@ -345,7 +345,7 @@ typedef void (*ScanFn)(ScanArgs);
 // chunks in flight) keep the kernels within about 100 VGPRs.
 template <int WAVES, int PIECES>
 static ScanFn pick(const DevPlan &p) {
-    if (p.variant == 2) return scan_kernel<WAVES, 2, PIECES / 2, 3, 2, 4, 0>;
+    if (p.variant == 2) return scan_kernel<WAVES, 2, PIECES / 2, 2, 2, 4, 0>;
     if (p.nl == 3) return scan_kernel<WAVES, 2, PIECES / 2, 3, 1, 4, 0>;
     switch (p.pk) {
         case 1: return scan_kernel<WAVES, 2, PIECES / 2, 2, 1, 1, 1>;
