@@ -18,6 +18,9 @@ HIPCC_FLAGS = [
     "-fPIC",
     "-shared",
     "-Wall",
+    # the six-waves-per-SIMD register target of the scan kernels is not met
+    # by the tiles whose LDS allows fewer waves; that is expected
+    "-Wno-pass-failed",
     # never emit packed-FP32 instructions (none are needed: integer code)
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-I", os.path.join(ROOT, "include"),

@@ -76,8 +76,8 @@ __global__ __launch_bounds__(WAVES * kWave) void batch_kernel(BatchArgs a) {
         if (p.m > 4u * p.nw && wave_any(mk != 0))
             mk = tail_check(mk, s0, t.base, p.pattern, p.m, 4u * p.nw);
         const uint32_t c = __popc(mk);
-        const uint32_t incl = wave_incl_scan32(c, lane);
-        const uint32_t wtot = __shfl(incl, kWave - 1, kWave);
+        const uint32_t incl = wave_incl_scan32(c);
+        const uint32_t wtot = last_lane(incl);
         if (lane == 0) s_wcnt[wave] = wtot;
         __syncthreads();
         if (!a.write) {

@@ -158,11 +158,25 @@ static __device__ __noinline__ uint32_t tail_check(uint32_t mk, uint64_t s0, con
     return keep;
 }
 
-__device__ __forceinline__ uint32_t wave_sum32(uint32_t v) {
-#pragma unroll
-    for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, kWave);
+// Inclusive prefix sum over the 64 lanes with DPP row shifts (Hillis-Steele
+// inside each row of 16 lanes) and the two row broadcasts of the last lane
+// of rows 0 and 1: six full-rate VALU adds, no LDS permutes.
+__device__ __forceinline__ uint32_t wave_incl_scan32(uint32_t v) {
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x111, 0xF, 0xF, true);   // row_shr:1
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x112, 0xF, 0xF, true);   // row_shr:2
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x114, 0xF, 0xF, true);   // row_shr:4
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x118, 0xF, 0xF, true);   // row_shr:8
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x142, 0xA, 0xF, false);  // row_bcast:15
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x143, 0xC, 0xF, false);  // row_bcast:31
     return v;
 }
+
+// Value of lane 63 (the wave total after an inclusive scan).
+__device__ __forceinline__ uint32_t last_lane(uint32_t v) {
+    return (uint32_t)__builtin_amdgcn_readlane((int)v, kWave - 1);
+}
+
+__device__ __forceinline__ uint32_t wave_sum32(uint32_t v) { return last_lane(wave_incl_scan32(v)); }
 
 __device__ __forceinline__ uint64_t wave_sum64(uint64_t v) {
 #pragma unroll
@@ -170,14 +184,6 @@ __device__ __forceinline__ uint64_t wave_sum64(uint64_t v) {
     return v;
 }
 
-__device__ __forceinline__ uint32_t wave_incl_scan32(uint32_t v, int lane) {
-#pragma unroll
-    for (int d = 1; d < kWave; d <<= 1) {
-        const uint32_t t = __shfl_up(v, d, kWave);
-        if (lane >= d) v += t;
-    }
-    return v;
-}
 
 __device__ __forceinline__ void status_store(uint64_t *p, uint64_t v) {
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -272,12 +278,13 @@ __device__ __forceinline__ void flush_stage(const uint32_t *stage, uint32_t fill
 }
 
 // Write stage[0..fill) as dst[j] = add + stage[j] (tile-relative offsets of
-// a two-phase slot list).  Lanes write consecutive entries.
+// a two-phase slot list), dropping entries at or past `room`.  Lanes write
+// consecutive entries.
 __device__ __forceinline__ void flush_list(const uint32_t *stage, uint32_t fill, uint32_t *dst,
-                                           uint32_t add, int lane) {
+                                           uint32_t room, uint32_t add, int lane) {
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     __builtin_amdgcn_wave_barrier();
-    for (uint32_t j = lane; j < fill; j += kWave) dst[j] = add + stage[j];
+    for (uint32_t j = lane; j < fill && j < room; j += kWave) dst[j] = add + stage[j];
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     __builtin_amdgcn_wave_barrier();
 }

@@ -81,6 +81,9 @@ constexpr uint32_t kWriteTwoPhase = 2;
 // two-phase write.
 constexpr uint32_t kGroupTiles = 64;
 constexpr uint32_t kExpandTiles = 8;
+// Output capacity per tile up to which expand workgroups take kExpandTiles
+// tiles (above it, one tile each).
+constexpr uint64_t kExpandFewPerTile = 64;
 
 // ---- batched search -------------------------------------------------------
 // A unit is one tile of one text; its workgroup loads the tile once and runs

@@ -63,8 +63,8 @@ __device__ __forceinline__ void expand_masks(const uint32_t (*masks)[THREADS], u
         const uint32_t mk = (masks[piece >> 1][tid] >> ((piece & 1) * 16)) & 0xFFFFu;
         const uint32_t c = __popc(mk);
         if (!wave_any(c != 0)) continue;
-        const uint32_t incl = wave_incl_scan32(c, lane);
-        const uint32_t tot = __shfl(incl, kWave - 1, kWave);
+        const uint32_t incl = wave_incl_scan32(c);
+        const uint32_t tot = last_lane(incl);
         if (fill + tot > kStage) {
             sink(stage, fill, done);
             done += fill;
@@ -104,8 +104,14 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t tile_rsrc(const ScanArgs &a, u
 // tile publishes its count as soon as it is computed, independently of the
 // other tiles' look-back and write phases; a look-back only waits on lower
 // workgroup indices, which in-order dispatch has already started.
+// Six waves per SIMD (at most 80 VGPRs) for the two-load kernels: one more
+// resident wave per SIMD than 88 VGPRs would allow, which the streaming
+// loads need.  The three-load direct kernel keeps its registers.  Tiles
+// whose LDS admits fewer waves (4x32, 16x8, 16x16) do not reach the target;
+// their register use is left as it is.
 template <int WAVES, int U, int C, int NL, int VAR, int PK, int NW>
-__global__ __launch_bounds__(WAVES * kWave, 4) void scan_kernel(ScanArgs a) {
+__global__ __launch_bounds__(WAVES * kWave) __attribute__((amdgpu_waves_per_eu(NL == 2 ? 6 : 4)))
+void scan_kernel(ScanArgs a) {
     constexpr int kThreads = WAVES * kWave;
     constexpr int kPieces = U * C;  // pieces per wave per tile
     constexpr uint32_t kWaveSpan = kPieces * kWavePiece;
@@ -178,9 +184,11 @@ __global__ __launch_bounds__(WAVES * kWave, 4) void scan_kernel(ScanArgs a) {
         for (int i = 0; i < wave; ++i) before += s_wcnt[i];
         uint32_t *dst = slot + before;
         const uint32_t wave_off = (uint32_t)wave * kWaveSpan;
+        const uint32_t room = kSlotWords - before;  // the slot's end bounds every write
         expand_masks<kPieces, kThreads>(s_mask, s_stage[wave], tid, lane,
                                         [&](const uint32_t *st, uint32_t fill, uint32_t done) {
-                                            flush_list(st, fill, dst + done, wave_off, lane);
+                                            flush_list(st, fill, dst + done,
+                                                       done < room ? room - done : 0u, wave_off, lane);
                                         });
         return;
     }
@@ -268,15 +276,15 @@ __global__ __launch_bounds__(WAVES * kWave) void expand_kernel(ScanArgs a) {
         const int64_t tile_pos0 = (int64_t)(t * kTile) - (int64_t)a.delta;
         if (tot <= kSlotWords) {
             const uint32_t *slot = a.slots + t * kSlotWords;
-            for (uint32_t j0 = 0; j0 < tot; j0 += 4 * kThreads) {
-                uint32_t r[4];
+            for (uint32_t j0 = 0; j0 < tot; j0 += 8 * kThreads) {
+                uint32_t r[8];
 #pragma unroll
-                for (int u = 0; u < 4; ++u) {
+                for (int u = 0; u < 8; ++u) {
                     const uint32_t j = j0 + u * kThreads + tid;
                     r[u] = j < tot ? slot[j] : 0;
                 }
 #pragma unroll
-                for (int u = 0; u < 4; ++u) {
+                for (int u = 0; u < 8; ++u) {
                     const uint32_t j = j0 + u * kThreads + tid;
                     if (j < tot && pos + j < a.cap) a.out[pos + j] = tile_pos0 + r[u];
                 }
@@ -419,7 +427,10 @@ static ExpandFn pick_expand(TileConfig cfg) {
 hipError_t launch_expand(ScanArgs a, TileConfig cfg, hipStream_t s) {
     ExpandFn fn = pick_expand(cfg);
     if (!fn) return hipErrorInvalidValue;
-    a.expand_tiles = kExpandTiles;
+    // A few positions per tile: 8 tiles per workgroup, so the counts before
+    // the workgroup are read by fewer workgroups.  More: one tile each, so
+    // that every list is copied by its own workgroup in parallel.
+    a.expand_tiles = a.cap <= (uint64_t)a.num_tiles * kExpandFewPerTile ? kExpandTiles : 1;
     const uint32_t grid = (a.num_tiles + a.expand_tiles - 1) / a.expand_tiles;
     hipLaunchKernelGGL(fn, dim3(grid), dim3(cfg.waves * kWave), 0, s, a);
     return hipGetLastError();
