@@ -155,6 +155,11 @@ typedef struct {
 } epsm_pair_ref;
 
 #define EPSM_BATCH_COUNT_ONLY 0x1u
+/* Filter every pair on its own in the count pass.  By default a text with at
+ * least 4 patterns of m >= 4 counts them in groups of up to 32 through one
+ * shared filter (a bucket table of their first four bytes, then an exact
+ * check); the output is the same either way. */
+#define EPSM_BATCH_NO_GROUPS 0x2u
 
 typedef struct {
     const epsm_text_ref *texts;  /* host array [n_texts] */

@@ -179,7 +179,7 @@ class Batch:
     """
 
     def __init__(self, texts, pairs, out=None, counts=None, offsets=None, total=None,
-                 count_only: bool = False):
+                 count_only: bool = False, groups: bool = True):
         for t in texts:
             _check_text(t)
         self.texts = list(texts)
@@ -209,7 +209,7 @@ class Batch:
         b.d_counts = self.counts.data_ptr()
         b.d_offsets = self.offsets.data_ptr()
         b.d_total = self.total.data_ptr()
-        b.flags = BATCH_COUNT_ONLY if count_only else 0
+        b.flags = (BATCH_COUNT_ONLY if count_only else 0) | (0 if groups else _lib.BATCH_NO_GROUPS)
         self.struct = b
 
     def run(self, stream=None) -> None:
@@ -248,19 +248,20 @@ class BatchPlan:
             pass
 
 
-def search_batch(texts, pairs, stream=None):
+def search_batch(texts, pairs, stream=None, groups: bool = True):
     """All (text, pattern) pairs; returns (positions, counts, offsets) as int64 tensors.
 
     pairs: iterable of (text index, Plan or bytes).  Runs a count-only batch to
-    size the output, then the full batch.
+    size the output, then the full batch.  groups=False filters every pair on
+    its own in the count pass (EPSM_BATCH_NO_GROUPS).
     """
     pairs = [(ti, _as_plan(p)) for ti, p in pairs]
-    b0 = Batch(texts, pairs, count_only=True)
+    b0 = Batch(texts, pairs, count_only=True, groups=groups)
     b0.run(stream)
     total = int(b0.total.item())
     dev = texts[0].device if texts else torch.device("cuda")
     out = torch.empty(max(total, 1), dtype=torch.int64, device=dev)
-    b1 = Batch(texts, pairs, out=out[:total] if total else None)
+    b1 = Batch(texts, pairs, out=out[:total] if total else None, groups=groups)
     b1.run(stream)
     n = len(pairs)
     return out[:total], b1.counts[:n], b1.offsets[:n]

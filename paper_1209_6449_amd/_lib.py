@@ -33,6 +33,7 @@ CLASS_WORDS = 1
 CLASS_FINGERPRINT = 2
 N_CLASSES = 3
 BATCH_COUNT_ONLY = 0x1
+BATCH_NO_GROUPS = 0x2
 MAX_M = 4096
 
 

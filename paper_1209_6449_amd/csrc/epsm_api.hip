@@ -244,13 +244,18 @@ int g_batch_waves = 8;  // batch tile = g_batch_waves KiB
 
 BatchPtrs batch_ptrs(uint8_t *base, const BatchLayout &L) {
     return {(BatchTextDesc *)(base + L.texts), (BatchPairDesc *)(base + L.pairs),
-            (uint32_t *)(base + L.order), (BatchUnit *)(base + L.units), (uint32_t *)(base + L.ptc),
-            (uint64_t *)(base + L.pto), (uint64_t *)(base + L.bsum)};
+            (uint32_t *)(base + L.order), (uint32_t *)(base + L.solo),
+            (BatchGroupDesc *)(base + L.groups), (uint32_t *)(base + L.gpairs),
+            (uint32_t *)(base + L.gtables), (BatchUnit *)(base + L.units),
+            (uint32_t *)(base + L.ptc), (uint64_t *)(base + L.pto), (uint64_t *)(base + L.bsum)};
 }
 
-epsm_status build_batch(const epsm_batch *b, int waves, HostBatch &hb, bool check_outputs) {
+epsm_status build_batch(const epsm_batch *b, int waves, HostBatch &hb, bool check_outputs,
+                        bool group) {
     if (!b) return fail(EPSM_EINVAL, "batch is NULL");
-    if (b->flags & ~EPSM_BATCH_COUNT_ONLY) return fail(EPSM_EINVAL, "unknown batch flags");
+    if (b->flags & ~(EPSM_BATCH_COUNT_ONLY | EPSM_BATCH_NO_GROUPS))
+        return fail(EPSM_EINVAL, "unknown batch flags");
+    if (b->flags & EPSM_BATCH_NO_GROUPS) group = false;
     if (b->n_texts && !b->texts) return fail(EPSM_EINVAL, "texts is NULL");
     if (b->n_pairs && !b->pairs) return fail(EPSM_EINVAL, "pairs is NULL");
     if (check_outputs) {
@@ -338,6 +343,36 @@ epsm_status build_batch(const epsm_batch *b, int waves, HostBatch &hb, bool chec
         hb.texts[i].pair_end = start[i + 1];
         if (text_pairs[i]) units += text_tiles[i];
     }
+    // count pass: a text with at least kGroupMin patterns of m >= 4 filters
+    // them in groups of up to kGroupMax through one bucket table of their
+    // first four bytes; its other pairs are filtered one by one
+    for (uint32_t i = 0; i < b->n_texts; ++i) {
+        BatchTextDesc &d = hb.texts[i];
+        uint32_t words = 0;
+        for (uint32_t q = start[i]; q < start[i + 1]; ++q) words += hb.pairs[hb.order[q]].plan.m >= 4;
+        const bool grouped = group && words >= kGroupMin;
+        d.solo_begin = (uint32_t)hb.solo.size();
+        for (uint32_t q = start[i]; q < start[i + 1]; ++q)
+            if (!grouped || hb.pairs[hb.order[q]].plan.m < 4) hb.solo.push_back(hb.order[q]);
+        d.solo_end = (uint32_t)hb.solo.size();
+        d.group_begin = (uint32_t)hb.groups.size();
+        if (grouped) {
+            for (uint32_t q = start[i]; q < start[i + 1]; ++q) {
+                const uint32_t k = hb.order[q];
+                if (hb.pairs[k].plan.m < 4) continue;
+                if (hb.groups.size() == d.group_begin || hb.groups.back().count == kGroupMax) {
+                    hb.groups.push_back({(uint32_t)hb.group_pairs.size(), 0});
+                    hb.group_tables.resize(hb.group_tables.size() + kGroupBuckets, 0);
+                }
+                BatchGroupDesc &g = hb.groups.back();
+                const uint32_t bucket = group_bucket(hb.pairs[k].plan.pw[0]);
+                hb.group_tables[(hb.groups.size() - 1) * kGroupBuckets + bucket] |= 1u << g.count;
+                hb.group_pairs.push_back(k);
+                g.count++;
+            }
+        }
+        d.group_end = (uint32_t)hb.groups.size();
+    }
     if (units > 0x7FFFFFFFull) return fail(EPSM_EUNSUPPORTED, "batch has too many tiles");
     hb.units.reserve(units);
     for (uint32_t i = 0; i < b->n_texts; ++i)
@@ -362,6 +397,10 @@ epsm_status upload_batch(HostBatch &hb, const BatchLayout &L, uint8_t *dev, hipS
     put(P.texts, hb.texts.data(), hb.texts.size() * sizeof(BatchTextDesc));
     put(P.pairs, hb.pairs.data(), hb.pairs.size() * sizeof(BatchPairDesc));
     put(P.order, hb.order.data(), hb.order.size() * sizeof(uint32_t));
+    put(P.solo, hb.solo.data(), hb.solo.size() * sizeof(uint32_t));
+    put(P.groups, hb.groups.data(), hb.groups.size() * sizeof(BatchGroupDesc));
+    put(P.gpairs, hb.group_pairs.data(), hb.group_pairs.size() * sizeof(uint32_t));
+    put(P.gtables, hb.group_tables.data(), hb.group_tables.size() * sizeof(uint32_t));
     put(P.units, hb.units.data(), hb.units.size() * sizeof(BatchUnit));
     // pageable sources: the copies are staged before hipMemcpyAsync returns,
     // but finish them here so the host vectors can be released safely
@@ -377,6 +416,10 @@ epsm_status run_batch_count(const BatchPtrs &P, const HostBatch &hb, const epsm_
     a.texts = P.texts;
     a.pairs = P.pairs;
     a.pair_order = P.order;
+    a.solo_order = P.solo;
+    a.groups = P.groups;
+    a.group_pairs = P.gpairs;
+    a.group_tables = P.gtables;
     a.units = P.units;
     a.pt_count = P.ptc;
     a.pt_offset = P.pto;

@@ -34,8 +34,56 @@ __device__ __forceinline__ uint32_t any_mask(const uint32_t (&w)[kBatchNL * 4 + 
     }
 }
 
+// Window of 4 text bytes at byte `off` of a wave's LDS copy of its piece.
+__device__ __forceinline__ uint32_t lds_window(const uint32_t *tw, uint32_t off) {
+    const uint32_t q = off >> 2, r = off & 3;
+    return r == 0 ? tw[q] : __builtin_amdgcn_alignbyte(tw[q + 1], tw[q], r);
+}
+
+// Words of a wave's LDS copy of its text piece: the piece's 1024 bytes, the
+// 32 bytes after it, and one zero word for the last window.
+constexpr uint32_t kTextWords = kWavePiece / 4 + 8 + 1;
+
+// Multi-pattern count of one lane piece against group g (staged in LDS):
+// each of the 16 windows is looked up in the bucket table; a window whose
+// bucket is not empty is compared with the first word of every member in it,
+// then with the member's remaining words (from the LDS copy of the piece,
+// up to 32 bytes) and, past 32 bytes, the tail check.  Hits of member j are
+// added to s_cnt[j].
+__device__ __forceinline__ void group_count(const uint32_t (&w)[kBatchNL * 4 + 1], const uint32_t *tw,
+                                            const uint32_t *s_tab, const uint32_t (*s_pw)[8],
+                                            const uint32_t (*s_pm)[8], const uint64_t *s_m,
+                                            const uint8_t *const *s_pat, uint32_t *s_cnt,
+                                            const BatchTextDesc &t, uint64_t s0, uint32_t lane_byte) {
+    uint32_t cand = 0;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) cand |= (s_tab[group_bucket(window(w, k))] != 0 ? 1u : 0u) << k;
+    while (cand) {
+        const uint32_t k = __builtin_ctz(cand);
+        cand &= cand - 1;
+        const uint32_t off = lane_byte + k;
+        const uint32_t x = lds_window(tw, off);
+        uint32_t members = s_tab[group_bucket(x)];
+        const uint64_t s = s0 + k;
+        while (members) {
+            const uint32_t j = __builtin_ctz(members);
+            members &= members - 1;
+            if (x != s_pw[j][0]) continue;
+            const uint64_t m = s_m[j];
+            if (s < t.delta || s > t.delta + t.n - m) continue;
+            const uint32_t nw = m >= 32 ? 8u : (uint32_t)((m + 3) / 4);
+            bool ok = true;
+            for (uint32_t i = 1; i < nw && ok; ++i)
+                ok = (lds_window(tw, off + 4 * i) & s_pm[j][i]) == s_pw[j][i];
+            if (ok && m > 32) ok = tail_check(1u, s, t.base, s_pat[j], m, 32) != 0;
+            if (ok) atomicAdd(&s_cnt[j], 1u);
+        }
+    }
+}
+
 template <int WAVES>
 __global__ __launch_bounds__(WAVES * kWave) void batch_kernel(BatchArgs a) {
+    constexpr int kThreads = WAVES * kWave;
     constexpr uint32_t kTileB = WAVES * kWavePiece;
     __shared__ uint32_t s_wcnt[WAVES];
     __shared__ uint32_t s_stage[WAVES][kStage];
@@ -61,10 +109,15 @@ __global__ __launch_bounds__(WAVES * kWave) void batch_kernel(BatchArgs a) {
     }
     w[kBatchNL * 4] = 0;
 
+    // the count pass filters the solo pairs one by one and the groups
+    // together; the write pass redoes, pair by pair, only entries with hits
+    const uint32_t *order = a.write ? a.pair_order : a.solo_order;
+    const uint32_t pb = a.write ? t.pair_begin : t.solo_begin;
+    const uint32_t pe = a.write ? t.pair_end : t.solo_end;
     const int64_t wave_pos0 = (int64_t)(tile_start + (uint64_t)wave * kWavePiece) - (int64_t)t.delta;
 #pragma unroll 1
-    for (uint32_t pi = t.pair_begin; pi < t.pair_end; ++pi) {
-        const uint32_t pidx = a.pair_order[pi];
+    for (uint32_t pi = pb; pi < pe; ++pi) {
+        const uint32_t pidx = order[pi];
         const BatchPairDesc &pd = a.pairs[pidx];
         if (pd.tiles == 0) continue;  // m > n: the pair has no entries
         const uint64_t entry = pd.cnt_base + unit.tile;
@@ -101,6 +154,48 @@ __global__ __launch_bounds__(WAVES * kWave) void batch_kernel(BatchArgs a) {
             flush_stage(s_stage[wave], wtot, a.out, a.cap, obase, wave_pos0, lane);
         }
         __syncthreads();  // s_wcnt is rewritten by the next pattern
+    }
+    if (a.write || t.group_begin == t.group_end) return;
+
+    // groups: the piece goes to LDS once (windows at run-time offsets), then
+    // each group's table, first words and lengths are staged in turn
+    __shared__ uint32_t s_text[WAVES][kTextWords];
+    __shared__ uint32_t s_tab[kGroupBuckets];
+    __shared__ uint32_t s_pw[kGroupMax][8], s_pm[kGroupMax][8];
+    __shared__ uint64_t s_m[kGroupMax];
+    __shared__ const uint8_t *s_pat[kGroupMax];
+    __shared__ uint32_t s_cnt[kGroupMax];
+    uint32_t *tw = s_text[wave];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) tw[lane * 4 + i] = w[i];
+    if (lane == kWave - 1) {
+#pragma unroll
+        for (int i = 0; i < 8; ++i) tw[kWavePiece / 4 + i] = w[4 + i];
+        tw[kTextWords - 1] = 0;
+    }
+#pragma unroll 1
+    for (uint32_t g = t.group_begin; g < t.group_end; ++g) {
+        const BatchGroupDesc gd = a.groups[g];
+        const uint32_t *gt = a.group_tables + (size_t)g * kGroupBuckets;
+        for (uint32_t i = tid; i < kGroupBuckets; i += kThreads) s_tab[i] = gt[i];
+        for (uint32_t i = tid; i < gd.count * 8; i += kThreads) {
+            const DevPlan &p = a.pairs[a.group_pairs[gd.first + i / 8]].plan;
+            s_pw[i / 8][i % 8] = p.pw[i % 8];
+            s_pm[i / 8][i % 8] = p.pmask[i % 8];
+            if (i % 8 == 0) {
+                s_m[i / 8] = p.m;
+                s_pat[i / 8] = p.pattern;
+                s_cnt[i / 8] = 0;
+            }
+        }
+        __syncthreads();
+        group_count(w, tw, s_tab, s_pw, s_pm, s_m, s_pat, s_cnt, t, s0, (uint32_t)lane * kPiece);
+        __syncthreads();
+        if ((uint32_t)tid < gd.count) {
+            const BatchPairDesc &pd = a.pairs[a.group_pairs[gd.first + tid]];
+            a.pt_count[pd.cnt_base + unit.tile] = s_cnt[tid];
+        }
+        __syncthreads();  // s_cnt and the staged group are rewritten next
     }
 }
 

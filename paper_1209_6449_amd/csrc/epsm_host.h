@@ -40,6 +40,10 @@ struct HostBatch {
     std::vector<BatchTextDesc> texts;
     std::vector<BatchPairDesc> pairs;
     std::vector<uint32_t> order;
+    std::vector<uint32_t> solo;            // count pass: pairs filtered alone
+    std::vector<BatchGroupDesc> groups;    // count pass: pattern groups
+    std::vector<uint32_t> group_pairs;
+    std::vector<uint32_t> group_tables;    // kGroupBuckets per group
     std::vector<BatchUnit> units;
     // device data of host-only plans (fingerprint tables, long patterns),
     // uploaded with the descriptors; per pair the blob offsets (or kNoBlob)
@@ -53,7 +57,7 @@ constexpr uint64_t kNoBlob = ~uint64_t(0);
 // Byte layout of the device copy of a batch: descriptors, then the
 // (pair, tile) counts, their offsets and the scan's block sums.
 struct BatchLayout {
-    size_t blob, texts, pairs, order, units, ptc, pto, bsum, total;
+    size_t blob, texts, pairs, order, solo, groups, gpairs, gtables, units, ptc, pto, bsum, total;
     explicit BatchLayout(const HostBatch &hb) {
         auto up = [](size_t x) { return (x + 255) & ~size_t(255); };
         size_t at = 0;
@@ -61,6 +65,10 @@ struct BatchLayout {
         texts = at; at += up(hb.texts.size() * sizeof(BatchTextDesc));
         pairs = at; at += up(hb.pairs.size() * sizeof(BatchPairDesc));
         order = at; at += up(hb.order.size() * sizeof(uint32_t));
+        solo = at; at += up(hb.solo.size() * sizeof(uint32_t));
+        groups = at; at += up(hb.groups.size() * sizeof(BatchGroupDesc));
+        gpairs = at; at += up(hb.group_pairs.size() * sizeof(uint32_t));
+        gtables = at; at += up(hb.group_tables.size() * sizeof(uint32_t));
         units = at; at += up(hb.units.size() * sizeof(BatchUnit));
         ptc = at; at += up(hb.entries * sizeof(uint32_t));
         pto = at; at += up((hb.entries + 1) * sizeof(uint64_t));
@@ -73,6 +81,10 @@ struct BatchPtrs {
     BatchTextDesc *texts;
     BatchPairDesc *pairs;
     uint32_t *order;
+    uint32_t *solo;
+    BatchGroupDesc *groups;
+    uint32_t *gpairs;
+    uint32_t *gtables;
     BatchUnit *units;
     uint32_t *ptc;
     uint64_t *pto;
@@ -81,8 +93,10 @@ struct BatchPtrs {
 
 BatchPtrs batch_ptrs(uint8_t *base, const BatchLayout &L);
 // Validate a batch and build its work descriptors (check_outputs: require
-// the output pointers of the epsm_batch).
-epsm_status build_batch(const epsm_batch *b, int waves, HostBatch &hb, bool check_outputs);
+// the output pointers of the epsm_batch).  group: gather the patterns of a
+// text into multi-pattern groups for the count pass.
+epsm_status build_batch(const epsm_batch *b, int waves, HostBatch &hb, bool check_outputs,
+                        bool group = true);
 // Copy descriptors (and host-only plan data) to `dev`; synchronises `s`.
 epsm_status upload_batch(HostBatch &hb, const BatchLayout &L, uint8_t *dev, hipStream_t s);
 epsm_status run_batch_count(const BatchPtrs &P, const HostBatch &hb, const epsm_batch_outputs &o,

@@ -96,7 +96,33 @@ struct BatchTextDesc {
     uint64_t load_end;       // round_up(delta + n, 16)
     uint32_t pair_begin;     // this text's pairs are pair_order[pair_begin, pair_end)
     uint32_t pair_end;
+    uint32_t solo_begin;     // count pass: pairs filtered one by one,
+    uint32_t solo_end;       //   solo_order[solo_begin, solo_end)
+    uint32_t group_begin;    // count pass: pattern groups filtered together,
+    uint32_t group_end;      //   groups[group_begin, group_end)
 };
+
+// Multi-pattern count (several patterns of one text through one filter).
+// A group holds up to kGroupMax patterns of m >= 4 aimed at one text; its
+// bucket table maps the hash of a 4-byte window to the set of group members
+// (bit j) whose first four bytes hash there.
+constexpr uint32_t kGroupMax = 32;
+constexpr int kGroupBits = 10;
+constexpr uint32_t kGroupBuckets = 1u << kGroupBits;
+// A text's word patterns are grouped only when it has at least this many.
+constexpr uint32_t kGroupMin = 4;
+
+struct BatchGroupDesc {
+    uint32_t first;          // members are group_pairs[first, first + count)
+    uint32_t count;
+};
+
+// Bucket of a 4-byte window x (little endian): fold the top byte into the
+// low 24 bits, one 24-bit multiply, keep the top kGroupBits bits.
+__host__ __device__ inline uint32_t group_bucket(uint32_t x) {
+    const uint32_t y = (x ^ (x >> 16)) & 0xFFFFFFu;
+    return (y * 0x9E3779u) >> (32 - kGroupBits);
+}
 
 struct BatchPairDesc {
     DevPlan plan;
@@ -114,6 +140,10 @@ struct BatchArgs {
     const BatchTextDesc *texts;
     const BatchPairDesc *pairs;
     const uint32_t *pair_order;
+    const uint32_t *solo_order;
+    const BatchGroupDesc *groups;
+    const uint32_t *group_pairs;
+    const uint32_t *group_tables;  // [groups][kGroupBuckets]
     const BatchUnit *units;
     uint32_t *pt_count;        // [entries] hits of each (pair, tile)
     const uint64_t *pt_offset; // [entries + 1] exclusive prefix of pt_count (write pass)

@@ -197,3 +197,56 @@ def test_long_patterns_in_batch(epsm):
     pos, counts, offsets = pos.cpu().numpy(), counts.cpu().numpy(), offsets.cpu().numpy()
     for k, (ti, plan) in enumerate(plans):
         assert np.array_equal(pos[offsets[k]:offsets[k] + counts[k]], oracle.positions(t, plan.pattern)), k
+
+
+def group_batch(seed, n_texts=12, n_pat=70):
+    """Texts with many patterns each (several 32-pattern groups): patterns
+    sharing their first four bytes (same bucket, different tails), m from 4
+    to 100 (past the 32 bytes checked from LDS), dense binary texts, cuts at
+    both ends of the text, unaligned starts."""
+    rng = np.random.default_rng(seed)
+    texts, host, pairs = [], [], []
+    for i in range(n_texts):
+        n = int(rng.integers(1, 200_000)) if i % 5 else int(rng.integers(1, 64))
+        sigma = [2, 4, 64][i % 3]
+        t = rng.integers(0, sigma, n).astype(np.uint8)
+        off = int(rng.integers(0, 16))
+        buf = torch.zeros(n + off + 1, dtype=torch.uint8, device="cuda")
+        if n:
+            buf[off:off + n] = torch.from_numpy(t).cuda()
+        texts.append(buf[off:off + n])
+        host.append(t)
+        stem = rng.integers(0, sigma, 4).astype(np.uint8).tobytes()
+        for j in range(n_pat):
+            m = int(rng.choice([1, 3, 4, 5, 8, 15, 16, 17, 31, 32, 33, 40, 64, 100]))
+            r = rng.random()
+            if n >= m and r < 0.4:
+                o = [0, n - m, int(rng.integers(0, n - m + 1))][j % 3]
+                p = t[o:o + m].tobytes()
+            elif r < 0.7 and m >= 4:
+                p = stem + rng.integers(0, sigma, m - 4).astype(np.uint8).tobytes()
+            else:
+                p = rng.integers(0, sigma, m).astype(np.uint8).tobytes()
+            pairs.append((i, p))
+    return texts, host, pairs
+
+
+@pytest.mark.parametrize("waves", [4, 16])
+def test_grouped_count_equals_ungrouped_and_oracle(epsm, waves):
+    epsm.set_batch_config(waves)
+    try:
+        texts, host, pairs = group_batch(seed=100 + waves)
+        plans = [(ti, epsm.Plan(p, epsm.PLAN_HOST_ONLY if k % 2 else 0)) for k, (ti, p) in enumerate(pairs)]
+        say(f"grouped batch waves={waves} pairs={len(plans)}")
+        g = [x.cpu().numpy() for x in epsm.search_batch(texts, plans, groups=True)]
+        say("ungrouped")
+        u = [x.cpu().numpy() for x in epsm.search_batch(texts, plans, groups=False)]
+        epsm.stream_check()
+        for a, b in zip(g, u):
+            assert np.array_equal(a, b)
+        pos, counts, offsets = g
+        for k, (ti, plan) in enumerate(plans):
+            exp = oracle.positions(host[ti], plan.pattern)
+            assert np.array_equal(pos[offsets[k]:offsets[k] + counts[k]], exp), (k, ti, plan.m)
+    finally:
+        epsm.set_batch_config(8)
