@@ -15,6 +15,7 @@
 namespace epsm {
 
 constexpr int kBatchNL = 3;  // 48 bytes per lane: any m <= 32 verified from registers
+constexpr uint32_t kPairChunk = 32;  // pair descriptors staged in LDS at a time
 
 // Mask of one lane piece for a runtime-described pattern.
 __device__ __forceinline__ uint32_t any_mask(const uint32_t (&w)[kBatchNL * 4 + 1], const DevPlan &p) {
@@ -110,50 +111,72 @@ __global__ __launch_bounds__(WAVES * kWave) void batch_kernel(BatchArgs a) {
     w[kBatchNL * 4] = 0;
 
     // the count pass filters the solo pairs one by one and the groups
-    // together; the write pass redoes, pair by pair, only entries with hits
+    // together; the write pass redoes, pair by pair, only entries with hits.
+    // Pair descriptors are staged in LDS a chunk at a time, so the loop over
+    // pairs waits on no global load.
     const uint32_t *order = a.write ? a.pair_order : a.solo_order;
     const uint32_t pb = a.write ? t.pair_begin : t.solo_begin;
     const uint32_t pe = a.write ? t.pair_end : t.solo_end;
     const int64_t wave_pos0 = (int64_t)(tile_start + (uint64_t)wave * kWavePiece) - (int64_t)t.delta;
+    constexpr uint32_t kDescWords = sizeof(BatchPairDesc) / 4;
+    static_assert(sizeof(BatchPairDesc) % 4 == 0, "descriptors are copied as words");
+    __shared__ BatchPairDesc s_pd[kPairChunk];
+    __shared__ uint32_t s_pcnt[kPairChunk];
+    __shared__ uint64_t s_poff[kPairChunk];
 #pragma unroll 1
-    for (uint32_t pi = pb; pi < pe; ++pi) {
-        const uint32_t pidx = order[pi];
-        const BatchPairDesc &pd = a.pairs[pidx];
-        if (pd.tiles == 0) continue;  // m > n: the pair has no entries
-        const uint64_t entry = pd.cnt_base + unit.tile;
-        if (a.write && a.pt_count[entry] == 0) continue;
-        const DevPlan &p = pd.plan;
-        uint32_t mk = any_mask(w, p);
-        const uint64_t last = t.delta + t.n - p.m;  // m <= n here
-        if (tile_start + kTileB > last || tile_start < t.delta) mk &= valid_mask(s0, t.delta, last);
-        if (p.m > 4u * p.nw && wave_any(mk != 0))
-            mk = tail_check(mk, s0, t.base, p.pattern, p.m, 4u * p.nw);
-        const uint32_t c = __popc(mk);
-        const uint32_t incl = wave_incl_scan32(c);
-        const uint32_t wtot = last_lane(incl);
-        if (lane == 0) s_wcnt[wave] = wtot;
-        __syncthreads();
-        if (!a.write) {
-            if (tid == 0) {
-                uint32_t total = 0;
-#pragma unroll
-                for (int i = 0; i < WAVES; ++i) total += s_wcnt[i];
-                a.pt_count[entry] = total;
-            }
-        } else if (wtot) {
-            uint64_t obase = a.pt_offset[entry];
-            for (int i = 0; i < wave; ++i) obase += s_wcnt[i];
-            uint32_t at = incl - c;
-            const uint32_t rel0 = (uint32_t)lane * kPiece;
-            uint32_t bits = mk;
-            while (bits) {
-                const uint32_t k = __builtin_ctz(bits);
-                bits &= bits - 1;
-                s_stage[wave][at++] = rel0 + k;
-            }
-            flush_stage(s_stage[wave], wtot, a.out, a.cap, obase, wave_pos0, lane);
+    for (uint32_t cb = pb; cb < pe; cb += kPairChunk) {
+        const uint32_t nc = min(kPairChunk, pe - cb);
+        for (uint32_t i = tid; i < nc * kDescWords; i += kThreads)
+            reinterpret_cast<uint32_t *>(s_pd)[i] =
+                reinterpret_cast<const uint32_t *>(&a.pairs[order[cb + i / kDescWords]])[i % kDescWords];
+        if ((uint32_t)tid < nc) {
+            const BatchPairDesc &pd = a.pairs[order[cb + tid]];
+            const uint64_t entry = pd.cnt_base + unit.tile;
+            const bool live = pd.tiles != 0;  // m > n: the pair has no entries
+            s_pcnt[tid] = a.write && live ? a.pt_count[entry] : 0;
+            s_poff[tid] = a.write && live ? a.pt_offset[entry] : 0;
         }
-        __syncthreads();  // s_wcnt is rewritten by the next pattern
+        __syncthreads();
+#pragma unroll 1
+        for (uint32_t j = 0; j < nc; ++j) {
+            const BatchPairDesc &pd = s_pd[j];
+            if (pd.tiles == 0) continue;
+            if (a.write && s_pcnt[j] == 0) continue;
+            const DevPlan &p = pd.plan;
+            uint32_t mk = any_mask(w, p);
+            const uint64_t last = t.delta + t.n - p.m;  // m <= n here
+            if (tile_start + kTileB > last || tile_start < t.delta) mk &= valid_mask(s0, t.delta, last);
+            if (p.m > 4u * p.nw && wave_any(mk != 0))
+                mk = tail_check(mk, s0, t.base, p.pattern, p.m, 4u * p.nw);
+            const uint32_t c = __popc(mk);
+            const uint32_t incl = wave_incl_scan32(c);
+            const uint32_t wtot = last_lane(incl);
+            if (!a.write) {
+                // count pass: waves add their totals; no barrier per pair
+                if (lane == 0 && wtot) atomicAdd(&s_pcnt[j], wtot);
+                continue;
+            }
+            if (lane == 0) s_wcnt[wave] = wtot;
+            __syncthreads();
+            if (wtot) {
+                uint64_t obase = s_poff[j];
+                for (int i = 0; i < wave; ++i) obase += s_wcnt[i];
+                uint32_t at = incl - c;
+                const uint32_t rel0 = (uint32_t)lane * kPiece;
+                uint32_t bits = mk;
+                while (bits) {
+                    const uint32_t k = __builtin_ctz(bits);
+                    bits &= bits - 1;
+                    s_stage[wave][at++] = rel0 + k;
+                }
+                flush_stage(s_stage[wave], wtot, a.out, a.cap, obase, wave_pos0, lane);
+            }
+            __syncthreads();  // s_wcnt is rewritten by the next pattern
+        }
+        __syncthreads();
+        if (!a.write && (uint32_t)tid < nc && s_pd[tid].tiles)
+            a.pt_count[s_pd[tid].cnt_base + unit.tile] = s_pcnt[tid];
+        __syncthreads();  // the next chunk restages s_pd and s_pcnt
     }
     if (a.write || t.group_begin == t.group_end) return;
 
