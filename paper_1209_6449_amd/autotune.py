@@ -27,7 +27,7 @@ import time
 import torch
 
 from . import (CLASS_BYTES, CLASS_FINGERPRINT, CLASS_WORDS, PLAN_HASH_BITS, PLAN_HOST_ONLY,
-               WRITE_AUTO, WRITE_SINGLE_PASS, WRITE_TWO_PHASE, Batch, Plan, count_into, lib,
+               WRITE_AUTO, WRITE_SINGLE_PASS, WRITE_TWO_PHASE, Batch, BatchPlan, Plan, count_into, lib,
                search_into, set_batch_config, set_default_hash_bits, set_tile_config,
                set_tune_table, stream_check, tile_configs)
 
@@ -204,8 +204,9 @@ def tune_hash_bits(rows, n: int = 1 << 28, reps: int = 5, log=print) -> tuple[in
 
 
 def tune_batch(n_texts: int = 400, max_len: int = 1 << 22, reps: int = 3, log=print) -> tuple[int, dict]:
-    """Batch tile (KiB per text tile): least time of a prepared-free batch
-    call over seeded texts of log-uniform length with 1..32 patterns each."""
+    """Batch tile (KiB per text tile): least device time of a prepared batch
+    (its captured graph replayed) over seeded texts of log-uniform length with
+    1..32 patterns each; every tile must give the same output."""
     import random
     r = random.Random(4242)
     texts, pairs = [], []
@@ -226,14 +227,16 @@ def tune_batch(n_texts: int = 400, max_len: int = 1 << 22, reps: int = 3, log=pr
     for w in BATCH_WAVES:
         set_batch_config(w)
         b = Batch(texts, pairs, out=out)
-        b.run()
+        bp = BatchPlan(b)
+        bp.launch()
         torch.cuda.synchronize()
         got = (out[:total].clone(), b.counts[:len(pairs)].clone())
         if ref is None:
             ref = got
         elif not (torch.equal(ref[0], got[0]) and torch.equal(ref[1], got[1])):
             raise RuntimeError(f"batch tile {w}: output differs")
-        t = _time_ms(b.run, reps)
+        t = _time_ms(bp.launch, reps)
+        bp.close()
         per[str(w)] = round(t, 4)
         if best_ms is None or t < best_ms:
             best, best_ms = w, t
