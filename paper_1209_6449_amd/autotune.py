@@ -160,9 +160,12 @@ def tune_tiles(sizes=DEFAULT_SIZES, reps: int = 5, log=print) -> tuple[list, dic
                         _check_identical(cases, count_only, refs, name)
                         ms_total = sum(_time_ms(lambda c=c: c.run(count_only), reps) for c in cases)
                         per[name] = round(ms_total, 4)
-                        # a forced strategy must beat AUTO clearly: AUTO adapts
-                        # to the output density, which these cases only sample
-                        score = ms_total * (1.0 if strategy == WRITE_AUTO else 1.05)
+                        # a choice other than the default tile and AUTO must win
+                        # clearly: timings vary by a few percent between runs,
+                        # and AUTO adapts to the output density, which these
+                        # cases only sample
+                        score = ms_total * (1.0 if strategy == WRITE_AUTO else 1.05) * \
+                            (1.0 if tile == default else 1.03)
                         if best_ms is None or score < best_ms:
                             best, best_ms = (tile, strategy, name), score
                 key = f"{CLASS_NAMES[cls]}/{'count' if count_only else 'positions'}/{n}"
@@ -196,9 +199,10 @@ def tune_hash_bits(rows, n: int = 1 << 28, reps: int = 5, log=print) -> tuple[in
             _check_identical(cases, co, refs[co], f"hash bits {k}")
             total += sum(_time_ms(lambda c=c: c.run(co), reps) for c in cases)
         per[str(k)] = round(total, 4)
-        if best_ms is None or total < best_ms:
-            best, best_ms = k, total
-    log(f"[autotune] fingerprint width: best k={best} ({best_ms:.3f} ms vs k=11 {per['11']:.3f} ms)")
+        score = total * (1.0 if k == 11 else 1.05)  # a wider table costs LDS, hence occupancy
+        if best_ms is None or score < best_ms:
+            best, best_ms = k, score
+    log(f"[autotune] fingerprint width: best k={best} ({per[str(best)]:.3f} ms vs k=11 {per['11']:.3f} ms)")
     stream_check()
     return best, per
 
