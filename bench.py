@@ -383,8 +383,15 @@ def main():
                     e1.record()
                     events.append((e0, e1))
             else:
+                if record and args.detail:
+                    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                    e0.record()
                 epsm.count_into(c.plan, t, hits)
+                if record and args.detail:
+                    e1.record()
+                    cevents.append((e0, e1))
 
+    cevents = []
     for _ in range(args.warmup):
         step(False)
     torch.cuda.synchronize()
@@ -414,6 +421,13 @@ def main():
             n = texts[c.text_idx].numel()
             log(f"text{c.text_idx} m={len(c.pattern):2d} {c.origin:11s} hits={c.count:11d} {ms:8.3f} ms "
                 f"text {n / ms / 1e6:7.1f} GB/s alg {(n + 8 * c.count) / ms / 1e6:7.1f} GB/s")
+        cnt_cases = [c for c in cases if c.mode == "count"]
+        for i, c in enumerate(cnt_cases):
+            ms = sum(cevents[s * len(cnt_cases) + i][0].elapsed_time(cevents[s * len(cnt_cases) + i][1])
+                     for s in range(args.steps)) / args.steps
+            n = texts[c.text_idx].numel()
+            log(f"count text{c.text_idx} m={len(c.pattern):2d} {c.origin:11s} hits={c.count:11d} {ms:8.3f} ms "
+                f"text {n / ms / 1e6:7.1f} GB/s")
     n_pos_launches = len(events)
     achieved = pos_alg_bytes * args.steps / (pos_ms / 1e3) / 1e9
     traffic = load_traffic(args.workload)

@@ -233,3 +233,43 @@ def test_autotune_cache_round_trip(tmp_path):
     finally:
         autotune.reset()
     assert host_plan(bytes(range(20)))["hash_bits"] == 11
+
+
+def test_header_constants_match_binding():
+    """Every numeric #define of include/epsm.h has the same value in the binding."""
+    src = open(HEADER).read()
+    defs = dict(re.findall(r"#define EPSM_([A-Z0-9_]+) (0x[0-9a-fA-F]+|\d+)u", src))
+    assert len(defs) >= 15
+    for name, val in defs.items():
+        assert hasattr(_lib, name), name
+        assert getattr(_lib, name) == int(val, 0), name
+
+
+def test_struct_layouts_match_the_c_compiler(tmp_path):
+    """The ctypes mirrors have the sizes and field offsets gcc gives the
+    structs of include/epsm.h."""
+    import ctypes as C
+    import shutil
+    import subprocess
+    if shutil.which("gcc") is None:
+        pytest.skip("gcc not available")
+    mirrors = {"epsm_plan_info": _lib.PlanInfo, "epsm_tune_entry": _lib.TuneEntry,
+               "epsm_text_ref": _lib.TextRef, "epsm_pair_ref": _lib.PairRef, "epsm_batch": _lib.Batch,
+               "epsm_server_config": _lib.ServerConfig, "epsm_query_result": _lib.QueryResult,
+               "epsm_server_stats": _lib.ServerStats}
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "epsm.h"', "int main(void) {"]
+    for cname, py in mirrors.items():
+        lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
+        for field, _ in py._fields_:
+            lines.append(f'printf("{cname} {field} %zu\\n", offsetof({cname}, {field}));')
+    lines.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {tuple(l.split()[:2]): int(l.split()[2]) for l in out if l.strip()}
+    for cname, py in mirrors.items():
+        assert got[(cname, "size")] == C.sizeof(py), cname
+        for field, _ in py._fields_:
+            assert got[(cname, field)] == getattr(py, field).offset, (cname, field)
