@@ -63,8 +63,27 @@ __device__ __forceinline__ uint32_t lanes_from_masks(const uint64_t (&b)[16]) {
 // words and transposes them into per-lane masks.  Keeping the common path
 // free of per-position branches matters: the scalar unit issues one
 // instruction per SIMD every four cycles and was the bottleneck.
+// m = 1: per-lane byte equality without wave masks.  For x = word ^ c*0x01010101
+// a byte is zero iff the byte matches; ((x & 0x7F..) + 0x7F..) sets the high
+// bit of every byte whose low seven bits are not all zero, without carries
+// between bytes, so ~(that | x | 0x7F..) keeps exactly the high bits of the
+// zero bytes.  One multiply gathers those four bits (byte i's bit lands on
+// bit 28 + i; no partial product reaches bits 24..27 or carries into 28..31).
+__device__ __forceinline__ uint32_t byte_mask(const uint32_t *w, uint32_t c) {
+    const uint32_t rep = c * 0x01010101u;
+    uint32_t mk = 0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const uint32_t x = w[q] ^ rep;
+        const uint32_t z = ~(((x & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | x | 0x7F7F7F7Fu);
+        mk |= ((((z >> 7) & 0x01010101u) * 0x10204080u) >> 28) << (4 * q);
+    }
+    return mk;
+}
+
 template <int NL, int PK, int NW>
 __device__ __forceinline__ uint32_t direct_mask(const uint32_t (&w)[NL * 4 + 1], const DevPlan &p) {
+    if constexpr (PK == 1) return byte_mask(w, p.pw[0]);
     constexpr int NWMAX = 4 * NL - 4;
     uint64_t b[16];
     uint64_t any = 0;
