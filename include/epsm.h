@@ -68,16 +68,23 @@ typedef struct epsm_plan_s *epsm_plan_t;
  * Encoded in bits 8..11 of flags as EPSM_PLAN_HASH_BITS(k), 8 <= k <= 14;
  * 0 selects the default (11). */
 #define EPSM_PLAN_HASH_BITS(k) (((uint32_t)(k) & 0xFu) << 8)
+/* The pattern is a string of DNA codes 0..3 (one per byte, e.g. A,C,G,T ->
+ * 0,1,2,3; the mapping is the caller's) to be searched in packed 2-bit texts
+ * with epsm_search_dna / epsm_count_dna.  Excludes the variant and
+ * fingerprint flags. */
+#define EPSM_PLAN_DNA 0x10u
 
 /* Variants */
 #define EPSM_VARIANT_DIRECT 1u
 #define EPSM_VARIANT_FINGERPRINT 2u
+#define EPSM_VARIANT_DNA 3u
 
 /* Kernel classes of single-text searches (the key of the tune table). */
 #define EPSM_CLASS_BYTES 0u        /* direct variant, m <= 3: byte compares */
 #define EPSM_CLASS_WORDS 1u        /* direct variant, m >= 4: packed-word compares */
 #define EPSM_CLASS_FINGERPRINT 2u  /* fingerprint variant (Section 3.4) */
-#define EPSM_N_CLASSES 3u
+#define EPSM_CLASS_DNA 3u          /* packed 2-bit DNA texts */
+#define EPSM_N_CLASSES 4u
 
 /* Longest pattern this build accepts. */
 #define EPSM_MAX_M 4096u
@@ -141,6 +148,33 @@ epsm_status epsm_search(epsm_plan_t plan, const uint8_t *d_text, uint64_t n,
 /* epsm_count: the occurrence count only, to *d_n_hits (device, uint64). */
 epsm_status epsm_count(epsm_plan_t plan, const uint8_t *d_text, uint64_t n,
                        uint64_t *d_n_hits, void *stream);
+
+/* ---- packed DNA texts ------------------------------------------------------ */
+
+/*
+ * A text over four symbols stored at two bits per symbol: symbol i occupies
+ * bits 2*(i%4) and 2*(i%4)+1 of byte i/4, so n symbols take ceil(n/4) bytes
+ * and a little-endian 32-bit word holds 16 consecutive symbols.  The search
+ * is the same problem (all s, 0 <= s <= n-m, with t[s+j] = p[j] for j < m;
+ * positions and n count symbols) on a quarter of the bytes.  The paper leaves
+ * such texts out (it states the byte-alphabet setting in Section 2); this is
+ * the packed-text extension of its direct compare.
+ */
+
+/* Pack n symbol codes (device bytes; only their low two bits are used) into
+ * d_packed (device, ceil(n/4) bytes; no byte past that is written).  Bits of
+ * the last byte past n are zero. */
+epsm_status epsm_pack_dna(const uint8_t *d_codes, uint64_t n, uint8_t *d_packed, void *stream);
+
+/* epsm_search / epsm_count over a packed text of n symbols at d_packed (any
+ * byte alignment).  The plan must be made with EPSM_PLAN_DNA, and such a plan
+ * is rejected by the byte searches and by batches (EPSM_EINVAL).  Positions
+ * are symbol indices. */
+epsm_status epsm_search_dna(epsm_plan_t plan, const uint8_t *d_packed, uint64_t n,
+                            int64_t *d_out, uint64_t out_capacity, uint64_t *d_n_hits,
+                            void *stream);
+epsm_status epsm_count_dna(epsm_plan_t plan, const uint8_t *d_packed, uint64_t n,
+                           uint64_t *d_n_hits, void *stream);
 
 /* ---- batched search ------------------------------------------------------ */
 

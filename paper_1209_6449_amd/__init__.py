@@ -17,14 +17,16 @@ import torch
 
 from . import _lib
 from ._lib import (BATCH_COUNT_ONLY, CLASS_BYTES, CLASS_FINGERPRINT, CLASS_WORDS,  # noqa: F401
-                   MAX_M, N_CLASSES, PLAN_COLLIDE, PLAN_FORCE_DIRECT, PLAN_FORCE_FINGERPRINT,
+                   CLASS_DNA, MAX_M, N_CLASSES, PLAN_COLLIDE, PLAN_DNA, PLAN_FORCE_DIRECT,
+                   PLAN_FORCE_FINGERPRINT, VARIANT_DNA,
                    PLAN_HASH_BITS, PLAN_HOST_ONLY, VARIANT_DIRECT, VARIANT_FINGERPRINT,
                    WRITE_AUTO, WRITE_SINGLE_PASS, WRITE_TWO_PHASE)
 
 __all__ = ["EpsmError", "Plan", "search", "count", "search_into", "count_into", "reserve",
            "stream_check", "lib", "library_path", "Batch", "BatchPlan", "search_batch",
            "set_tile_config", "set_batch_config", "tile_configs", "set_tune_table",
-           "set_default_hash_bits"]
+           "set_default_hash_bits", "pack_dna", "search_dna", "count_dna", "search_dna_into",
+           "count_dna_into"]
 
 
 def lib():
@@ -150,6 +152,63 @@ def search(text: torch.Tensor, pattern, flags: int = 0, stream=None) -> torch.Te
     search_into(plan, text, out, hits, stream)
     if int(hits.item()) != n:
         raise RuntimeError("count changed between passes")
+    return out
+
+
+def pack_dna(codes: torch.Tensor, stream=None) -> torch.Tensor:
+    """2-bit packing (epsm_pack_dna) of a uint8 CUDA tensor of codes 0..3."""
+    _check_text(codes)
+    n = codes.numel()
+    packed = torch.empty((n + 3) // 4, dtype=torch.uint8, device=codes.device)
+    _check(lib().epsm_pack_dna(codes.data_ptr() if n else None, n, packed.data_ptr() if n else None,
+                               _stream_handle(stream)), "epsm_pack_dna")
+    return packed
+
+
+def _check_packed(packed: torch.Tensor, n: int) -> None:
+    _check_text(packed)
+    if packed.numel() < (n + 3) // 4:
+        raise ValueError(f"a packed text of {n} symbols needs {(n + 3) // 4} bytes")
+
+
+def search_dna_into(plan: Plan, packed: torch.Tensor, n: int, out: torch.Tensor | None,
+                    n_hits: torch.Tensor, stream=None) -> None:
+    """epsm_search_dna: positions (symbol indices) of plan in n packed symbols."""
+    _check_packed(packed, n)
+    cap = 0 if out is None else out.numel()
+    _check(lib().epsm_search_dna(plan.handle, packed.data_ptr() if n else None, n,
+                                 None if out is None or cap == 0 else out.data_ptr(), cap,
+                                 n_hits.data_ptr(), _stream_handle(stream)), "epsm_search_dna")
+
+
+def count_dna_into(plan: Plan, packed: torch.Tensor, n: int, n_hits: torch.Tensor, stream=None) -> None:
+    _check_packed(packed, n)
+    _check(lib().epsm_count_dna(plan.handle, packed.data_ptr() if n else None, n, n_hits.data_ptr(),
+                                _stream_handle(stream)), "epsm_count_dna")
+
+
+def _as_dna_plan(pattern_or_plan) -> Plan:
+    if isinstance(pattern_or_plan, Plan):
+        return pattern_or_plan
+    return Plan(pattern_or_plan, PLAN_DNA)
+
+
+def count_dna(packed: torch.Tensor, n: int, pattern, stream=None) -> int:
+    """Occurrences of a code pattern (bytes of 0..3, or a PLAN_DNA Plan) in n packed symbols."""
+    plan = _as_dna_plan(pattern)
+    hits = torch.zeros(1, dtype=torch.int64, device=packed.device)
+    count_dna_into(plan, packed, n, hits, stream)
+    return int(hits.item())
+
+
+def search_dna(packed: torch.Tensor, n: int, pattern, stream=None) -> torch.Tensor:
+    """All occurrence positions (symbol indices) as an int64 tensor."""
+    plan = _as_dna_plan(pattern)
+    hits = torch.zeros(1, dtype=torch.int64, device=packed.device)
+    count_dna_into(plan, packed, n, hits, stream)
+    k = int(hits.item())
+    out = torch.empty(k, dtype=torch.int64, device=packed.device)
+    search_dna_into(plan, packed, n, out, hits, stream)
     return out
 
 

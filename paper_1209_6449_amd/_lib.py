@@ -17,6 +17,7 @@ PLAN_HOST_ONLY = 0x1
 PLAN_FORCE_DIRECT = 0x2
 PLAN_FORCE_FINGERPRINT = 0x4
 PLAN_COLLIDE = 0x8
+PLAN_DNA = 0x10
 
 
 def PLAN_HASH_BITS(k: int) -> int:
@@ -25,13 +26,15 @@ def PLAN_HASH_BITS(k: int) -> int:
 
 VARIANT_DIRECT = 1
 VARIANT_FINGERPRINT = 2
+VARIANT_DNA = 3
 WRITE_AUTO = 0
 WRITE_SINGLE_PASS = 1
 WRITE_TWO_PHASE = 2
 CLASS_BYTES = 0
 CLASS_WORDS = 1
 CLASS_FINGERPRINT = 2
-N_CLASSES = 3
+CLASS_DNA = 3
+N_CLASSES = 4
 BATCH_COUNT_ONLY = 0x1
 BATCH_NO_GROUPS = 0x2
 MAX_M = 4096
@@ -128,6 +131,12 @@ SIGNATURES = {
     "epsm_count": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64,
                                   ctypes.c_void_p, ctypes.c_void_p]),
     "epsm_search_batch": (ctypes.c_int, [ctypes.POINTER(Batch), ctypes.c_void_p]),
+    "epsm_pack_dna": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_void_p, ctypes.c_void_p]),
+    "epsm_search_dna": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64,
+                                       ctypes.c_void_p, ctypes.c_uint64, ctypes.c_void_p,
+                                       ctypes.c_void_p]),
+    "epsm_count_dna": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64,
+                                      ctypes.c_void_p, ctypes.c_void_p]),
     "epsm_set_tile_config": (ctypes.c_int, [ctypes.c_uint32, ctypes.c_uint32]),
     "epsm_set_batch_config": (ctypes.c_int, [ctypes.c_uint32]),
     "epsm_tile_configs": (ctypes.c_uint32, [ctypes.POINTER(ctypes.c_uint32),

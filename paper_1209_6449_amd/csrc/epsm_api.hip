@@ -33,7 +33,7 @@ epsm_status hip_fail(hipError_t e, const char *what) {
 
 constexpr uint32_t kKnownPlanFlags = EPSM_PLAN_HOST_ONLY | EPSM_PLAN_FORCE_DIRECT |
                                      EPSM_PLAN_FORCE_FINGERPRINT | EPSM_PLAN_COLLIDE |
-                                     EPSM_PLAN_HASH_BITS(0xF);
+                                     EPSM_PLAN_HASH_BITS(0xF) | EPSM_PLAN_DNA;
 constexpr uint32_t kDefaultHashBits = 11;  // k = 11 in Section 3.4
 
 // Default tile: 8 waves x 16 KiB per wave = 128 KiB per workgroup tile.
@@ -46,6 +46,7 @@ uint32_t g_default_hash_bits = kDefaultHashBits;
 constexpr uint32_t kMaxTuneEntries = 256;
 
 uint32_t kernel_class(const DevPlan &d) {
+    if (d.variant == EPSM_VARIANT_DNA) return EPSM_CLASS_DNA;
     if (d.variant == EPSM_VARIANT_FINGERPRINT) return EPSM_CLASS_FINGERPRINT;
     return (d.nl == 2 && d.pk < 4) ? EPSM_CLASS_BYTES : EPSM_CLASS_WORDS;
 }
@@ -178,9 +179,13 @@ epsm_status check_plan(epsm_plan_t plan) {
 
 // Count (write = false) or positions (write = true) for one text.
 epsm_status run_search(epsm_plan_t plan, const uint8_t *d_text, uint64_t n, int64_t *d_out,
-                       uint64_t cap, uint64_t *d_n_hits, hipStream_t stream, bool write) {
+                       uint64_t cap, uint64_t *d_n_hits, hipStream_t stream, bool write,
+                       bool dna = false) {
     epsm_status st = check_plan(plan);
     if (st != EPSM_OK) return st;
+    if (dna != (plan->dev.variant == EPSM_VARIANT_DNA))
+        return fail(EPSM_EINVAL, dna ? "a packed DNA search needs a plan made with EPSM_PLAN_DNA"
+                                     : "a plan made with EPSM_PLAN_DNA needs a packed DNA search");
     if (!d_n_hits) return fail(EPSM_EINVAL, "d_n_hits is NULL");
     if (n > 0 && !d_text) return fail(EPSM_EINVAL, "d_text is NULL");
     if (write && cap > 0 && !d_out) return fail(EPSM_EINVAL, "d_out is NULL with out_capacity > 0");
@@ -189,12 +194,15 @@ epsm_status run_search(epsm_plan_t plan, const uint8_t *d_text, uint64_t n, int6
         hipError_t e = launch_set_u64(d_n_hits, 0, stream);
         return e == hipSuccess ? EPSM_OK : hip_fail(e, "launch(set)");
     }
+    // coordinates are bytes, or 2-bit symbols (four per byte) for packed DNA
     ScanArgs a{};
+    const uint32_t sh = dna ? 2u : 0u;
     const uintptr_t addr = (uintptr_t)d_text;
     a.base = (const uint8_t *)(addr & ~uintptr_t(15));
-    a.delta = addr & 15;
+    a.delta = (uint64_t)(addr & 15) << sh;
     a.last = a.delta + n - m;
-    a.load_end = (a.delta + n + 15) & ~uint64_t(15);
+    a.load_end = ((((a.delta + n) + (1u << sh) - 1) >> sh) + 15) & ~uint64_t(15);  // bytes
+    a.shift = sh;
     a.out = d_out;
     a.cap = write ? cap : 0;
     a.n_hits = d_n_hits;
@@ -292,6 +300,8 @@ epsm_status build_batch(const epsm_batch *b, int waves, HostBatch &hb, bool chec
         const epsm_pair_ref &pr = b->pairs[k];
         if (pr.text >= b->n_texts) return fail(EPSM_EINVAL, "pair refers to a text out of range");
         if (!pr.plan) return fail(EPSM_EINVAL, "pair has a NULL plan");
+        if (pr.plan->dev.variant == EPSM_VARIANT_DNA)
+            return fail(EPSM_EINVAL, "batches search byte texts; EPSM_PLAN_DNA plans are not accepted");
         if (pr.plan->device >= 0 && pr.plan->device != dev)
             return fail(EPSM_EINVAL, "plan belongs to another device");
         BatchPairDesc &d = hb.pairs[k];
@@ -496,7 +506,15 @@ epsm_status epsm_plan(const uint8_t *pattern, uint64_t m, uint32_t flags, epsm_p
     }
     if (k < 8 || k > 14) return fail(EPSM_EINVAL, "hash bits must be in [8, 14]");
 
-    bool fingerprint = m >= 16;
+    const bool dna = (flags & EPSM_PLAN_DNA) != 0;
+    if (dna) {
+        if (flags & (EPSM_PLAN_FORCE_DIRECT | EPSM_PLAN_FORCE_FINGERPRINT | EPSM_PLAN_COLLIDE |
+                     EPSM_PLAN_HASH_BITS(0xF)))
+            return fail(EPSM_EINVAL, "EPSM_PLAN_DNA takes no variant or fingerprint flags");
+        for (uint64_t i = 0; i < m; ++i)
+            if (pattern[i] > 3) return fail(EPSM_EINVAL, "DNA pattern codes must be 0..3");
+    }
+    bool fingerprint = !dna && m >= 16;
     if (flags & EPSM_PLAN_FORCE_DIRECT) fingerprint = false;
     if (flags & EPSM_PLAN_FORCE_FINGERPRINT) {
         if (m < 15) return fail(EPSM_EINVAL, "the fingerprint variant needs m >= 15");
@@ -528,6 +546,26 @@ epsm_status epsm_plan(const uint8_t *pattern, uint64_t m, uint32_t flags, epsm_p
     d.pk = (uint32_t)std::min<uint64_t>(m, 4);
     d.collide = (flags & EPSM_PLAN_COLLIDE) ? 1 : 0;
     d.hash_bits = fingerprint ? k : 0;
+    if (dna) {
+        // 16 symbols per word, symbol t of word j at bits 2t; the first three
+        // words are compared from registers, the rest by the tail check
+        d.variant = EPSM_VARIANT_DNA;
+        d.nl = 1;
+        d.pk = 4;
+        d.nw = (uint32_t)std::min<uint64_t>((m + 15) / 16, 3);
+        for (int j = 0; j < 8; ++j) {
+            uint32_t wv = 0, mv = 0;
+            for (int t = 0; t < 16; ++t) {
+                const uint64_t i = 16ull * j + t;
+                if (i < m) {
+                    wv |= (uint32_t)pattern[i] << (2 * t);
+                    mv |= 3u << (2 * t);
+                }
+            }
+            d.pw[j] = wv;
+            d.pmask[j] = mv;
+        }
+    }
     if (fingerprint) {
         // Section 3.4: L[v] = { j : h(p[j..j+7]) = v }, offsets j in [0, 7].
         p->table.assign((size_t)1 << k, 0);
@@ -599,6 +637,26 @@ epsm_status epsm_count(epsm_plan_t plan, const uint8_t *d_text, uint64_t n, uint
                        void *stream) {
     g_last_error.clear();
     return run_search(plan, d_text, n, nullptr, 0, d_n_hits, (hipStream_t)stream, false);
+}
+
+epsm_status epsm_search_dna(epsm_plan_t plan, const uint8_t *d_packed, uint64_t n, int64_t *d_out,
+                            uint64_t out_capacity, uint64_t *d_n_hits, void *stream) {
+    g_last_error.clear();
+    return run_search(plan, d_packed, n, d_out, out_capacity, d_n_hits, (hipStream_t)stream, true,
+                      true);
+}
+
+epsm_status epsm_count_dna(epsm_plan_t plan, const uint8_t *d_packed, uint64_t n,
+                           uint64_t *d_n_hits, void *stream) {
+    g_last_error.clear();
+    return run_search(plan, d_packed, n, nullptr, 0, d_n_hits, (hipStream_t)stream, false, true);
+}
+
+epsm_status epsm_pack_dna(const uint8_t *d_codes, uint64_t n, uint8_t *d_packed, void *stream) {
+    g_last_error.clear();
+    if (n && (!d_codes || !d_packed)) return fail(EPSM_EINVAL, "NULL buffer");
+    hipError_t e = launch_pack_dna(d_codes, n, d_packed, (hipStream_t)stream);
+    return e == hipSuccess ? EPSM_OK : hip_fail(e, "launch(pack_dna)");
 }
 
 

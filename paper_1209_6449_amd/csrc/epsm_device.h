@@ -149,6 +149,61 @@ __device__ __forceinline__ uint32_t fingerprint_mask(const uint32_t (&w)[NL * 4 
     return any ? lanes_from_masks(b) : 0u;
 }
 
+// Packed DNA (variant 3): coordinates are 2-bit symbols, 16 to a 32-bit
+// word, symbol t of a word at bits 2t.  A lane holds 64 symbols (its 16 and
+// the 48 after them) in w[0..3].  The window of 16 symbols at symbol k of
+// word j is a funnel shift of words j and j+1 by 2k bits.
+__device__ __forceinline__ uint32_t dna_window(const uint32_t (&w)[5], int j, int k) {
+    return k == 0 ? w[j] : __builtin_amdgcn_alignbit(w[j + 1], w[j], (uint32_t)(2 * k));
+}
+
+// DNA hit mask of one lane piece: the first 16 symbols of the pattern
+// (masked below m) against each of the 16 windows, then the next one or two
+// pattern words where some lane of the wave still has a candidate.
+__device__ __forceinline__ uint32_t dna_mask(const uint32_t (&w)[5], const DevPlan &p) {
+    uint64_t b[16];
+    uint64_t any = 0;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+        b[k] = ballot((dna_window(w, 0, k) & p.pmask[0]) == p.pw[0]);
+        any |= b[k];
+    }
+    if (any == 0) return 0u;
+    if (p.nw > 1) {
+        any = 0;
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+#pragma unroll
+            for (int j = 1; j < 3; ++j)
+                if (j < (int)p.nw && b[k] != 0)
+                    b[k] &= ballot((dna_window(w, j, k) & p.pmask[j]) == p.pw[j]);
+            any |= b[k];
+        }
+        if (any == 0) return 0u;
+    }
+    return lanes_from_masks(b);
+}
+
+// Exact check of DNA pattern symbols [from, m) for each candidate, reading
+// the packed text and the pattern codes from global memory.
+static inline __device__ __noinline__ uint32_t tail_check_dna(uint32_t mk, uint64_t s0, const uint8_t *base,
+                                                              const uint8_t *pattern, uint64_t m,
+                                                              uint32_t from) {
+    uint32_t keep = 0;
+    while (mk) {
+        const uint32_t k = __builtin_ctz(mk);
+        mk &= mk - 1;
+        const uint64_t s = s0 + k;
+        bool ok = true;
+        for (uint64_t j = from; j < m; ++j) {
+            const uint64_t q = s + j;
+            if (((base[q >> 2] >> (2 * (q & 3))) & 3u) != pattern[j]) { ok = false; break; }
+        }
+        if (ok) keep |= 1u << k;
+    }
+    return keep;
+}
+
 // Start positions of the lane piece at base coordinate s0 that are valid
 // (delta <= s <= last), as a 16-bit mask.
 __device__ __forceinline__ uint32_t valid_mask(uint64_t s0, uint64_t delta, uint64_t last) {
@@ -325,6 +380,21 @@ __device__ __forceinline__ void load_chunk(uint32_t (&w)[U][NL * 4 + 1], __amdgp
     }
 }
 
+// DNA: one dwordx4 per lane and piece (64 symbols) at byte offset off.
+template <int U>
+__device__ __forceinline__ void load_chunk_dna(uint32_t (&w)[U][5], __amdgpu_buffer_rsrc_t r,
+                                               uint32_t off) {
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const u32x4 v = load16(r, off + u * (kWavePiece / 4));
+        w[u][0] = v.x;
+        w[u][1] = v.y;
+        w[u][2] = v.z;
+        w[u][3] = v.w;
+        w[u][4] = 0;
+    }
+}
+
 // Hit masks of the U pieces of one chunk, parked in LDS (two 16-bit masks per
 // word); returns the lane's hit count.
 template <int U, int NL, int VAR, int PK, int NW, int PAIRS, int THREADS>
@@ -337,14 +407,19 @@ __device__ __forceinline__ uint32_t process_chunk(const uint32_t (&w)[U][NL * 4 
     for (int u = 0; u < U; ++u) {
         uint32_t mk;
         if constexpr (VAR == 1) mk = direct_mask<NL, PK, NW>(w[u], a.plan);
-        else mk = fingerprint_mask<NL>(w[u], a.plan, tab);
+        else if constexpr (VAR == 2) mk = fingerprint_mask<NL>(w[u], a.plan, tab);
+        else mk = dna_mask(w[u], a.plan);
         const int piece = c * U + u;
         const uint64_t s0 = lane_start + (uint64_t)piece * kWavePiece;
         // only the first tile holds starts below delta and only the last
         // one holds starts past `last`
         if (edge) mk &= valid_mask(s0, a.delta, a.last);
-        if (tail && wave_any(mk != 0))
-            mk = tail_check(mk, s0, a.base, a.plan.pattern, a.plan.m, 4u * a.plan.nw);
+        if (tail && wave_any(mk != 0)) {
+            if constexpr (VAR == 3)
+                mk = tail_check_dna(mk, s0, a.base, a.plan.pattern, a.plan.m, 16u * a.plan.nw);
+            else
+                mk = tail_check(mk, s0, a.base, a.plan.pattern, a.plan.m, 4u * a.plan.nw);
+        }
         cnt += __popc(mk);
         if (u & 1) s_mask[piece >> 1][tid] = lo | (mk << 16);
         else lo = mk;

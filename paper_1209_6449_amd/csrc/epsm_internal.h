@@ -39,7 +39,8 @@ struct DevPlan {
     uint32_t pmask[8];       // 0xFF byte lanes below m
     uint64_t m;
     uint32_t nw;             // words compared from registers: min(ceil(m/4), 4*NL)
-    uint32_t variant;        // 1 direct, 2 fingerprint
+                             // (DNA: 16-symbol words, min(ceil(m/16), 3))
+    uint32_t variant;        // 1 direct, 2 fingerprint, 3 DNA (2-bit symbols)
     uint32_t pk;             // direct prefix kind: min(m, 4)
     uint32_t hash_bits;      // fingerprint: k
     uint32_t collide;        // fingerprint: constant-0 hash (test mode)
@@ -64,6 +65,7 @@ struct ScanArgs {
     uint64_t *gsum;          // two-phase: [ceil(num_tiles / kGroupTiles)] hits per tile group, zeroed
     uint32_t *slots;         // two-phase: [num_tiles * tile_bytes / 32] list or masks per tile
     uint32_t num_tiles;
+    uint32_t shift;          // coordinates per text byte, log2: 0 bytes, 2 packed DNA
     uint32_t write;          // kWriteNone, kWriteLookBack or kWriteTwoPhase
     uint32_t expand_tiles;   // two-phase: tiles per expand workgroup, 1..kExpandTiles
     DevPlan plan;
@@ -173,6 +175,9 @@ struct TileConfig {
 // Launchers (epsm_kernels.hip).  Return hipSuccess or the launch error.
 hipError_t launch_zero_u64(uint64_t *p, uint64_t count, hipStream_t s);
 hipError_t launch_set_u64(uint64_t *p, uint64_t value, hipStream_t s);
+// 2-bit packing of n symbol codes (low two bits of each byte) into
+// ceil(n/4) bytes, symbol i at bits 2*(i%4) of byte i/4.
+hipError_t launch_pack_dna(const uint8_t *codes, uint64_t n, uint8_t *packed, hipStream_t s);
 hipError_t launch_sum_bins(const uint64_t *bins, uint64_t *out, hipStream_t s);
 hipError_t launch_scan(const ScanArgs &a, TileConfig cfg, int grid, hipStream_t s);
 // Second phase of a two-phase search: slots -> positions, and *n_hits.

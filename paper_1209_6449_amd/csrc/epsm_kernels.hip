@@ -94,23 +94,25 @@ __device__ __forceinline__ void write_tile(const uint32_t (*masks)[THREADS], uin
                                   });
 }
 
-__device__ __forceinline__ __amdgpu_buffer_rsrc_t tile_rsrc(const ScanArgs &a, uint64_t tile_start) {
-    const uint64_t avail = a.load_end - tile_start;
+// Buffer descriptor of a tile; tile_byte is the tile's first byte (its first
+// coordinate >> a.shift), a.load_end the readable bytes from a.base.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t tile_rsrc(const ScanArgs &a, uint64_t tile_byte) {
+    const uint64_t avail = a.load_end - tile_byte;
     const uint32_t nrec = avail > 0xFFFFFFF0ull ? 0xFFFFFFF0u : (uint32_t)avail;
-    return make_rsrc(a.base + tile_start, nrec);
+    return make_rsrc(a.base + tile_byte, nrec);
 }
 
 // One workgroup per tile (workgroup index = tile index, no counter).  Every
 // tile publishes its count as soon as it is computed, independently of the
 // other tiles' look-back and write phases; a look-back only waits on lower
 // workgroup indices, which in-order dispatch has already started.
-// Six waves per SIMD (at most 80 VGPRs) for the two-load kernels: one more
+// Six waves per SIMD (at most 80 VGPRs) for the one- and two-load kernels: one more
 // resident wave per SIMD than 88 VGPRs would allow, which the streaming
 // loads need.  The three-load direct kernel keeps its registers.  Tiles
 // whose LDS admits fewer waves (4x32, 16x8, 16x16) do not reach the target;
 // their register use is left as it is.
 template <int WAVES, int U, int C, int NL, int VAR, int PK, int NW>
-__global__ __launch_bounds__(WAVES * kWave) __attribute__((amdgpu_waves_per_eu(NL == 2 ? 6 : 4)))
+__global__ __launch_bounds__(WAVES * kWave) __attribute__((amdgpu_waves_per_eu(NL <= 2 ? 6 : 4)))
 void scan_kernel(ScanArgs a) {
     constexpr int kThreads = WAVES * kWave;
     constexpr int kPieces = U * C;  // pieces per wave per tile
@@ -124,16 +126,23 @@ void scan_kernel(ScanArgs a) {
     __shared__ uint64_t s_excl;
     const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
 
+    // coordinates: text bytes, or 2-bit symbols for packed DNA (VAR == 3,
+    // four to a byte); a piece is 1024 coordinates either way
+    constexpr uint32_t kShift = VAR == 3 ? 2 : 0;
     const uint32_t tile = blockIdx.x;
     const uint64_t tile_start = (uint64_t)tile * kTile;
-    const __amdgpu_buffer_rsrc_t rsrc = tile_rsrc(a, tile_start);
+    const __amdgpu_buffer_rsrc_t rsrc = tile_rsrc(a, tile_start >> kShift);
     const uint32_t lane_off = (uint32_t)wave * kWaveSpan + (uint32_t)lane * kPiece;
     const uint64_t lane_start = tile_start + lane_off;
     const bool edge = tile == 0 || tile == a.num_tiles - 1;
-    const bool tail = a.plan.m > 4u * a.plan.nw;
+    const bool tail = a.plan.m > (VAR == 3 ? 16u : 4u) * a.plan.nw;
+    auto load = [&](uint32_t (&w)[U][NL * 4 + 1], uint32_t off) {
+        if constexpr (VAR == 3) load_chunk_dna<U>(w, rsrc, off >> kShift);
+        else load_chunk<U, NL>(w, rsrc, off);
+    };
 
     uint32_t wa[U][NL * 4 + 1], wb[U][NL * 4 + 1];
-    load_chunk<U, NL>(wa, rsrc, lane_off);
+    load(wa, lane_off);
     if constexpr (VAR == 2) {
         const uint32_t rows = (1u << a.plan.hash_bits) / 8;  // 16-byte rows of the table
         const u32x4 *src = reinterpret_cast<const u32x4 *>(a.plan.table);
@@ -145,10 +154,10 @@ void scan_kernel(ScanArgs a) {
     uint32_t cnt = 0;
 #pragma unroll 1
     for (int c = 0; c < C; c += 2) {
-        load_chunk<U, NL>(wb, rsrc, lane_off + (uint32_t)(c + 1) * U * kWavePiece);
+        load(wb, lane_off + (uint32_t)(c + 1) * U * kWavePiece);
         cnt += process_chunk<U, NL, VAR, PK, NW, kPieces / 2, kThreads>(
             wa, c, a, s_table, lane_start, edge, tail, s_mask, tid);
-        if (c + 2 < C) load_chunk<U, NL>(wa, rsrc, lane_off + (uint32_t)(c + 2) * U * kWavePiece);
+        if (c + 2 < C) load(wa, lane_off + (uint32_t)(c + 2) * U * kWavePiece);
         cnt += process_chunk<U, NL, VAR, PK, NW, kPieces / 2, kThreads>(
             wb, c + 1, a, s_table, lane_start, edge, tail, s_mask, tid);
     }
@@ -330,6 +339,28 @@ __global__ void zero_u64_kernel(uint64_t *p, uint64_t count) {
     for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += stride) p[i] = 0;
 }
 
+// 16 symbols per thread: codes[16i .. 16i+16) -> packed bytes [4i, 4i+4).
+__global__ __launch_bounds__(256) void pack_dna_kernel(const uint8_t *codes, uint64_t n,
+                                                       uint8_t *packed) {
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const uint64_t first = i * 16;
+    if (first >= n) return;
+    uint32_t v = 0;
+    for (int t = 0; t < 16; ++t)
+        if (first + t < n) v |= (uint32_t)(codes[first + t] & 3u) << (2 * t);
+    const uint64_t bytes = (n + 3) / 4;
+    for (int b = 0; b < 4; ++b)
+        if (4 * i + b < bytes) packed[4 * i + b] = (uint8_t)(v >> (8 * b));
+}
+
+hipError_t launch_pack_dna(const uint8_t *codes, uint64_t n, uint8_t *packed, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    const uint64_t threads = (n + 15) / 16;
+    hipLaunchKernelGGL(pack_dna_kernel, dim3((uint32_t)((threads + 255) / 256)), dim3(256), 0, s, codes,
+                       n, packed);
+    return hipGetLastError();
+}
+
 __global__ void set_u64_kernel(uint64_t *p, uint64_t value) {
     if (blockIdx.x == 0 && threadIdx.x == 0) *p = value;
 }
@@ -353,6 +384,7 @@ typedef void (*ScanFn)(ScanArgs);
 // chunks in flight) keep the kernels within about 100 VGPRs.
 template <int WAVES, int PIECES>
 static ScanFn pick(const DevPlan &p) {
+    if (p.variant == 3) return scan_kernel<WAVES, 2, PIECES / 2, 1, 3, 4, 0>;
     if (p.variant == 2) return scan_kernel<WAVES, 2, PIECES / 2, 2, 2, 4, 0>;
     if (p.nl == 3) return scan_kernel<WAVES, 2, PIECES / 2, 3, 1, 4, 0>;
     switch (p.pk) {

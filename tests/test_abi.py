@@ -176,11 +176,47 @@ def test_kernel_class_of_plan(m, flags, cls):
     assert host_plan(bytes((3 * i + 1) % 256 for i in range(m)), flags)["kernel_class"] == cls
 
 
+@pytest.mark.parametrize("m", [1, 7, 16, 17, 33, 48, 49, 100])
+def test_dna_plan_packs_codes_two_bits_each(m):
+    rng = np.random.default_rng(m)
+    codes = rng.integers(0, 4, m).astype(np.uint8)
+    info = host_plan(codes.tobytes(), epsm.PLAN_DNA)
+    assert info["variant"] == epsm.VARIANT_DNA and info["kernel_class"] == epsm.CLASS_DNA
+    assert info["prefix_words"] == min((m + 15) // 16, 3) and info["table"] is None
+    for j in range(8):
+        syms = codes[16 * j:16 * j + 16]
+        assert info["words"][j] == sum(int(c) << (2 * t) for t, c in enumerate(syms))
+        assert info["masks"][j] == sum(3 << (2 * t) for t in range(len(syms)))
+
+
+@pytest.mark.parametrize("pattern,flags", [
+    (b"\x00\x04", epsm.PLAN_DNA),                                    # code > 3
+    (b"\x00\x01", epsm.PLAN_DNA | epsm.PLAN_FORCE_DIRECT),           # no variant flags
+    (b"\x00" * 20, epsm.PLAN_DNA | epsm.PLAN_HASH_BITS(12)),          # no fingerprint flags
+])
+def test_dna_plan_rejects(pattern, flags):
+    with pytest.raises(epsm.EpsmError) as e:
+        epsm.Plan(pattern, flags | epsm.PLAN_HOST_ONLY)
+    assert e.value.status == _lib.EPSM_EINVAL
+
+
+def test_dna_null_arguments():
+    L = epsm.lib()
+    assert L.epsm_search_dna(None, None, 0, None, 0, None, None) == _lib.EPSM_EINVAL
+    assert L.epsm_count_dna(None, None, 0, None, None) == _lib.EPSM_EINVAL
+    assert L.epsm_pack_dna(None, 5, None, None) == _lib.EPSM_EINVAL
+    assert L.epsm_pack_dna(None, 0, None, None) == _lib.EPSM_OK      # nothing to pack
+    plan = epsm.Plan(b"\x01\x02", epsm.PLAN_DNA | epsm.PLAN_HOST_ONLY)
+    dummy = ctypes.c_uint64()
+    st = L.epsm_search_dna(plan.handle, ctypes.addressof(dummy), 8, None, 0, ctypes.addressof(dummy), None)
+    assert st == _lib.EPSM_EINVAL                                      # host-only plan
+
+
 def test_tune_table_validation():
     tiles = epsm.tile_configs()
     ok = [(epsm.CLASS_WORDS, 0, 1 << 20, *tiles[1]), (epsm.CLASS_FINGERPRINT, 1, (1 << 64) - 1, *tiles[0])]
     epsm.set_tune_table(ok)
-    for bad, status in [((3, 0, 1, 8, 16), _lib.EPSM_EINVAL),          # unknown class
+    for bad, status in [((4, 0, 1, 8, 16), _lib.EPSM_EINVAL),          # unknown class
                         ((0, 2, 1, 8, 16), _lib.EPSM_EINVAL),          # unknown mode
                         ((0, 0, 1, 8, 12), _lib.EPSM_EUNSUPPORTED),    # tile not built
                         ((0, 0, 1, 8, 16, 3), _lib.EPSM_EINVAL)]:      # unknown strategy

@@ -29,7 +29,7 @@ def test_small_tune_and_apply(at, tmp_path):
     epsm, autotune = at
     say("tune: sizes 64 KiB, 1 MiB")
     cache = autotune.tune(sizes=(1 << 16, 1 << 20), reps=1, batch=False, log=say)
-    assert len(cache["table"]) == 2 * 2 * epsm.N_CLASSES
+    assert len(cache["table"]) == 2 * 2 * len(autotune.CLASS_MS)
     assert all(len(r) == 6 and r[5] in (0, 1, 2) for r in cache["table"])
     built = [list(t) for t in epsm.tile_configs()]
     assert all(list(r[3:5]) in built for r in cache["table"])
