@@ -53,7 +53,7 @@ def parse_args():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="sweep1g", choices=["sweep1g", "zipf4g", "batch", "serve"])
+    ap.add_argument("--workload", default="sweep1g", choices=["sweep1g", "zipf4g", "batch", "serve", "dna"])
     ap.add_argument("--serve-queries", type=int, default=1000, help="queries per serving run")
     ap.add_argument("--batch-texts", type=int, default=10_000, help="texts in the batch workload")
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
@@ -107,6 +107,89 @@ def build_zipf4g(torch, W, epsm):
                           "4 GiB a^n with a^m (m=1..16); positions+count modes",
               "text_bytes": 1 << 32, "ms": list(range(1, 17)), "searches_per_step": len(cases)}
     return texts, [spec, per], cases, config
+
+
+def run_dna_workload(args, torch, W, epsm):
+    """Genome-like text of 2^32 symbols (uniform over 4 codes) searched packed
+    at 2 bits per symbol (1 GiB) and, for comparison, as bytes (4 GiB), with
+    the same cut and random patterns of m in {8, 12, 16, 20, 24, 32}."""
+    n = 1 << 32
+    spec = W.TextSpec(n=n, kind="uniform", key=W.text_key(6, 0), sigma=4)
+    log("generating 2^32 DNA codes on the GPU and packing them")
+    codes = W.gen_bytes(spec, device="cuda")
+    packed = epsm.pack_dna(codes)
+    torch.cuda.synchronize()
+    g = W.rng(6, 1)
+    pats = []
+    for m in (8, 12, 16, 20, 24, 32):
+        pats.append((W.cut_pattern(spec, m, g)[0], "cut"))
+        pats.append((W.random_pattern(m, W.alphabet_of(spec), g), "random"))
+    cases = [(p, o, epsm.Plan(p, epsm.PLAN_DNA), epsm.Plan(p)) for p, o in pats]
+    hits = torch.zeros(1, dtype=torch.int64, device="cuda")
+    counts = []
+    for p, _, pd, pb in cases:
+        epsm.count_dna_into(pd, packed, n, hits)
+        c = int(hits.item())
+        epsm.count_into(pb, codes, hits)
+        if int(hits.item()) != c:
+            raise AssertionError("packed and byte counts differ")
+        counts.append(c)
+    out = torch.empty(max(max(counts), 1), dtype=torch.int64, device="cuda")
+
+    def timed(fn):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        fn()
+        e1.record()
+        return e0, e1
+
+    def step(record):
+        ev = []
+        for (p, _, pd, pb), c in zip(cases, counts):
+            ev.append(timed(lambda: epsm.search_dna_into(pd, packed, n, out[:c], hits)))
+            ev.append(timed(lambda: epsm.count_dna_into(pd, packed, n, hits)))
+        return ev
+
+    for _ in range(args.warmup):
+        step(False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    evs = [step(True) for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    epsm.stream_check()
+    # the byte path over the same codes, for comparison (not in the value)
+    byte_ms = []
+    for (p, _, pd, pb), c in zip(cases, counts):
+        e = [timed(lambda: epsm.search_into(pb, codes, out[:c], hits)), timed(lambda: epsm.count_into(pb, codes, hits))]
+        torch.cuda.synchronize()
+        byte_ms.append([a.elapsed_time(b) for a, b in e])
+    detail, pos_ms_total, pos_bytes = [], 0.0, 0
+    for i, ((p, o, _, _), c) in enumerate(zip(cases, counts)):
+        pm = sum(evs[s][2 * i][0].elapsed_time(evs[s][2 * i][1]) for s in range(args.steps)) / args.steps
+        cm = sum(evs[s][2 * i + 1][0].elapsed_time(evs[s][2 * i + 1][1]) for s in range(args.steps)) / args.steps
+        pos_ms_total += pm
+        pos_bytes += n // 4 + 8 * c
+        detail.append({"m": len(p), "origin": o, "hits": c, "positions_ms": round(pm, 4),
+                       "count_ms": round(cm, 4), "byte_positions_ms": round(byte_ms[i][0], 4),
+                       "byte_count_ms": round(byte_ms[i][1], 4),
+                       "gsym_s_positions": round(n / pm / 1e6, 1), "gsym_s_count": round(n / cm / 1e6, 1),
+                       "gsym_s_byte_count": round(n / byte_ms[i][1] / 1e6, 1)})
+        if args.detail:
+            log(f"dna m={len(p):2d} {o:6s} hits={c:9d} packed: positions {pm:7.3f} ms count {cm:7.3f} ms "
+                f"({n / cm / 1e6:7.1f} Gsym/s) | bytes: positions {byte_ms[i][0]:7.3f} ms "
+                f"count {byte_ms[i][1]:7.3f} ms")
+    achieved = pos_bytes / (pos_ms_total / 1e3) / 1e9
+    config = {"workload": "dna: 2^32 symbols uniform over 4 codes, packed 2 bits per symbol (1 GiB); "
+                          "cut+random patterns m in {8,12,16,20,24,32}; positions+count modes",
+              "symbols": n, "packed_bytes": n // 4, "searches_per_step": 2 * len(cases)}
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "kernel": "packed-DNA positions-mode search (zero_u64 + scan_kernel + expand_kernel)",
+                "launches": len(cases) * args.steps,
+                "avg_launch_ms": round(pos_ms_total / len(cases), 4),
+                "alg_bytes_per_launch": round(pos_bytes / len(cases))}
+    return n * 2 * len(cases) * args.steps / elapsed, elapsed / args.steps, config, detail, roofline
 
 
 def run_batch_workload(args, torch, W, epsm):
@@ -328,6 +411,17 @@ def main():
             "config": dict(config, tuning=tuning), "serve": {"points": points, "p50_ms": top["p50_ms"],
                                         "p99_ms": top["p99_ms"], "server_stats": stats},
             "roofline": None, "cpu_baseline": None,
+        }
+        print(json.dumps(result), flush=True)
+        return
+    if args.workload == "dna":
+        sym_s, step_s, config, detail, roofline = run_dna_workload(args, torch, W, epsm)
+        result = {
+            "metric": "packed DNA symbols scanned per second", "value": round(sym_s / 1e9, 2),
+            "unit": "Gsym/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+            "ms_per_step": round(step_s * 1e3, 3), "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": "u2", "data": "synthetic", "config": dict(config, tuning=tuning),
+            "dna": detail, "roofline": roofline, "cpu_baseline": None,
         }
         print(json.dumps(result), flush=True)
         return

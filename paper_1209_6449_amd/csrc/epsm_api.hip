@@ -551,7 +551,7 @@ epsm_status epsm_plan(const uint8_t *pattern, uint64_t m, uint32_t flags, epsm_p
         // words are compared from registers, the rest by the tail check
         d.variant = EPSM_VARIANT_DNA;
         d.nl = 1;
-        d.pk = 4;
+        d.pk = m >= 16 ? 16 : 4;  // 16: the first word needs no mask
         d.nw = (uint32_t)std::min<uint64_t>((m + 15) / 16, 3);
         for (int j = 0; j < 8; ++j) {
             uint32_t wv = 0, mv = 0;

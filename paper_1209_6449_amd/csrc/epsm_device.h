@@ -158,14 +158,17 @@ __device__ __forceinline__ uint32_t dna_window(const uint32_t (&w)[5], int j, in
 }
 
 // DNA hit mask of one lane piece: the first 16 symbols of the pattern
-// (masked below m) against each of the 16 windows, then the next one or two
-// pattern words where some lane of the wave still has a candidate.
+// (masked below m unless FULL, i.e. m >= 16) against each of the 16 windows,
+// then the next one or two pattern words where some lane of the wave still
+// has a candidate.
+template <bool FULL>
 __device__ __forceinline__ uint32_t dna_mask(const uint32_t (&w)[5], const DevPlan &p) {
     uint64_t b[16];
     uint64_t any = 0;
 #pragma unroll
     for (int k = 0; k < 16; ++k) {
-        b[k] = ballot((dna_window(w, 0, k) & p.pmask[0]) == p.pw[0]);
+        const uint32_t x = dna_window(w, 0, k);
+        b[k] = ballot((FULL ? x : (x & p.pmask[0])) == p.pw[0]);
         any |= b[k];
     }
     if (any == 0) return 0u;
@@ -408,7 +411,7 @@ __device__ __forceinline__ uint32_t process_chunk(const uint32_t (&w)[U][NL * 4 
         uint32_t mk;
         if constexpr (VAR == 1) mk = direct_mask<NL, PK, NW>(w[u], a.plan);
         else if constexpr (VAR == 2) mk = fingerprint_mask<NL>(w[u], a.plan, tab);
-        else mk = dna_mask(w[u], a.plan);
+        else mk = dna_mask<PK == 16>(w[u], a.plan);
         const int piece = c * U + u;
         const uint64_t s0 = lane_start + (uint64_t)piece * kWavePiece;
         // only the first tile holds starts below delta and only the last

@@ -41,7 +41,7 @@ struct DevPlan {
     uint32_t nw;             // words compared from registers: min(ceil(m/4), 4*NL)
                              // (DNA: 16-symbol words, min(ceil(m/16), 3))
     uint32_t variant;        // 1 direct, 2 fingerprint, 3 DNA (2-bit symbols)
-    uint32_t pk;             // direct prefix kind: min(m, 4)
+    uint32_t pk;             // direct prefix kind: min(m, 4) (DNA: 16 if m >= 16, else 4)
     uint32_t hash_bits;      // fingerprint: k
     uint32_t collide;        // fingerprint: constant-0 hash (test mode)
     uint32_t nl;             // dwordx4 loads per lane per piece (2 or 3)

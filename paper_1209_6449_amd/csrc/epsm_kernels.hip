@@ -384,7 +384,9 @@ typedef void (*ScanFn)(ScanArgs);
 // chunks in flight) keep the kernels within about 100 VGPRs.
 template <int WAVES, int PIECES>
 static ScanFn pick(const DevPlan &p) {
-    if (p.variant == 3) return scan_kernel<WAVES, 2, PIECES / 2, 1, 3, 4, 0>;
+    if (p.variant == 3)
+        return p.pk == 16 ? scan_kernel<WAVES, 2, PIECES / 2, 1, 3, 16, 0>
+                          : scan_kernel<WAVES, 2, PIECES / 2, 1, 3, 4, 0>;
     if (p.variant == 2) return scan_kernel<WAVES, 2, PIECES / 2, 2, 2, 4, 0>;
     if (p.nl == 3) return scan_kernel<WAVES, 2, PIECES / 2, 3, 1, 4, 0>;
     switch (p.pk) {
