@@ -73,11 +73,23 @@ typedef struct epsm_plan_s *epsm_plan_t;
  * with epsm_search_dna / epsm_count_dna.  Excludes the variant and
  * fingerprint flags. */
 #define EPSM_PLAN_DNA 0x10u
+/* Never use the strided filter (see EPSM_VARIANT_STRIDE); long patterns then
+ * use the per-block fingerprint filter.  Output is the same. */
+#define EPSM_PLAN_NO_STRIDE 0x20u
 
 /* Variants */
 #define EPSM_VARIANT_DIRECT 1u
 #define EPSM_VARIANT_FINGERPRINT 2u
 #define EPSM_VARIANT_DNA 3u
+/* Long patterns (m >= 263): the fingerprint filter with a stride, as EPSMc
+ * (Section 3.4) is defined: only the aligned 8-byte blocks at multiples of S
+ * are read (S the largest power of two <= min(m - 7, 2048)), so the text
+ * lines in between are not fetched.  Every occurrence contains exactly one
+ * such block, at pattern offset j in [0, S); the plan's table lists the
+ * offsets per hash value, and every candidate is checked exactly.  Chosen by
+ * default unless a FORCE or COLLIDE flag or EPSM_PLAN_NO_STRIDE is given;
+ * inside batches such a plan filters per block like EPSM_VARIANT_FINGERPRINT. */
+#define EPSM_VARIANT_STRIDE 4u
 
 /* Kernel classes of single-text searches (the key of the tune table). */
 #define EPSM_CLASS_BYTES 0u        /* direct variant, m <= 3: byte compares */
@@ -118,6 +130,7 @@ typedef struct {
                                 the plan. */
     int32_t device;          /* HIP device of the device tables, -1 if host only */
     uint32_t kernel_class;   /* EPSM_CLASS_* of the plan's scan kernel */
+    uint32_t stride;         /* EPSM_VARIANT_STRIDE: bytes between inspected blocks, else 0 */
 } epsm_plan_info;
 
 /* Copy the plan's description to *info (host memory). */

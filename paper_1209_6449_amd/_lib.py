@@ -18,6 +18,7 @@ PLAN_FORCE_DIRECT = 0x2
 PLAN_FORCE_FINGERPRINT = 0x4
 PLAN_COLLIDE = 0x8
 PLAN_DNA = 0x10
+PLAN_NO_STRIDE = 0x20
 
 
 def PLAN_HASH_BITS(k: int) -> int:
@@ -27,6 +28,7 @@ def PLAN_HASH_BITS(k: int) -> int:
 VARIANT_DIRECT = 1
 VARIANT_FINGERPRINT = 2
 VARIANT_DNA = 3
+VARIANT_STRIDE = 4
 WRITE_AUTO = 0
 WRITE_SINGLE_PASS = 1
 WRITE_TWO_PHASE = 2
@@ -52,6 +54,7 @@ class PlanInfo(ctypes.Structure):
         ("table", ctypes.POINTER(ctypes.c_uint16)),
         ("device", ctypes.c_int32),
         ("kernel_class", ctypes.c_uint32),
+        ("stride", ctypes.c_uint32),
     ]
 
 

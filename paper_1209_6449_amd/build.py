@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libepsm.so")
-SOURCES = ["epsm_kernels.hip", "epsm_batch.hip", "epsm_api.hip", "epsm_serve.hip"]
+SOURCES = ["epsm_kernels.hip", "epsm_batch.hip", "epsm_stride.hip", "epsm_api.hip", "epsm_serve.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",

@@ -33,7 +33,8 @@ epsm_status hip_fail(hipError_t e, const char *what) {
 
 constexpr uint32_t kKnownPlanFlags = EPSM_PLAN_HOST_ONLY | EPSM_PLAN_FORCE_DIRECT |
                                      EPSM_PLAN_FORCE_FINGERPRINT | EPSM_PLAN_COLLIDE |
-                                     EPSM_PLAN_HASH_BITS(0xF) | EPSM_PLAN_DNA;
+                                     EPSM_PLAN_HASH_BITS(0xF) | EPSM_PLAN_DNA |
+                                     EPSM_PLAN_NO_STRIDE;
 constexpr uint32_t kDefaultHashBits = 11;  // k = 11 in Section 3.4
 
 // Default tile: 8 waves x 16 KiB per wave = 128 KiB per workgroup tile.
@@ -47,7 +48,8 @@ constexpr uint32_t kMaxTuneEntries = 256;
 
 uint32_t kernel_class(const DevPlan &d) {
     if (d.variant == EPSM_VARIANT_DNA) return EPSM_CLASS_DNA;
-    if (d.variant == EPSM_VARIANT_FINGERPRINT) return EPSM_CLASS_FINGERPRINT;
+    if (d.variant == EPSM_VARIANT_FINGERPRINT || d.variant == EPSM_VARIANT_STRIDE)
+        return EPSM_CLASS_FINGERPRINT;
     return (d.nl == 2 && d.pk < 4) ? EPSM_CLASS_BYTES : EPSM_CLASS_WORDS;
 }
 
@@ -178,6 +180,50 @@ epsm_status check_plan(epsm_plan_t plan) {
 }
 
 // Count (write = false) or positions (write = true) for one text.
+// Long patterns (strided filter): a count pass per workgroup, an exclusive
+// scan of the counts, then (positions) the write pass; the total is the
+// scan's last entry.  Workspace: [counts u32][offsets u64][scan block sums].
+epsm_status run_stride(epsm_plan_t plan, const uint8_t *d_text, uint64_t n, int64_t *d_out,
+                       uint64_t cap, uint64_t *d_n_hits, hipStream_t stream, bool write) {
+    const DevPlan &d = plan->dev;
+    StrideArgs a{};
+    const uintptr_t addr = (uintptr_t)d_text;
+    a.base = (const uint8_t *)(addr & ~uintptr_t(15));
+    a.delta = addr & 15;
+    a.last = a.delta + n - d.m;
+    a.load_end = (a.delta + n + 15) & ~uint64_t(15);
+    a.stride = d.stride;
+    a.hash_bits = kStrideHashBits;
+    a.table = d.stride_table;
+    a.pattern = d.pattern;
+    a.m = d.m;
+    a.first_block = (a.delta + a.stride - 1) / a.stride;
+    const uint64_t last_block = (a.last + a.stride - 1) / a.stride;
+    a.num_blocks = last_block >= a.first_block ? last_block - a.first_block + 1 : 0;
+    const uint64_t tiles = (a.num_blocks + kStrideBlocksPerTile - 1) / kStrideBlocksPerTile;
+    if (tiles > 0x7FFFFFFFull) return fail(EPSM_EUNSUPPORTED, "text too long for the tile grid");
+    const size_t cnt_bytes = (tiles * sizeof(uint32_t) + 255) & ~size_t(255);
+    const size_t off_bytes = ((tiles + 1) * sizeof(uint64_t) + 255) & ~size_t(255);
+    const size_t bsum_bytes = ((tiles + kScanBlock - 1) / kScanBlock + 1) * sizeof(uint64_t);
+    uint8_t *ws = nullptr;
+    epsm_status st = workspace_for(stream, cnt_bytes + off_bytes + bsum_bytes, &ws);
+    if (st != EPSM_OK) return st;
+    a.tile_count = (uint32_t *)ws;
+    uint64_t *offsets = (uint64_t *)(ws + cnt_bytes);
+    a.tile_offset = offsets;
+    hipError_t e = launch_stride(a, (uint32_t)tiles, stream);
+    if (e == hipSuccess)
+        e = launch_scan_counts(a.tile_count, tiles, offsets, (uint64_t *)(ws + cnt_bytes + off_bytes), stream);
+    if (e == hipSuccess && write && cap > 0) {
+        a.write = 1;
+        a.out = d_out;
+        a.cap = cap;
+        e = launch_stride(a, (uint32_t)tiles, stream);
+    }
+    if (e == hipSuccess) e = launch_copy_u64(offsets + tiles, d_n_hits, stream);
+    return e == hipSuccess ? EPSM_OK : hip_fail(e, "launch(stride)");
+}
+
 epsm_status run_search(epsm_plan_t plan, const uint8_t *d_text, uint64_t n, int64_t *d_out,
                        uint64_t cap, uint64_t *d_n_hits, hipStream_t stream, bool write,
                        bool dna = false) {
@@ -194,6 +240,8 @@ epsm_status run_search(epsm_plan_t plan, const uint8_t *d_text, uint64_t n, int6
         hipError_t e = launch_set_u64(d_n_hits, 0, stream);
         return e == hipSuccess ? EPSM_OK : hip_fail(e, "launch(set)");
     }
+    if (plan->dev.variant == EPSM_VARIANT_STRIDE)
+        return run_stride(plan, d_text, n, d_out, cap, d_n_hits, stream, write);
     // coordinates are bytes, or 2-bit symbols (four per byte) for packed DNA
     ScanArgs a{};
     const uint32_t sh = dna ? 2u : 0u;
@@ -306,6 +354,7 @@ epsm_status build_batch(const epsm_batch *b, int waves, HostBatch &hb, bool chec
             return fail(EPSM_EINVAL, "plan belongs to another device");
         BatchPairDesc &d = hb.pairs[k];
         d.plan = pr.plan->dev;
+        if (d.plan.variant == EPSM_VARIANT_STRIDE) d.plan.variant = EPSM_VARIANT_FINGERPRINT;  // tile filter
         d.text = pr.text;
         d.tiles = pr.plan->dev.m <= b->texts[pr.text].n ? text_tiles[pr.text] : 0;
         d.cnt_base = entries;
@@ -575,6 +624,28 @@ epsm_status epsm_plan(const uint8_t *pattern, uint64_t m, uint32_t flags, epsm_p
             p->table[v] |= (uint16_t)(1u << (8 - j));
         }
     }
+    // Long patterns: EPSMc with stride S (Section 3.4 inspects one block per
+    // stride), S the largest power of two <= min(m - 7, kStrideMax), at least
+    // kStrideMin; the table lists, per hash value, the offsets j in [0, S)
+    // of the pattern blocks p[j..j+7] with that hash, in ascending j.
+    const bool forced = flags & (EPSM_PLAN_FORCE_DIRECT | EPSM_PLAN_FORCE_FINGERPRINT | EPSM_PLAN_COLLIDE);
+    if (fingerprint && !forced && !(flags & EPSM_PLAN_NO_STRIDE) && m >= kStrideMin + 7) {
+        uint32_t S = kStrideMin;
+        while (S * 2 <= kStrideMax && S * 2 + 7 <= m) S *= 2;
+        const uint32_t buckets = 1u << kStrideHashBits;
+        std::vector<uint32_t> hv(S);
+        std::vector<uint16_t> &t = p->stride_table;
+        t.assign(buckets + 1 + S, 0);
+        for (uint32_t j = 0; j < S; ++j) {
+            hv[j] = fp_hash(load_le32(pattern, m, j), load_le32(pattern, m, j + 4), kStrideHashBits);
+            t[hv[j] + 1]++;
+        }
+        for (uint32_t v = 0; v < buckets; ++v) t[v + 1] += t[v];
+        std::vector<uint16_t> fillp(t.begin(), t.begin() + buckets);
+        for (uint32_t j = 0; j < S; ++j) t[buckets + 1 + fillp[hv[j]]++] = (uint16_t)j;
+        d.stride = S;
+        d.variant = EPSM_VARIANT_STRIDE;
+    }
 
     if (!(flags & EPSM_PLAN_HOST_ONLY)) {
         hipError_t e = hipGetDevice(&p->device);
@@ -585,7 +656,10 @@ epsm_status epsm_plan(const uint8_t *pattern, uint64_t m, uint32_t flags, epsm_p
         // one device block: [pattern, zero padded to 16 bytes][table]
         const size_t pat_bytes = (m + 15) & ~uint64_t(15);
         const size_t tab_bytes = p->table.size() * sizeof(uint16_t);
-        std::vector<uint8_t> staging(pat_bytes + tab_bytes, 0);
+        const size_t stab_bytes = p->stride_table.size() * sizeof(uint16_t);
+        std::vector<uint8_t> staging(pat_bytes + tab_bytes + stab_bytes, 0);
+        if (stab_bytes)
+            std::memcpy(staging.data() + pat_bytes + tab_bytes, p->stride_table.data(), stab_bytes);
         std::memcpy(staging.data(), pattern, m);
         if (tab_bytes) std::memcpy(staging.data() + pat_bytes, p->table.data(), tab_bytes);
         e = hipMalloc(&p->d_pattern, staging.size());
@@ -598,6 +672,7 @@ epsm_status epsm_plan(const uint8_t *pattern, uint64_t m, uint32_t flags, epsm_p
         }
         d.pattern = p->d_pattern;
         d.table = tab_bytes ? (const uint16_t *)(p->d_pattern + pat_bytes) : nullptr;
+        d.stride_table = stab_bytes ? (const uint16_t *)(p->d_pattern + pat_bytes + tab_bytes) : nullptr;
     }
     *out = p;
     return EPSM_OK;
@@ -624,6 +699,7 @@ epsm_status epsm_plan_get_info(epsm_plan_t plan, epsm_plan_info *info) {
     info->table = plan->table.empty() ? nullptr : plan->table.data();
     info->device = plan->device;
     info->kernel_class = kernel_class(d);
+    info->stride = d.stride;
     return EPSM_OK;
 }
 

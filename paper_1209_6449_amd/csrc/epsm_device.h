@@ -219,8 +219,8 @@ __device__ __forceinline__ uint32_t valid_mask(uint64_t s0, uint64_t delta, uint
 
 // Exact check of pattern bytes [4*nw, m) for each candidate (patterns longer
 // than the register run); reads the text and pattern from global memory.
-static __device__ __noinline__ uint32_t tail_check(uint32_t mk, uint64_t s0, const uint8_t *base,
-                                            const uint8_t *pattern, uint64_t m, uint32_t from) {
+static inline __device__ __noinline__ uint32_t tail_check(uint32_t mk, uint64_t s0, const uint8_t *base,
+                                                   const uint8_t *pattern, uint64_t m, uint32_t from) {
     uint32_t keep = 0;
     while (mk) {
         const uint32_t k = __builtin_ctz(mk);

@@ -12,6 +12,7 @@
 struct epsm_plan_s {
     std::vector<uint8_t> pattern;
     std::vector<uint16_t> table;  // host copy, fingerprint only
+    std::vector<uint16_t> stride_table;  // strided filter: bucket starts, then offsets
     epsm::DevPlan dev{};          // pointers filled for device plans
     uint32_t flags = 0;
     int device = -1;

@@ -47,6 +47,10 @@ struct DevPlan {
     uint32_t nl;             // dwordx4 loads per lane per piece (2 or 3)
     const uint16_t *table;   // fingerprint table, 2^k entries (device)
     const uint8_t *pattern;  // full pattern (device), for m > 4*nw
+    const uint16_t *stride_table;  // strided filter: [2^kStrideHashBits + 1] bucket
+                                   // starts, then [stride] offsets (device)
+    uint32_t stride;         // strided filter: bytes between inspected blocks
+    uint32_t pad_;
 };
 
 // One search over one text.
@@ -86,6 +90,34 @@ constexpr uint32_t kExpandTiles = 8;
 // Output capacity per tile up to which expand workgroups take kExpandTiles
 // tiles (above it, one tile each).
 constexpr uint64_t kExpandFewPerTile = 64;
+
+// ---- strided fingerprint filter (long patterns) ----------------------------
+constexpr int kStrideWaves = 8;
+constexpr int kStrideThreads = kStrideWaves * kWave;
+constexpr uint32_t kStrideBlocksPerLane = 4;
+constexpr uint64_t kStrideBlocksPerTile = (uint64_t)kStrideThreads * kStrideBlocksPerLane;
+constexpr uint32_t kStrideMin = 256, kStrideMax = 2048;  // S: powers of two, S <= m - 7
+constexpr uint32_t kStrideHashBits = 12;
+
+struct StrideArgs {
+    const uint8_t *base;      // 16-byte aligned address at or below the text start
+    uint64_t delta, last;     // valid starts are [delta, last] (base coordinates)
+    uint64_t load_end;        // readable bytes from base
+    uint64_t stride;          // S
+    uint32_t hash_bits;
+    uint32_t write;           // 0: per-workgroup counts; 1: positions
+    const uint16_t *table;    // bucket starts, then offsets
+    const uint8_t *pattern;
+    uint64_t m;
+    uint64_t first_block;     // inspected blocks are (first_block + b) * S, b < num_blocks
+    uint64_t num_blocks;
+    uint32_t *tile_count;     // [workgroups]
+    const uint64_t *tile_offset;  // [workgroups + 1], exclusive scan of tile_count
+    int64_t *out;
+    uint64_t cap;
+};
+hipError_t launch_stride(const StrideArgs &a, uint32_t tiles, hipStream_t s);
+hipError_t launch_copy_u64(const uint64_t *src, uint64_t *dst, hipStream_t s);
 
 // ---- batched search -------------------------------------------------------
 // A unit is one tile of one text; its workgroup loads the tile once and runs

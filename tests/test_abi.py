@@ -309,3 +309,22 @@ def test_struct_layouts_match_the_c_compiler(tmp_path):
         assert got[(cname, "size")] == C.sizeof(py), cname
         for field, _ in py._fields_:
             assert got[(cname, field)] == getattr(py, field).offset, (cname, field)
+
+
+@pytest.mark.parametrize("m,flags,variant,stride", [
+    (262, 0, epsm.VARIANT_FINGERPRINT, 0),
+    (263, 0, epsm.VARIANT_STRIDE, 256),
+    (518, 0, epsm.VARIANT_STRIDE, 256),
+    (519, 0, epsm.VARIANT_STRIDE, 512),
+    (4096, 0, epsm.VARIANT_STRIDE, 2048),
+    (1000, epsm.PLAN_NO_STRIDE, epsm.VARIANT_FINGERPRINT, 0),
+    (1000, epsm.PLAN_FORCE_FINGERPRINT, epsm.VARIANT_FINGERPRINT, 0),
+    (1000, epsm.PLAN_COLLIDE, epsm.VARIANT_FINGERPRINT, 0),
+    (1000, epsm.PLAN_FORCE_DIRECT, epsm.VARIANT_DIRECT, 0),
+])
+def test_long_pattern_variant_and_stride(m, flags, variant, stride):
+    """The stride is the largest power of two <= min(m - 7, 2048), at least 256."""
+    info = host_plan(bytes((5 * i + 3) % 256 for i in range(m)), flags)
+    assert info["variant"] == variant and info["stride"] == stride
+    if variant == epsm.VARIANT_STRIDE:
+        assert info["kernel_class"] == epsm.CLASS_FINGERPRINT and info["table"] is not None

@@ -292,3 +292,58 @@ def test_unary_text_two_phase_closed_form(epsm):
         epsm.stream_check()
     finally:
         epsm.set_tune_table([])
+
+
+def planted_text(rng, n, sigma, pattern, spots):
+    text = rng.integers(0, sigma, n).astype(np.uint8)
+    for o in spots:
+        if 0 <= o <= n - len(pattern):
+            text[o:o + len(pattern)] = np.frombuffer(pattern, dtype=np.uint8)
+    return text
+
+
+@pytest.mark.parametrize("m", [263, 300, 519, 1031, 2055, 4096])
+def test_strided_filter_matches_oracle(epsm, m):
+    """Long patterns (strided filter) against the oracle and against the
+    per-block filter: planted copies at both text ends, near block boundaries,
+    overlapping; sparse and binary texts; unaligned starts; counts."""
+    rng = np.random.default_rng(m)
+    for sigma in (2, 4, 64):
+        pattern = rng.integers(0, sigma, m).astype(np.uint8).tobytes()
+        for n in (m, m + 1, 3 * m + 17, 200_000 + m):
+            spots = [0, n - m, n // 2, (n // 2) + 1, (n // 3) & ~255, ((n // 3) & ~255) - 1]
+            text = planted_text(rng, n, sigma, pattern, spots)
+            for offset in (0, 5):
+                plan = epsm.Plan(pattern)
+                assert plan.info()["variant"] == epsm.VARIANT_STRIDE
+                say(f"stride m={m} sigma={sigma} n={n} offset={offset}")
+                t = to_gpu(text, offset)
+                got = epsm.search(t, plan).cpu().numpy()
+                exp = oracle.positions(text, pattern)
+                assert np.array_equal(got, exp), (m, sigma, n, offset, got[:5], exp[:5])
+                assert epsm.count(t, plan) == exp.size
+                base = epsm.search(t, epsm.Plan(pattern, epsm.PLAN_NO_STRIDE)).cpu().numpy()
+                assert np.array_equal(base, exp)
+    epsm.stream_check()
+
+
+@pytest.mark.parametrize("m", [263, 520, 2055])
+def test_strided_filter_periodic_text(epsm, m):
+    """a^n with a^m: every offset of the table is a candidate of every block;
+    n - m + 1 hits (closed form), truncated output is the prefix."""
+    n = 65_536 + 9
+    t = torch.full((n,), ord("a"), dtype=torch.uint8, device="cuda")
+    plan = epsm.Plan(b"a" * m)
+    assert plan.info()["variant"] == epsm.VARIANT_STRIDE
+    say(f"stride periodic m={m}")
+    got = epsm.search(t, plan)
+    assert got.numel() == n - m + 1
+    assert torch.equal(got, torch.arange(n - m + 1, dtype=torch.int64, device="cuda"))
+    for cap in (0, 1, 1000):
+        out = torch.full((cap + 2,), -3, dtype=torch.int64, device="cuda")
+        hits = torch.zeros(1, dtype=torch.int64, device="cuda")
+        epsm.search_into(plan, t, out[:cap], hits)
+        assert int(hits.item()) == n - m + 1
+        assert torch.equal(out[:cap].cpu(), torch.arange(cap, dtype=torch.int64))
+        assert bool((out[cap:] == -3).all())
+    epsm.stream_check()
