@@ -53,7 +53,7 @@ def parse_args():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="sweep1g", choices=["sweep1g", "zipf4g", "batch", "serve", "dna"])
+    ap.add_argument("--workload", default="sweep1g", choices=["sweep1g", "zipf4g", "batch", "serve", "dna", "long"])
     ap.add_argument("--serve-queries", type=int, default=1000, help="queries per serving run")
     ap.add_argument("--batch-texts", type=int, default=10_000, help="texts in the batch workload")
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
@@ -190,6 +190,71 @@ def run_dna_workload(args, torch, W, epsm):
                 "avg_launch_ms": round(pos_ms_total / len(cases), 4),
                 "alg_bytes_per_launch": round(pos_bytes / len(cases))}
     return n * 2 * len(cases) * args.steps / elapsed, elapsed / args.steps, config, detail, roofline
+
+
+def run_long_workload(args, torch, W, epsm):
+    """Long patterns on a 4 GiB Zipf text: the strided filter (one 8-byte
+    block per S bytes, S = 256..2048) against the per-block filter, with cut
+    patterns of m in {263, 300, 519, 1031, 2055, 4096}."""
+    spec, _, _, _ = W.config3()
+    n = spec.n
+    log("generating the 4 GiB Zipf text on the GPU")
+    text = W.gen_bytes(spec, device="cuda")
+    torch.cuda.synchronize()
+    g = W.rng(7, 1)
+    cases = []
+    for m in (263, 300, 519, 1031, 2055, 4096):
+        p, _ = W.cut_pattern(spec, m, g)
+        cases.append((p, epsm.Plan(p), epsm.Plan(p, epsm.PLAN_NO_STRIDE)))
+    hits = torch.zeros(1, dtype=torch.int64, device="cuda")
+    counts = []
+    for p, ps, pb in cases:
+        epsm.count_into(ps, text, hits)
+        c = int(hits.item())
+        epsm.count_into(pb, text, hits)
+        if int(hits.item()) != c:
+            raise AssertionError("strided and per-block counts differ")
+        counts.append(c)
+    out = torch.empty(max(max(counts), 1), dtype=torch.int64, device="cuda")
+
+    def timed(fn):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        fn()
+        e1.record()
+        return e0, e1
+
+    def step():
+        return [(timed(lambda: epsm.search_into(ps, text, out[:c], hits)),
+                 timed(lambda: epsm.count_into(ps, text, hits))) for (p, ps, pb), c in zip(cases, counts)]
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    evs = [step() for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    epsm.stream_check()
+    detail, pos_ms_total = [], 0.0
+    for i, ((p, ps, pb), c) in enumerate(zip(cases, counts)):
+        pm = sum(evs[s][i][0][0].elapsed_time(evs[s][i][0][1]) for s in range(args.steps)) / args.steps
+        cm = sum(evs[s][i][1][0].elapsed_time(evs[s][i][1][1]) for s in range(args.steps)) / args.steps
+        e = timed(lambda: epsm.count_into(pb, text, hits))
+        torch.cuda.synchronize()
+        bm = e[0].elapsed_time(e[1])
+        pos_ms_total += pm
+        stride = ps.info()["stride"]
+        detail.append({"m": len(p), "stride": stride, "hits": c, "positions_ms": round(pm, 4),
+                       "count_ms": round(cm, 4), "per_block_count_ms": round(bm, 4),
+                       "text_gbs_count": round(n / cm / 1e6, 1), "per_block_text_gbs": round(n / bm / 1e6, 1)})
+        if args.detail:
+            log(f"long m={len(p):4d} S={stride:4d} hits={c:3d} strided: positions {pm:7.3f} ms count {cm:7.3f} ms "
+                f"({n / cm / 1e6:8.1f} GB/s of text) | per-block count {bm:7.3f} ms ({n / bm / 1e6:7.1f} GB/s)")
+    config = {"workload": "long: 4 GiB Zipf(1) 96-symbol text, cut patterns m in {263,300,519,1031,2055,4096}; "
+                          "strided filter; positions+count modes",
+              "text_bytes": n, "searches_per_step": 2 * len(cases)}
+    return n * 2 * len(cases) * args.steps / elapsed, elapsed / args.steps, config, detail, pos_ms_total
 
 
 def run_batch_workload(args, torch, W, epsm):
@@ -422,6 +487,17 @@ def main():
             "ms_per_step": round(step_s * 1e3, 3), "higher_is_better": True, "scaling": "weak",
             "vs_baseline": None, "dtype": "u2", "data": "synthetic", "config": dict(config, tuning=tuning),
             "dna": detail, "roofline": roofline, "cpu_baseline": None,
+        }
+        print(json.dumps(result), flush=True)
+        return
+    if args.workload == "long":
+        tb_s, step_s, config, detail, _ = run_long_workload(args, torch, W, epsm)
+        result = {
+            "metric": METRIC, "value": round(tb_s / 1e9, 1), "unit": "GB/s", "n_gpus": 1,
+            "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(step_s * 1e3, 3),
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u8",
+            "data": "synthetic", "config": dict(config, tuning=tuning), "long": detail,
+            "roofline": None, "cpu_baseline": None,
         }
         print(json.dumps(result), flush=True)
         return

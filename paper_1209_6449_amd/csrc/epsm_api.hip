@@ -195,6 +195,7 @@ epsm_status run_stride(epsm_plan_t plan, const uint8_t *d_text, uint64_t n, int6
     a.stride = d.stride;
     a.hash_bits = kStrideHashBits;
     a.table = d.stride_table;
+    a.blocks = d.stride_blocks;
     a.pattern = d.pattern;
     a.m = d.m;
     a.first_block = (a.delta + a.stride - 1) / a.stride;
@@ -643,6 +644,13 @@ epsm_status epsm_plan(const uint8_t *pattern, uint64_t m, uint32_t flags, epsm_p
         for (uint32_t v = 0; v < buckets; ++v) t[v + 1] += t[v];
         std::vector<uint16_t> fillp(t.begin(), t.begin() + buckets);
         for (uint32_t j = 0; j < S; ++j) t[buckets + 1 + fillp[hv[j]]++] = (uint16_t)j;
+        // the pattern block of each listed offset, in the same order
+        p->stride_blocks.resize(2 * (size_t)S);
+        for (uint32_t i = 0; i < S; ++i) {
+            const uint32_t j = t[buckets + 1 + i];
+            p->stride_blocks[2 * i] = load_le32(pattern, m, j);
+            p->stride_blocks[2 * i + 1] = load_le32(pattern, m, j + 4);
+        }
         d.stride = S;
         d.variant = EPSM_VARIANT_STRIDE;
     }
@@ -656,10 +664,14 @@ epsm_status epsm_plan(const uint8_t *pattern, uint64_t m, uint32_t flags, epsm_p
         // one device block: [pattern, zero padded to 16 bytes][table]
         const size_t pat_bytes = (m + 15) & ~uint64_t(15);
         const size_t tab_bytes = p->table.size() * sizeof(uint16_t);
+        const size_t sblk_bytes = p->stride_blocks.size() * sizeof(uint32_t);  // first: 8-byte aligned
         const size_t stab_bytes = p->stride_table.size() * sizeof(uint16_t);
-        std::vector<uint8_t> staging(pat_bytes + tab_bytes + stab_bytes, 0);
+        std::vector<uint8_t> staging(pat_bytes + tab_bytes + sblk_bytes + stab_bytes, 0);
+        if (sblk_bytes)
+            std::memcpy(staging.data() + pat_bytes + tab_bytes, p->stride_blocks.data(), sblk_bytes);
         if (stab_bytes)
-            std::memcpy(staging.data() + pat_bytes + tab_bytes, p->stride_table.data(), stab_bytes);
+            std::memcpy(staging.data() + pat_bytes + tab_bytes + sblk_bytes, p->stride_table.data(),
+                        stab_bytes);
         std::memcpy(staging.data(), pattern, m);
         if (tab_bytes) std::memcpy(staging.data() + pat_bytes, p->table.data(), tab_bytes);
         e = hipMalloc(&p->d_pattern, staging.size());
@@ -672,7 +684,9 @@ epsm_status epsm_plan(const uint8_t *pattern, uint64_t m, uint32_t flags, epsm_p
         }
         d.pattern = p->d_pattern;
         d.table = tab_bytes ? (const uint16_t *)(p->d_pattern + pat_bytes) : nullptr;
-        d.stride_table = stab_bytes ? (const uint16_t *)(p->d_pattern + pat_bytes + tab_bytes) : nullptr;
+        d.stride_blocks = sblk_bytes ? (const uint2 *)(p->d_pattern + pat_bytes + tab_bytes) : nullptr;
+        d.stride_table =
+            stab_bytes ? (const uint16_t *)(p->d_pattern + pat_bytes + tab_bytes + sblk_bytes) : nullptr;
     }
     *out = p;
     return EPSM_OK;

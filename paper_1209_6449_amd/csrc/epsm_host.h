@@ -13,6 +13,7 @@ struct epsm_plan_s {
     std::vector<uint8_t> pattern;
     std::vector<uint16_t> table;  // host copy, fingerprint only
     std::vector<uint16_t> stride_table;  // strided filter: bucket starts, then offsets
+    std::vector<uint32_t> stride_blocks; // strided filter: pattern blocks (lo, hi) per offset
     epsm::DevPlan dev{};          // pointers filled for device plans
     uint32_t flags = 0;
     int device = -1;

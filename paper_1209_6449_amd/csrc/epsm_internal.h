@@ -49,6 +49,7 @@ struct DevPlan {
     const uint8_t *pattern;  // full pattern (device), for m > 4*nw
     const uint16_t *stride_table;  // strided filter: [2^kStrideHashBits + 1] bucket
                                    // starts, then [stride] offsets (device)
+    const uint2 *stride_blocks;    // strided filter: [stride] pattern blocks in offset order
     uint32_t stride;         // strided filter: bytes between inspected blocks
     uint32_t pad_;
 };
@@ -107,6 +108,7 @@ struct StrideArgs {
     uint32_t hash_bits;
     uint32_t write;           // 0: per-workgroup counts; 1: positions
     const uint16_t *table;    // bucket starts, then offsets
+    const uint2 *blocks;      // [stride] pattern blocks p[j..j+7] (lo, hi) in offset order
     const uint8_t *pattern;
     uint64_t m;
     uint64_t first_block;     // inspected blocks are (first_block + b) * S, b < num_blocks
