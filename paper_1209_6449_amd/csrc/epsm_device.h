@@ -424,6 +424,7 @@ __device__ __forceinline__ uint32_t process_chunk(const uint32_t (&w)[U][NL * 4 
                 mk = tail_check(mk, s0, a.base, a.plan.pattern, a.plan.m, 4u * a.plan.nw);
         }
         cnt += __popc(mk);
+        if (a.write == 0) continue;  // count only: the masks are not needed
         if (u & 1) s_mask[piece >> 1][tid] = lo | (mk << 16);
         else lo = mk;
     }
