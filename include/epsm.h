@@ -372,7 +372,8 @@ epsm_status epsm_server_submit(epsm_server_t s, uint32_t text_id, const uint8_t 
  * until epsm_server_release(query_id). */
 epsm_status epsm_server_poll(epsm_server_t s, epsm_query_result *out, uint32_t max,
                              uint32_t *n_out, uint32_t wait_us);
-/* Free a completed query's results. */
+/* Free the results of a query that epsm_server_poll has returned;
+ * EPSM_EINVAL for an unknown id or a query not yet returned by a poll. */
 epsm_status epsm_server_release(epsm_server_t s, uint64_t query_id);
 /* Server clock in seconds (the time base of the result timestamps). */
 double epsm_server_now(epsm_server_t s);

@@ -41,6 +41,7 @@ struct Query {
     double submit = 0, start = 0, done = 0;
     int32_t status = EPSM_OK;
     uint32_t batch_queries = 0;
+    bool polled = false;              // handed out by epsm_server_poll
     std::vector<uint64_t> counts, offsets;
     std::vector<int64_t> positions;
     uint64_t total = 0;
@@ -63,11 +64,11 @@ struct Pinned {  // growable pinned host buffer
     size_t cap = 0;
     hipError_t reserve(size_t n) {
         if (n <= cap) return hipSuccess;
+        size_t want = std::max<size_t>(n, 2 * cap);
+        want = std::max<size_t>(want, 1024);
         if (ptr) (void)hipHostFree(ptr);
         ptr = nullptr;
         cap = 0;
-        size_t want = std::max<size_t>(n, 2 * cap);
-        want = std::max<size_t>(want, 1024);
         hipError_t e = hipHostMalloc((void **)&ptr, want * sizeof(T), hipHostMallocDefault);
         if (e == hipSuccess) cap = want;
         else ptr = nullptr;
@@ -352,6 +353,7 @@ void epsm_server_s::run() {
         q->status = EPSM_EDEVICE;
         q->done = now();
         completed.push_back(q);
+        ++done;
     }
     cv_done.notify_all();
 }
@@ -461,6 +463,7 @@ epsm_status epsm_server_poll(epsm_server_t s, epsm_query_result *out, uint32_t m
         r.submit_time = q->submit;
         r.start_time = q->start;
         r.done_time = q->done;
+        q->polled = true;
         out[n++] = r;
     }
     *n_out = n;
@@ -472,7 +475,9 @@ epsm_status epsm_server_release(epsm_server_t s, uint64_t query_id) {
     std::lock_guard<std::mutex> lk(s->mu);
     auto it = s->queries.find(query_id);
     if (it == s->queries.end()) return fail(EPSM_EINVAL, "unknown query id");
-    if (it->second->done == 0) return fail(EPSM_EINVAL, "query has not completed");
+    // only a query already returned by epsm_server_poll: the completion queue
+    // still points at one that has completed but not been polled
+    if (!it->second->polled) return fail(EPSM_EINVAL, "query has not been returned by epsm_server_poll");
     s->queries.erase(it);
     return EPSM_OK;
 }

@@ -109,3 +109,22 @@ def test_empty_query_and_bad_text_id(env):
             srv.submit(5, [b"ab"])
         with pytest.raises(epsm.EpsmError):
             srv.submit(0, [b""])  # m = 0
+
+
+def test_release_only_after_poll(env):
+    epsm, serve, texts, host, queries = env
+    import time
+    with serve.Server(slots=1) as srv:
+        srv.add_text(texts[0])
+        qid = srv.submit(0, [b"ab", b"abc"])
+        L = epsm.lib()
+        deadline = time.time() + 60
+        while srv.stats()["completed"] < 1 and time.time() < deadline:
+            time.sleep(0.001)
+        # completed but not yet polled: its results are still queued
+        assert L.epsm_server_release(srv._h, qid) != 0
+        got = []
+        while not got:
+            got = srv.poll(1, 100_000)  # poll() releases what it returns
+        assert got[0].query_id == qid and got[0].status == 0
+        assert L.epsm_server_release(srv._h, qid) != 0  # already released
