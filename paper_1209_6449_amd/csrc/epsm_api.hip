@@ -800,6 +800,10 @@ epsm_status epsm_batch_prepare(const epsm_batch *batch, epsm_batch_plan_t *out) 
     bp->hb.order.shrink_to_fit();
     bp->hb.blob.clear();
     bp->hb.blob.shrink_to_fit();
+    bp->hb.solo = std::vector<uint32_t>();
+    bp->hb.groups = std::vector<BatchGroupDesc>();
+    bp->hb.group_pairs = std::vector<uint32_t>();
+    bp->hb.group_tables = std::vector<uint32_t>();
     bp->hb.units.shrink_to_fit();
     *out = bp;
     return EPSM_OK;
