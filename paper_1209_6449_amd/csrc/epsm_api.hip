@@ -75,36 +75,40 @@ SearchChoice choice_for(const DevPlan &d, bool count_only, uint64_t n) {
     return {g_tile, EPSM_WRITE_AUTO};
 }
 
-// Device workspace of one search: [count bins][look-back status words] or
-// [count bins][group sums][wave counts][slots].
+// Device workspace of one search: [tile counts] (count only), [look-back
+// status words] (single pass, cleared before the scan), or [tile counts][tile
+// offsets][wave counts][slots] (two phase).  Only the status words are
+// cleared; every other entry is written before it is read.
 struct SearchWorkspace {
-    size_t bins = 0, status = 0, gsum = 0, wcnt = 0, slots = 0, total = 0, zeroed = 0;
+    size_t tcnt = 0, status = 0, toff = 0, wcnt = 0, slots = 0, total = 0, zeroed = 0;
 };
 
 SearchWorkspace search_workspace(uint64_t tiles, TileConfig tile, uint32_t write) {
     SearchWorkspace w;
-    size_t at = kCountBins * sizeof(uint64_t);
+    size_t at = 0;
     if (write == kWriteLookBack) {
         w.status = at;
         at += tiles * sizeof(uint64_t);
         w.zeroed = at;
     } else if (write == kWriteTwoPhase) {
-        w.gsum = at;
-        at += ((tiles + kGroupTiles - 1) / kGroupTiles) * sizeof(uint64_t);
-        w.zeroed = at;
+        w.tcnt = at;
+        at += ((tiles * sizeof(uint32_t)) + 255) & ~size_t(255);
+        w.toff = at;
+        at += (((tiles + 1) * sizeof(uint64_t)) + 255) & ~size_t(255);
         w.wcnt = at;
         at += ((tiles * (uint64_t)tile.waves * sizeof(uint32_t)) + 255) & ~size_t(255);
         w.slots = at;
         at += tiles * (uint64_t)tile.bytes() / 32 * sizeof(uint32_t);
     } else {
-        w.zeroed = at;
+        w.tcnt = at;
+        at += tiles * sizeof(uint32_t);
     }
-    w.total = at;
+    w.total = std::max<size_t>(at, 256);
     return w;
 }
 
 
-// ---- workspace: count bins and look-back status words, one buffer per stream ----
+// ---- workspace: one device buffer per (device, stream), grown on demand ----
 struct Workspace {
     uint8_t *ptr = nullptr;
     size_t bytes = 0;
@@ -274,23 +278,28 @@ epsm_status run_search(epsm_plan_t plan, const uint8_t *d_text, uint64_t n, int6
     uint8_t *ws = nullptr;
     st = workspace_for(stream, L.total, &ws);
     if (st != EPSM_OK) return st;
-    a.bins = (uint64_t *)ws;
+    a.tcnt = (uint32_t *)(ws + L.tcnt);
     a.status = (uint64_t *)(ws + L.status);
-    a.gsum = (uint64_t *)(ws + L.gsum);
+    a.toff = (uint64_t *)(ws + L.toff);
     a.wcnt = (uint32_t *)(ws + L.wcnt);
     a.slots = (uint32_t *)(ws + L.slots);
     a.fault = fault_word(stream);
     if (!a.fault) return fail(EPSM_ENOMEM, "fault word allocation");
-    hipError_t e = launch_zero_u64((uint64_t *)ws, L.zeroed / 8, stream);
-    if (e != hipSuccess) return hip_fail(e, "launch(zero)");
+    hipError_t e = hipSuccess;
+    if (L.zeroed) {
+        e = launch_zero_u64((uint64_t *)ws, L.zeroed / 8, stream);
+        if (e != hipSuccess) return hip_fail(e, "launch(zero)");
+    }
 
     e = launch_scan(a, tile, (int)tiles, stream);
     if (e != hipSuccess) return hip_fail(e, "launch(scan)");
     if (a.write == kWriteNone)
-        e = launch_sum_bins(a.bins, d_n_hits, stream);
-    else if (a.write == kWriteTwoPhase)
-        e = launch_expand(a, tile, stream);
-    if (e != hipSuccess) return hip_fail(e, "launch(sum_bins/expand)");
+        e = launch_sum_tiles(a.tcnt, a.num_tiles, d_n_hits, stream);
+    else if (a.write == kWriteTwoPhase) {
+        e = launch_tile_offsets(a.tcnt, a.num_tiles, a.toff, d_n_hits, stream);
+        if (e == hipSuccess) e = launch_expand(a, tile, stream);
+    }
+    if (e != hipSuccess) return hip_fail(e, "launch(sum_tiles/expand)");
     return EPSM_OK;
 }
 

@@ -19,9 +19,6 @@ constexpr uint64_t kValueMask = (1ull << 62) - 1;
 // cycles plus a memory round trip: several seconds in total).  Every wait is
 // expected to end long before; the bound only guarantees the kernel drains.
 constexpr uint32_t kSpinLimit = 1u << 22;
-// Count-only searches add per-tile counts into this many words (spreading
-// the device-scope atomics over many addresses) and then sum them.
-constexpr int kCountBins = 256;
 
 // Fingerprint hash of an aligned 8-byte text block (lo = bytes 0..3, hi =
 // bytes 4..7, little endian), reduced to `bits` bits.  A two-multiply
@@ -64,10 +61,11 @@ struct ScanArgs {
     uint64_t cap;
     uint64_t *n_hits;        // full count (device)
     uint64_t *status;        // [num_tiles] look-back words, zeroed before launch
-    uint64_t *bins;          // [kCountBins] count-only partial sums, zeroed before launch
+    uint32_t *tcnt;          // count only and two-phase: [num_tiles] hits of each tile
+                             // (every entry written)
     uint32_t *fault;         // set to 1 if a bounded wait gave up (never expected)
     uint32_t *wcnt;          // two-phase: [num_tiles * waves] hits of each wave of each tile
-    uint64_t *gsum;          // two-phase: [ceil(num_tiles / kGroupTiles)] hits per tile group, zeroed
+    uint64_t *toff;          // two-phase: [num_tiles + 1] exclusive prefix of tcnt (tile_offsets_kernel)
     uint32_t *slots;         // two-phase: [num_tiles * tile_bytes / 32] list or masks per tile
     uint32_t num_tiles;
     uint32_t shift;          // coordinates per text byte, log2: 0 bytes, 2 packed DNA
@@ -84,9 +82,7 @@ struct ScanArgs {
 constexpr uint32_t kWriteNone = 0;
 constexpr uint32_t kWriteLookBack = 1;
 constexpr uint32_t kWriteTwoPhase = 2;
-// Tiles per group sum, and the most tiles per expand workgroup, of the
-// two-phase write.
-constexpr uint32_t kGroupTiles = 64;
+// The most tiles per expand workgroup of the two-phase write.
 constexpr uint32_t kExpandTiles = 8;
 // Output capacity per tile up to which expand workgroups take kExpandTiles
 // tiles (above it, one tile each).
@@ -212,7 +208,12 @@ hipError_t launch_set_u64(uint64_t *p, uint64_t value, hipStream_t s);
 // 2-bit packing of n symbol codes (low two bits of each byte) into
 // ceil(n/4) bytes, symbol i at bits 2*(i%4) of byte i/4.
 hipError_t launch_pack_dna(const uint8_t *codes, uint64_t n, uint8_t *packed, hipStream_t s);
-hipError_t launch_sum_bins(const uint64_t *bins, uint64_t *out, hipStream_t s);
+// *out = sum of tcnt[0 .. tiles) (one workgroup).
+hipError_t launch_sum_tiles(const uint32_t *tcnt, uint32_t tiles, uint64_t *out, hipStream_t s);
+// toff[i] = sum of tcnt[0 .. i) for i <= tiles, and *total = toff[tiles]
+// (one workgroup).
+hipError_t launch_tile_offsets(const uint32_t *tcnt, uint32_t tiles, uint64_t *toff, uint64_t *total,
+                            hipStream_t s);
 hipError_t launch_scan(const ScanArgs &a, TileConfig cfg, int grid, hipStream_t s);
 // Second phase of a two-phase search: slots -> positions, and *n_hits.
 hipError_t launch_expand(ScanArgs a, TileConfig cfg, hipStream_t s);

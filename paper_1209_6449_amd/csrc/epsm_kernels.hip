@@ -30,9 +30,11 @@
 // the predecessors' status words gives its exclusive prefix, so it writes
 // its positions itself.  Two phase: the tile parks its hits in its own
 // workspace slot (an ascending list of tile offsets when there are at most
-// tile/32 of them, else the raw masks), stores its per-wave counts and adds
-// its count to a group sum, and never waits; a second kernel computes each
-// tile's offset from the sums and expands the slots.  Measured on 1 GiB
+// tile/32 of them, else the raw masks), stores its per-wave and tile counts
+// and never waits; one workgroup then scans the tile counts into offsets, and
+// a third kernel expands the slots.  No atomics and nothing to clear (in
+// count mode, one atomic add per tile into 256 bins cost up to 10% of the
+// rate when every tile had hits).  Measured on 1 GiB
 // texts, the look-back costs about a quarter of the scan rate even when no
 // position is written (a waiting workgroup issues no loads), while the two
 // phase scan runs at the count-only rate; single pass stays ahead for dense
@@ -43,8 +45,8 @@
 // trip, so tiles are large (64 * 128 KiB per round trip); and a persistent
 // workgroup that walks several consecutive tiles delays the counts of its
 // later tiles behind the writes of its earlier ones, which serialises the
-// chain, so workgroups are not persistent.  Count-only searches add tile
-// counts into 256 bins.
+// chain, so workgroups are not persistent.  Count-only searches store one
+// count per tile (no atomics, nothing to clear) and a second kernel sums them.
 #include "epsm_device.h"
 
 namespace epsm {
@@ -169,18 +171,15 @@ void scan_kernel(ScanArgs a) {
     for (int i = 0; i < WAVES; ++i) tile_cnt += s_wcnt[i];
 
     if (a.write == kWriteNone) {
-        // count only: no ordering needed; spread the adds over kCountBins words
-        if (tid == 0 && tile_cnt)
-            atomicAdd((unsigned long long *)&a.bins[tile & (kCountBins - 1)],
-                      (unsigned long long)tile_cnt);
+        // count only: a plain store per tile, summed by one more kernel
+        if (tid == 0) a.tcnt[tile] = (uint32_t)tile_cnt;
         return;
     }
     if (a.write == kWriteTwoPhase) {
         // park the hits in the tile's slot; nothing waits on other tiles
         constexpr uint32_t kSlotWords = kTile / 32;  // = words of s_mask
         if (lane == 0) a.wcnt[(size_t)tile * WAVES + wave] = wtot;
-        if (tid == 0 && tile_cnt)
-            atomicAdd((unsigned long long *)&a.gsum[tile / kGroupTiles], (unsigned long long)tile_cnt);
+        if (tid == 0) a.tcnt[tile] = (uint32_t)tile_cnt;
         if (tile_cnt == 0) return;
         uint32_t *slot = a.slots + (size_t)tile * kSlotWords;
         if (tile_cnt > kSlotWords) {
@@ -237,18 +236,14 @@ __global__ __launch_bounds__(WAVES * kWave) void expand_kernel(ScanArgs a) {
     __shared__ uint32_t s_mk[WAVES][kPairs][kWave];
     __shared__ uint32_t s_wc[kExpandTiles][WAVES];
     __shared__ uint32_t s_tot[kExpandTiles];
-    __shared__ uint64_t s_part[WAVES];
     const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
     const uint32_t first = blockIdx.x * a.expand_tiles;  // num_tiles < 2^31
     const uint32_t cnt = min(first + a.expand_tiles, a.num_tiles) - first;
+    uint64_t pos = a.toff[first];
+    if (a.toff[first + cnt] == pos) return;  // no hits in these tiles
 
-    // prefix of the first tile (group sums, then the group's earlier tiles)
-    // and the wave counts and totals of this workgroup's tiles
-    const uint32_t g0 = first / kGroupTiles;
-    uint64_t v = 0;
-    for (uint32_t g = tid; g < g0; g += kThreads) v += a.gsum[g];
-    for (uint64_t i = (uint64_t)g0 * kGroupTiles * WAVES + tid; i < (uint64_t)first * WAVES; i += kThreads)
-        v += a.wcnt[i];
+    // the wave counts and totals of this workgroup's tiles; the output offset
+    // of its first tile comes from the tile offsets
     if (tid < kExpandTiles * WAVES)
         (&s_wc[0][0])[tid] = (uint32_t)tid < cnt * WAVES ? a.wcnt[(uint64_t)first * WAVES + tid] : 0;
     if (tid < kExpandTiles) {
@@ -257,12 +252,7 @@ __global__ __launch_bounds__(WAVES * kWave) void expand_kernel(ScanArgs a) {
             for (int w = 0; w < WAVES; ++w) t += a.wcnt[((uint64_t)first + tid) * WAVES + w];
         s_tot[tid] = t;
     }
-    v = wave_sum64(v);
-    if (lane == 0) s_part[wave] = v;
     __syncthreads();
-    uint64_t pos = 0;
-#pragma unroll
-    for (int i = 0; i < WAVES; ++i) pos += s_part[i];
 
     auto next_dense = [&](uint32_t i) {
         while (i < cnt && s_tot[i] <= kSlotWords) ++i;
@@ -312,25 +302,95 @@ __global__ __launch_bounds__(WAVES * kWave) void expand_kernel(ScanArgs a) {
         }
         pos += tot;
     }
-    if (first + cnt == a.num_tiles && tid == 0) *a.n_hits = pos;
 }
 
-// Sum of the count bins into *out (one workgroup of kCountBins threads).
-__global__ __launch_bounds__(kCountBins) void sum_bins_kernel(const uint64_t *bins, uint64_t *out) {
-    __shared__ uint64_t s_part[kCountBins / kWave];
-    const int tid = threadIdx.x;
-    const uint64_t v = wave_sum64(bins[tid]);
-    if ((tid & (kWave - 1)) == 0) s_part[tid / kWave] = v;
-    __syncthreads();
+// One workgroup reads the per-tile counts in chunks: thread i of the chunk at
+// c0 owns tiles c0 + kRunTiles * i + j, j < kRunTiles, loaded as independent
+// buffer loads (zero past the last tile), all in flight before the first is
+// used.  A run of kRunTiles tiles holds at most 2^24 hits (tiles are at most
+// 2^20 coordinates), a wave's runs at most 2^30.
+constexpr int kSumThreads = 1024;
+constexpr uint32_t kRunTiles = 16;
+constexpr uint32_t kChunkTiles = kSumThreads * kRunTiles;
+
+__device__ __forceinline__ uint32_t load_run(const uint32_t *tcnt, uint32_t tiles, uint32_t c0, int tid,
+                                             uint32_t (&v)[kRunTiles]) {
+    const uint32_t left = tiles - c0;
+    const __amdgpu_buffer_rsrc_t r = make_rsrc(reinterpret_cast<const uint8_t *>(tcnt + c0),
+                                               (left < kChunkTiles ? left : kChunkTiles) * 4u);
+#pragma unroll
+    for (uint32_t j = 0; j < kRunTiles; ++j)
+        v[j] = __builtin_amdgcn_raw_buffer_load_b32(r, (int)(((uint32_t)tid * kRunTiles + j) * 4u), 0, 0);
+    uint32_t run = 0;
+#pragma unroll
+    for (uint32_t j = 0; j < kRunTiles; ++j) run += v[j];
+    return run;
+}
+
+// Sum of the per-tile counts into *out (one workgroup).
+__global__ __launch_bounds__(kSumThreads) void sum_tiles_kernel(const uint32_t *tcnt, uint32_t tiles,
+                                                                 uint64_t *out) {
+    __shared__ uint32_t s_wave[kSumThreads / kWave];
+    const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
+    uint64_t total = 0;
+#pragma unroll 1
+    for (uint32_t c0 = 0; c0 < tiles; c0 += kChunkTiles) {
+        uint32_t v[kRunTiles];
+        const uint32_t w = wave_sum32(load_run(tcnt, tiles, c0, tid, v));
+        if (lane == 0) s_wave[wave] = w;
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < kSumThreads / kWave; ++i) total += s_wave[i];
+        __syncthreads();
+    }
+    if (tid == 0) *out = total;
+}
+
+// Exclusive scan of the per-tile counts, toff[i] = sum of tcnt[0 .. i) for
+// i <= tiles, and *total = toff[tiles] (one workgroup): per chunk, a wave scan
+// of the runs, the wave totals across the workgroup, then each thread writes
+// the offsets of its run.
+__global__ __launch_bounds__(kSumThreads) void tile_offsets_kernel(const uint32_t *tcnt, uint32_t tiles,
+                                                                   uint64_t *toff, uint64_t *total) {
+    __shared__ uint32_t s_wave[kSumThreads / kWave];
+    const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
+    uint64_t carry = 0;
+#pragma unroll 1
+    for (uint32_t c0 = 0; c0 < tiles; c0 += kChunkTiles) {
+        uint32_t v[kRunTiles];
+        const uint32_t run = load_run(tcnt, tiles, c0, tid, v);
+        const uint32_t incl = wave_incl_scan32(run);
+        if (lane == kWave - 1) s_wave[wave] = incl;
+        __syncthreads();
+        uint64_t at = carry + (incl - run), chunk = 0;
+#pragma unroll
+        for (int i = 0; i < kSumThreads / kWave; ++i) {
+            at += i < wave ? s_wave[i] : 0u;
+            chunk += s_wave[i];
+        }
+        const uint64_t i0 = (uint64_t)c0 + (uint32_t)tid * kRunTiles;
+#pragma unroll
+        for (uint32_t j = 0; j < kRunTiles; ++j) {
+            if (i0 + j < tiles) toff[i0 + j] = at;
+            at += v[j];
+        }
+        carry += chunk;
+        __syncthreads();
+    }
     if (tid == 0) {
-        uint64_t total = 0;
-        for (int i = 0; i < kCountBins / kWave; ++i) total += s_part[i];
-        *out = total;
+        toff[tiles] = carry;
+        *total = carry;
     }
 }
 
-hipError_t launch_sum_bins(const uint64_t *bins, uint64_t *out, hipStream_t s) {
-    hipLaunchKernelGGL(sum_bins_kernel, dim3(1), dim3(kCountBins), 0, s, bins, out);
+hipError_t launch_tile_offsets(const uint32_t *tcnt, uint32_t tiles, uint64_t *toff, uint64_t *total,
+                            hipStream_t s) {
+    hipLaunchKernelGGL(tile_offsets_kernel, dim3(1), dim3(kSumThreads), 0, s, tcnt, tiles, toff, total);
+    return hipGetLastError();
+}
+
+hipError_t launch_sum_tiles(const uint32_t *tcnt, uint32_t tiles, uint64_t *out, hipStream_t s) {
+    hipLaunchKernelGGL(sum_tiles_kernel, dim3(1), dim3(kSumThreads), 0, s, tcnt, tiles, out);
     return hipGetLastError();
 }
 
@@ -461,9 +521,9 @@ static ExpandFn pick_expand(TileConfig cfg) {
 hipError_t launch_expand(ScanArgs a, TileConfig cfg, hipStream_t s) {
     ExpandFn fn = pick_expand(cfg);
     if (!fn) return hipErrorInvalidValue;
-    // A few positions per tile: 8 tiles per workgroup, so the counts before
-    // the workgroup are read by fewer workgroups.  More: one tile each, so
-    // that every list is copied by its own workgroup in parallel.
+    // A few positions per tile: 8 tiles per workgroup, fewer workgroups to
+    // launch.  More: one tile each, so that every list is copied by its own
+    // workgroup in parallel.
     a.expand_tiles = a.cap <= (uint64_t)a.num_tiles * kExpandFewPerTile ? kExpandTiles : 1;
     const uint32_t grid = (a.num_tiles + a.expand_tiles - 1) / a.expand_tiles;
     hipLaunchKernelGGL(fn, dim3(grid), dim3(cfg.waves * kWave), 0, s, a);

@@ -178,7 +178,7 @@ def main(argv=None):
         t.add_argument("--" + k.replace("_", "-"), dest=k, required=True)
     t.add_argument("--calib-bytes", type=int, default=1 << 30)
     t.add_argument("--calib-kernel", default="copy")
-    t.add_argument("--kernel", default="scan_kernel,expand_kernel,zero_u64",
+    t.add_argument("--kernel", default="scan_kernel,expand_kernel,zero_u64,tile_offsets_kernel",
                    help="comma-separated kernel names; the first counts the units")
     t.add_argument("--workload", default="sweep1g")
     t.add_argument("--command", required=True)

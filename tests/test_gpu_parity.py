@@ -294,6 +294,30 @@ def test_unary_text_two_phase_closed_form(epsm):
         epsm.set_tune_table([])
 
 
+@pytest.mark.parametrize("strategy", [1, 2], ids=["single_pass", "two_phase"])
+def test_unary_text_beyond_2_32_positions(epsm, strategy):
+    """a^n with n > 2^32 on 64 KiB tiles: 65 539 tiles (several chunks of the
+    per-tile count sums and offsets), more than 2^32 positions (34 GB of
+    int64) and counts above 2^32; positions checked against i in slices."""
+    force(epsm, (8, 8), strategy)
+    try:
+        n = (1 << 32) + 3 * 65536 + 5
+        t = torch.full((n,), ord("a"), dtype=torch.uint8, device="cuda")
+        for m in (1, 6):
+            say(f"unary beyond 2^32 strategy {strategy} n={n} m={m}")
+            assert epsm.count(t, b"a" * m) == n - m + 1
+            got = epsm.search(t, b"a" * m)
+            assert got.numel() == n - m + 1
+            step = 1 << 28
+            for s in range(0, got.numel(), step):
+                e = min(s + step, got.numel())
+                assert torch.equal(got[s:e], torch.arange(s, e, dtype=torch.int64, device="cuda")), s
+            del got
+        epsm.stream_check()
+    finally:
+        epsm.set_tune_table([])
+
+
 def planted_text(rng, n, sigma, pattern, spots):
     text = rng.integers(0, sigma, n).astype(np.uint8)
     for o in spots:
