@@ -304,75 +304,102 @@ __global__ __launch_bounds__(WAVES * kWave) void expand_kernel(ScanArgs a) {
     }
 }
 
-// One workgroup reads the per-tile counts in chunks: thread i of the chunk at
-// c0 owns tiles c0 + kRunTiles * i + j, j < kRunTiles, loaded as independent
-// buffer loads (zero past the last tile), all in flight before the first is
-// used.  A run of kRunTiles tiles holds at most 2^24 hits (tiles are at most
-// 2^20 coordinates), a wave's runs at most 2^30.
+// One workgroup reads the per-tile counts in chunks of kRunTiles rows of
+// kSumThreads tiles: thread i holds tiles c0 + j * kSumThreads + i, j <
+// kRunTiles, so every load and store of a wave covers consecutive words.
+// The loads are independent buffer loads (zero past the last tile), all in
+// flight before the first is used.  A tile holds at most 2^20 hits (tiles are
+// at most 2^20 coordinates), a wave's row at most 2^26, a chunk at most 2^34.
 constexpr int kSumThreads = 1024;
+constexpr int kSumWaves = kSumThreads / kWave;
 constexpr uint32_t kRunTiles = 16;
 constexpr uint32_t kChunkTiles = kSumThreads * kRunTiles;
 
-__device__ __forceinline__ uint32_t load_run(const uint32_t *tcnt, uint32_t tiles, uint32_t c0, int tid,
-                                             uint32_t (&v)[kRunTiles]) {
+__device__ __forceinline__ void load_rows(const uint32_t *tcnt, uint32_t tiles, uint32_t c0, int tid,
+                                          uint32_t (&v)[kRunTiles]) {
     const uint32_t left = tiles - c0;
     const __amdgpu_buffer_rsrc_t r = make_rsrc(reinterpret_cast<const uint8_t *>(tcnt + c0),
                                                (left < kChunkTiles ? left : kChunkTiles) * 4u);
 #pragma unroll
     for (uint32_t j = 0; j < kRunTiles; ++j)
-        v[j] = __builtin_amdgcn_raw_buffer_load_b32(r, (int)(((uint32_t)tid * kRunTiles + j) * 4u), 0, 0);
-    uint32_t run = 0;
-#pragma unroll
-    for (uint32_t j = 0; j < kRunTiles; ++j) run += v[j];
-    return run;
+        v[j] = __builtin_amdgcn_raw_buffer_load_b32(r, (int)((j * kSumThreads + (uint32_t)tid) * 4u), 0, 0);
 }
 
 // Sum of the per-tile counts into *out (one workgroup).
 __global__ __launch_bounds__(kSumThreads) void sum_tiles_kernel(const uint32_t *tcnt, uint32_t tiles,
                                                                  uint64_t *out) {
-    __shared__ uint32_t s_wave[kSumThreads / kWave];
+    __shared__ uint64_t s_wave[kSumWaves];
     const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
-    uint64_t total = 0;
+    uint64_t v = 0;
 #pragma unroll 1
     for (uint32_t c0 = 0; c0 < tiles; c0 += kChunkTiles) {
-        uint32_t v[kRunTiles];
-        const uint32_t w = wave_sum32(load_run(tcnt, tiles, c0, tid, v));
-        if (lane == 0) s_wave[wave] = w;
-        __syncthreads();
+        uint32_t r[kRunTiles];
+        load_rows(tcnt, tiles, c0, tid, r);
 #pragma unroll
-        for (int i = 0; i < kSumThreads / kWave; ++i) total += s_wave[i];
-        __syncthreads();
+        for (uint32_t j = 0; j < kRunTiles; ++j) v += r[j];
     }
-    if (tid == 0) *out = total;
+    v = wave_sum64(v);
+    if (lane == 0) s_wave[wave] = v;
+    __syncthreads();
+    if (tid == 0) {
+        uint64_t total = 0;
+#pragma unroll
+        for (int i = 0; i < kSumWaves; ++i) total += s_wave[i];
+        *out = total;
+    }
 }
 
 // Exclusive scan of the per-tile counts, toff[i] = sum of tcnt[0 .. i) for
-// i <= tiles, and *total = toff[tiles] (one workgroup): per chunk, a wave scan
-// of the runs, the wave totals across the workgroup, then each thread writes
-// the offsets of its run.
+// i <= tiles, and *total = toff[tiles] (one workgroup).  Per chunk: a wave
+// scan of each row; the (row, wave) totals in row-major order are scanned by
+// the first kRunTiles * kSumWaves / kWave waves; each thread then adds its
+// (row, wave) prefix to its in-wave prefix and stores the offsets.
 __global__ __launch_bounds__(kSumThreads) void tile_offsets_kernel(const uint32_t *tcnt, uint32_t tiles,
                                                                    uint64_t *toff, uint64_t *total) {
-    __shared__ uint32_t s_wave[kSumThreads / kWave];
+    constexpr int kCells = kRunTiles * kSumWaves;  // (row, wave) totals per chunk
+    constexpr int kCellWaves = kCells / kWave;
+    static_assert(kCells % kWave == 0 && kCells <= kSumThreads, "one cell per thread");
+    __shared__ uint32_t s_cell[kCells];
+    __shared__ uint64_t s_pre[kCells];
+    __shared__ uint64_t s_part[kCellWaves];
     const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
     uint64_t carry = 0;
 #pragma unroll 1
     for (uint32_t c0 = 0; c0 < tiles; c0 += kChunkTiles) {
-        uint32_t v[kRunTiles];
-        const uint32_t run = load_run(tcnt, tiles, c0, tid, v);
-        const uint32_t incl = wave_incl_scan32(run);
-        if (lane == kWave - 1) s_wave[wave] = incl;
-        __syncthreads();
-        uint64_t at = carry + (incl - run), chunk = 0;
+        uint32_t v[kRunTiles], incl[kRunTiles];
+        load_rows(tcnt, tiles, c0, tid, v);
 #pragma unroll
-        for (int i = 0; i < kSumThreads / kWave; ++i) {
-            at += i < wave ? s_wave[i] : 0u;
-            chunk += s_wave[i];
+        for (uint32_t j = 0; j < kRunTiles; ++j) incl[j] = wave_incl_scan32(v[j]);
+        if (lane == kWave - 1) {
+#pragma unroll
+            for (uint32_t j = 0; j < kRunTiles; ++j) s_cell[j * kSumWaves + wave] = incl[j];
         }
-        const uint64_t i0 = (uint64_t)c0 + (uint32_t)tid * kRunTiles;
+        __syncthreads();
+        uint64_t x = 0, xi = 0;
+        if (tid < kCells) {
+            x = s_cell[tid];
+            xi = x;  // inclusive scan of the cells in this wave
+#pragma unroll
+            for (int d = 1; d < kWave; d <<= 1) {
+                const uint64_t t = __shfl_up(xi, d, kWave);
+                if (lane >= d) xi += t;
+            }
+            if (lane == kWave - 1) s_part[wave] = xi;
+        }
+        __syncthreads();
+        uint64_t chunk = 0;
+#pragma unroll
+        for (int i = 0; i < kCellWaves; ++i) chunk += s_part[i];
+        if (tid < kCells) {
+            uint64_t before = xi - x;
+            for (int i = 0; i < wave; ++i) before += s_part[i];
+            s_pre[tid] = before;
+        }
+        __syncthreads();
 #pragma unroll
         for (uint32_t j = 0; j < kRunTiles; ++j) {
-            if (i0 + j < tiles) toff[i0 + j] = at;
-            at += v[j];
+            const uint64_t i = (uint64_t)c0 + j * kSumThreads + (uint32_t)tid;
+            if (i < tiles) toff[i] = carry + s_pre[j * kSumWaves + wave] + (incl[j] - v[j]);
         }
         carry += chunk;
         __syncthreads();
