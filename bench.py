@@ -32,6 +32,7 @@ events on the launch stream, against the 8 TB/s HBM peak.
 from __future__ import annotations
 
 import argparse
+import gc
 import json
 import os
 import sys
@@ -467,6 +468,11 @@ def main():
 
     torch.cuda.set_device(0)
     tuning = apply_tuning(args.tuning, epsm)
+    # A collection pause while searches are queued can drain the queue and
+    # leave the GPU idle between the two events of one search; reference
+    # counting still frees everything the steps create.
+    gc.collect()
+    gc.disable()
     if args.workload == "serve":
         points, stats, config = run_serve_workload(args, torch, W, epsm)
         top = points[-1]  # 0.8 x saturation

@@ -254,7 +254,8 @@ uint32_t epsm_tile_configs(uint32_t *waves, uint32_t *pieces, uint32_t capacity)
  * over the counts of the tiles before it and writes its own positions; a tile
  * may wait for its predecessors.  TWO_PHASE: each tile parks its hits in a
  * slot of the workspace (a list of offsets, or its hit masks when the list
- * would be longer) without waiting, and a second kernel writes the positions;
+ * would be longer) without waiting; a one-workgroup scan of the tile counts
+ * then gives each tile its offset, and an expand kernel writes the positions;
  * fastest for sparse output.  AUTO: two-phase for texts of at least 32 tiles
  * with out_capacity <= n / 32 (the capacity bounds the positions written),
  * else single pass. */

@@ -215,7 +215,7 @@ hipError_t launch_sum_tiles(const uint32_t *tcnt, uint32_t tiles, uint64_t *out,
 hipError_t launch_tile_offsets(const uint32_t *tcnt, uint32_t tiles, uint64_t *toff, uint64_t *total,
                             hipStream_t s);
 hipError_t launch_scan(const ScanArgs &a, TileConfig cfg, int grid, hipStream_t s);
-// Second phase of a two-phase search: slots -> positions, and *n_hits.
+// Third step of a two-phase search (after tile_offsets_kernel): slots -> positions.
 hipError_t launch_expand(ScanArgs a, TileConfig cfg, hipStream_t s);
 int scan_blocks_per_cu(TileConfig cfg, const DevPlan &p);
 bool tile_config_supported(TileConfig cfg);

@@ -216,14 +216,13 @@ void scan_kernel(ScanArgs a) {
 }
 
 // Second phase of a two-phase search.  Workgroup b expands tiles [b * E,
-// +E), E = a.expand_tiles <= kExpandTiles: the output offset of its first
-// tile is the sum of the group sums before it plus the wave counts of the
-// earlier tiles of its group; then each tile's slot becomes positions, a
-// list by a plain copy, masks through the same staged expansion as the scan.  All
-// counts are loaded up front and the masks of the next dense tile are
-// loaded while the current one is expanded, so the chain of dependent
-// memory round trips per workgroup stays short.  The workgroup of the last
-// tile writes the total count.
+// +E), E = a.expand_tiles <= kExpandTiles, from the output offset of its
+// first tile (tile_offsets_kernel) and the tiles' wave counts; a run of tiles
+// without hits returns at once.  Each tile's slot becomes positions, a list
+// by a plain copy, masks through the same staged expansion as the scan.  All
+// counts are loaded up front and the masks of the next dense tile are loaded
+// while the current one is expanded, so the chain of dependent memory round
+// trips per workgroup stays short.
 template <int WAVES, int PIECES>
 __global__ __launch_bounds__(WAVES * kWave) void expand_kernel(ScanArgs a) {
     constexpr int kThreads = WAVES * kWave;
