@@ -418,6 +418,14 @@ def cpu_baseline(torch, texts, cases, seconds: float, threads: int):
         used.append(len(c.pattern))
         if elapsed >= seconds:
             break
+    # one thread on the first count-mode search, for the per-core rate
+    first = next(c for c in cases if c.mode == "count")
+    t = texts[first.text_idx].cpu().numpy()
+    t0 = time.perf_counter()
+    got = oracle.count_mt(t, first.pattern, 1)
+    one_s = time.perf_counter() - t0
+    if got != first.count:
+        raise AssertionError(f"oracle count {got} != GPU count {first.count} (one thread)")
     host_cache.clear()
     return {
         "value": round(done_bytes / elapsed / 1e9, 3),
@@ -427,7 +435,22 @@ def cpu_baseline(torch, texts, cases, seconds: float, threads: int):
         "sample": f"count mode (oracle_count_mt, {threads} threads) over the first {len(used)} "
                   f"count-mode searches of the workload (m = {used}), {done_bytes / 2**30:.1f} GiB "
                   f"of text in {elapsed:.1f} s; counts equal the GPU's",
+        "single_thread_value": round(t.size / one_s / 1e9, 3),
+        "single_thread_sample": f"the first count-mode search (m = {len(first.pattern)}), "
+                                f"{t.size / 2**30:.2f} GiB in {one_s:.2f} s",
+        "cpu_model": cpu_model(),
     }
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def load_traffic(workload: str):

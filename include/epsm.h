@@ -76,6 +76,10 @@ typedef struct epsm_plan_s *epsm_plan_t;
 /* Never use the strided filter (see EPSM_VARIANT_STRIDE); long patterns then
  * use the per-block fingerprint filter.  Output is the same. */
 #define EPSM_PLAN_NO_STRIDE 0x20u
+/* Direct variant: filter on a 4-byte prefix even for m >= 8 (the default
+ * there compares the first 8 bytes as one 64-bit word, Section 3.2's packed
+ * compare at twice the width).  Output is the same. */
+#define EPSM_PLAN_PREFIX4 0x40u
 
 /* Variants */
 #define EPSM_VARIANT_DIRECT 1u
@@ -131,6 +135,8 @@ typedef struct {
     int32_t device;          /* HIP device of the device tables, -1 if host only */
     uint32_t kernel_class;   /* EPSM_CLASS_* of the plan's scan kernel */
     uint32_t stride;         /* EPSM_VARIANT_STRIDE: bytes between inspected blocks, else 0 */
+    uint32_t prefix_bytes;   /* EPSM_VARIANT_DIRECT: bytes of the prefix compare
+                                (min(m, 4), or 8 for m >= 8), else 0 */
 } epsm_plan_info;
 
 /* Copy the plan's description to *info (host memory). */

@@ -18,7 +18,7 @@ import torch
 from . import _lib
 from ._lib import (BATCH_COUNT_ONLY, CLASS_BYTES, CLASS_FINGERPRINT, CLASS_WORDS,  # noqa: F401
                    CLASS_DNA, MAX_M, N_CLASSES, PLAN_COLLIDE, PLAN_DNA, PLAN_FORCE_DIRECT,
-                   PLAN_FORCE_FINGERPRINT, PLAN_NO_STRIDE, VARIANT_DNA, VARIANT_STRIDE,
+                   PLAN_FORCE_FINGERPRINT, PLAN_NO_STRIDE, PLAN_PREFIX4, VARIANT_DNA, VARIANT_STRIDE,
                    PLAN_HASH_BITS, PLAN_HOST_ONLY, VARIANT_DIRECT, VARIANT_FINGERPRINT,
                    WRITE_AUTO, WRITE_SINGLE_PASS, WRITE_TWO_PHASE)
 
@@ -89,6 +89,7 @@ class Plan:
             "m": inf.m, "variant": inf.variant, "flags": inf.flags, "hash_bits": inf.hash_bits,
             "prefix_words": inf.prefix_words, "words": list(inf.words), "masks": list(inf.masks),
             "table": table, "device": inf.device, "kernel_class": inf.kernel_class, "stride": inf.stride,
+            "prefix_bytes": inf.prefix_bytes,
         }
 
     def close(self) -> None:

@@ -19,6 +19,7 @@ PLAN_FORCE_FINGERPRINT = 0x4
 PLAN_COLLIDE = 0x8
 PLAN_DNA = 0x10
 PLAN_NO_STRIDE = 0x20
+PLAN_PREFIX4 = 0x40
 
 
 def PLAN_HASH_BITS(k: int) -> int:
@@ -55,6 +56,7 @@ class PlanInfo(ctypes.Structure):
         ("device", ctypes.c_int32),
         ("kernel_class", ctypes.c_uint32),
         ("stride", ctypes.c_uint32),
+        ("prefix_bytes", ctypes.c_uint32),
     ]
 
 

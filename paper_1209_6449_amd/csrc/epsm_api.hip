@@ -34,7 +34,7 @@ epsm_status hip_fail(hipError_t e, const char *what) {
 constexpr uint32_t kKnownPlanFlags = EPSM_PLAN_HOST_ONLY | EPSM_PLAN_FORCE_DIRECT |
                                      EPSM_PLAN_FORCE_FINGERPRINT | EPSM_PLAN_COLLIDE |
                                      EPSM_PLAN_HASH_BITS(0xF) | EPSM_PLAN_DNA |
-                                     EPSM_PLAN_NO_STRIDE;
+                                     EPSM_PLAN_NO_STRIDE | EPSM_PLAN_PREFIX4;
 constexpr uint32_t kDefaultHashBits = 11;  // k = 11 in Section 3.4
 
 // Default tile: 8 waves x 16 KiB per wave = 128 KiB per workgroup tile.
@@ -602,7 +602,10 @@ epsm_status epsm_plan(const uint8_t *pattern, uint64_t m, uint32_t flags, epsm_p
     const uint32_t nwmax = 4 * d.nl - 4;
     const uint64_t words = (m + 3) / 4;
     d.nw = (uint32_t)std::min<uint64_t>(words, nwmax);
+    // prefix width of the direct filter: one 64-bit compare of bytes 0..7
+    // for m >= 8 (a register run of two loads holds every window it needs)
     d.pk = (uint32_t)std::min<uint64_t>(m, 4);
+    if (!fingerprint && d.nl == 2 && m >= 8 && !(flags & EPSM_PLAN_PREFIX4)) d.pk = 8;
     d.collide = (flags & EPSM_PLAN_COLLIDE) ? 1 : 0;
     d.hash_bits = fingerprint ? k : 0;
     if (dna) {
@@ -723,6 +726,7 @@ epsm_status epsm_plan_get_info(epsm_plan_t plan, epsm_plan_info *info) {
     info->device = plan->device;
     info->kernel_class = kernel_class(d);
     info->stride = d.stride;
+    info->prefix_bytes = d.variant == EPSM_VARIANT_DIRECT ? d.pk : 0;
     return EPSM_OK;
 }
 

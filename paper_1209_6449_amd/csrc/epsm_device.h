@@ -32,18 +32,44 @@ __device__ __forceinline__ uint32_t window(const uint32_t (&w)[N], int k) {
 __device__ __forceinline__ uint64_t ballot(bool c) { return __builtin_amdgcn_ballot_w64(c); }
 __device__ __forceinline__ bool wave_any(bool c) { return ballot(c) != 0; }
 
+// Window of 8 text bytes starting at byte k of the lane's register run.
+template <int N>
+__device__ __forceinline__ uint64_t window64(const uint32_t (&w)[N], int k) {
+    return ((uint64_t)window(w, k + 4) << 32) | window(w, k);
+}
+
+// Pattern words j, j+1 and their byte masks as 64-bit values.
+__device__ __forceinline__ uint64_t pattern64(const DevPlan &p, int j) {
+    return ((uint64_t)p.pw[j + 1] << 32) | p.pw[j];
+}
+__device__ __forceinline__ uint64_t mask64(const DevPlan &p, int j) {
+    return ((uint64_t)p.pmask[j + 1] << 32) | p.pmask[j];
+}
+
 // Narrow a wave mask of candidates at lane byte k with pattern words
-// j0..nw-1 (each compare is one v_cmp whose result is the wave mask itself).
-// Stops as soon as no lane of the wave has a candidate left.  nw is the
-// template constant NW, or the plan's runtime value when NW == 0.
-template <int NWMAX, int NW, int N>
-__device__ __forceinline__ uint64_t verify_words(const uint32_t (&w)[N], int k, uint64_t b, int j0,
+// J0..nw-1, two words per compare: one 64-bit v_cmp whose result is the wave
+// mask itself, so a pair costs one scalar AND.  Skips the rest as soon as no
+// lane of the wave has a candidate left.  nw is the template constant NW, or
+// the plan's runtime value when NW == 0.  Every register index is a
+// compile-time constant (a runtime one would move the run to scratch).
+template <int NWMAX, int NW, int J0, int N>
+__device__ __forceinline__ uint64_t verify_words(const uint32_t (&w)[N], int k, uint64_t b,
                                                  const DevPlan &p) {
+    const int nw = NW > 0 ? NW : (int)p.nw;
 #pragma unroll
-    for (int j = 0; j < NWMAX; ++j) {
-        const bool in_range = NW > 0 ? (j < NW) : (j < (int)p.nw);
-        if (j >= j0 && in_range && b != 0)
-            b &= ballot((window(w, k + 4 * j) & p.pmask[j]) == p.pw[j]);
+    for (int j = J0; j < NWMAX; j += 2) {
+        if (j < nw && b != 0) {
+            if (j + 1 < nw) {
+                // XOR-ed halves, not the raw words: two adjacent words of the
+                // run joined into one 64-bit value become one 64-bit access
+                // to the run, which then no longer fits in registers
+                const uint32_t d0 = (window(w, k + 4 * j) ^ p.pw[j]) & p.pmask[j];
+                const uint32_t d1 = (window(w, k + 4 * j + 4) ^ p.pw[j + 1]) & p.pmask[j + 1];
+                b &= ballot((((uint64_t)d1 << 32) | d0) == 0);
+            } else {
+                b &= ballot((window(w, k + 4 * j) & p.pmask[j]) == p.pw[j]);
+            }
+        }
     }
     return b;
 }
@@ -95,6 +121,8 @@ __device__ __forceinline__ uint32_t direct_mask(const uint32_t (&w)[NL * 4 + 1],
             c = ((w[q] >> (8 * r)) & 0xFFu) == p.pw[0];
         } else if constexpr (PK == 2) {
             c = (window(w, k) & 0xFFFFu) == p.pw[0];
+        } else if constexpr (PK == 8) {
+            c = window64(w, k) == pattern64(p, 0);  // m >= 8: no mask
         } else if constexpr (PK == 3) {
             // bytes k..k+2 of the run and a zero top byte in one v_perm
             const uint32_t sel = (uint32_t)r | ((uint32_t)(r + 1) << 8) |
@@ -107,11 +135,12 @@ __device__ __forceinline__ uint32_t direct_mask(const uint32_t (&w)[NL * 4 + 1],
         any |= b[k];
     }
     if (any == 0) return 0u;
-    if constexpr (PK >= 4 && (NW == 0 || NW > 1)) {
+    constexpr int J0 = PK == 8 ? 2 : 1;  // words the prefix compare covers
+    if constexpr (PK >= 4 && (NW == 0 || NW > J0)) {
         any = 0;
 #pragma unroll
         for (int k = 0; k < 16; ++k) {
-            if (b[k]) b[k] = verify_words<NWMAX, NW>(w, k, b[k], 1, p);
+            if (b[k]) b[k] = verify_words<NWMAX, NW, J0>(w, k, b[k], p);
             any |= b[k];
         }
         if (any == 0) return 0u;
@@ -142,7 +171,9 @@ __device__ __forceinline__ uint32_t fingerprint_mask(const uint32_t (&w)[NL * 4 
 #pragma unroll
     for (int k = 0; k < 16; ++k) {
         uint64_t bk = ballot((cm >> k) & 1u);
-        if (bk) bk = verify_words<NWMAX, 0>(w, k, bk, 0, p);
+        // a fingerprint plan has m >= 15, so a two-load run (NL = 2) holds
+        // exactly its first four words
+        if (bk) bk = verify_words<NWMAX, NL == 2 ? 4 : 0, 0>(w, k, bk, p);
         b[k] = bk;
         any |= bk;
     }

@@ -140,6 +140,24 @@ def test_forced_variants_agree(epsm, m):
     check(epsm, text, p, epsm.PLAN_FORCE_FINGERPRINT | epsm.PLAN_COLLIDE, label="collide")
 
 
+@pytest.mark.parametrize("m", [8, 9, 11, 12, 13, 15])
+@pytest.mark.parametrize("sigma", [1, 2, 4, 256])
+def test_prefix_widths_agree(epsm, m, sigma):
+    """The direct filter's 8-byte prefix (default for m >= 8) and its 4-byte
+    prefix (EPSM_PLAN_PREFIX4) both equal the oracle: dense candidates on
+    small alphabets, tiles with a ragged tail, patterns cut at the ends."""
+    rng = np.random.default_rng(1000 * sigma + m)
+    n = 2 * TILE + 1001
+    text = rng.integers(0, sigma, n).astype(np.uint8)
+    assert epsm.Plan(b"x" * m, epsm.PLAN_HOST_ONLY).info()["variant"] == epsm.VARIANT_DIRECT
+    for o in (0, n - m, int(rng.integers(0, n - m + 1))):
+        p = text[o:o + m].tobytes()
+        check(epsm, text, p, label=f"prefix8 sigma {sigma}")
+        check(epsm, text, p, epsm.PLAN_PREFIX4, label=f"prefix4 sigma {sigma}")
+    p = rng.integers(0, max(sigma, 2), m).astype(np.uint8).tobytes()
+    check(epsm, text, p, label=f"prefix8 random sigma {sigma}")
+
+
 @pytest.mark.parametrize("bits", [8, 9, 12, 14])
 def test_hash_width_does_not_change_output(epsm, bits):
     rng = np.random.default_rng(bits)

@@ -23,7 +23,7 @@ rng = np.random.default_rng(7)
 for m in list(range(1, 40)) + [64, 100, 262, 263, 300, 519, 1031, 2055, 4096]:
     for sigma in (1, 2, 4, 256):
         p = rng.integers(0, sigma, m).astype(np.uint8).tobytes()
-        for flags in (0, epsm.PLAN_NO_STRIDE, epsm.PLAN_FORCE_DIRECT, epsm.PLAN_HASH_BITS(14)):
+        for flags in (0, epsm.PLAN_NO_STRIDE, epsm.PLAN_FORCE_DIRECT, epsm.PLAN_HASH_BITS(14), epsm.PLAN_PREFIX4):
             info = epsm.Plan(p, flags | H).info()
             assert info["m"] == m
         if m >= 15:
