@@ -82,11 +82,10 @@ struct ScanArgs {
 constexpr uint32_t kWriteNone = 0;
 constexpr uint32_t kWriteLookBack = 1;
 constexpr uint32_t kWriteTwoPhase = 2;
-// The most tiles per expand workgroup of the two-phase write.
-constexpr uint32_t kExpandTiles = 8;
-// Output capacity per tile up to which expand workgroups take kExpandTiles
-// tiles (above it, one tile each).
-constexpr uint64_t kExpandFewPerTile = 64;
+// The most tiles per expand workgroup of the two-phase write, and the
+// workgroups the expand grid is sized to (about one resident round).
+constexpr uint32_t kExpandTiles = 32;
+constexpr uint32_t kExpandRound = 768;
 
 // ---- strided fingerprint filter (long patterns) ----------------------------
 constexpr int kStrideWaves = 8;

@@ -215,14 +215,14 @@ void scan_kernel(ScanArgs a) {
     write_tile<kPieces, kThreads>(s_mask, s_stage[wave], a, obase, wave_pos0, tid, lane);
 }
 
-// Second phase of a two-phase search.  Workgroup b expands tiles [b * E,
-// +E), E = a.expand_tiles <= kExpandTiles, from the output offset of its
-// first tile (tile_offsets_kernel) and the tiles' wave counts; a run of tiles
-// without hits returns at once.  Each tile's slot becomes positions, a list
-// by a plain copy, masks through the same staged expansion as the scan.  All
-// counts are loaded up front and the masks of the next dense tile are loaded
-// while the current one is expanded, so the chain of dependent memory round
-// trips per workgroup stays short.
+// Last step of a two-phase search.  Workgroup b expands tiles [b * E, +E),
+// E = a.expand_tiles <= kExpandTiles, from the output offset of its first
+// tile (tile_offsets_kernel) and the tiles' counts, all loaded in one round
+// trip; a run of tiles without hits returns at once.  The offset lists of its
+// list tiles are copied as one flattened array, so every entry's load is in
+// flight at once rather than one tile's list per memory round trip.  Mask
+// tiles go through the same staged expansion as the scan, one after another,
+// the next one's masks loaded while the current one is expanded.
 template <int WAVES, int PIECES>
 __global__ __launch_bounds__(WAVES * kWave) void expand_kernel(ScanArgs a) {
     constexpr int kThreads = WAVES * kWave;
@@ -230,28 +230,66 @@ __global__ __launch_bounds__(WAVES * kWave) void expand_kernel(ScanArgs a) {
     constexpr uint32_t kTile = WAVES * kWaveSpan;
     constexpr uint32_t kSlotWords = kTile / 32;
     constexpr int kPairs = PIECES / 2;  // mask words per lane and tile
-    static_assert(kExpandTiles * WAVES <= kThreads, "one wave count per thread");
+    static_assert(kExpandTiles * WAVES <= kThreads && kExpandTiles <= kWave, "counts per thread");
     __shared__ uint32_t s_stage[WAVES][kStage];
     __shared__ uint32_t s_mk[WAVES][kPairs][kWave];
     __shared__ uint32_t s_wc[kExpandTiles][WAVES];
     __shared__ uint32_t s_tot[kExpandTiles];
+    __shared__ uint32_t s_rend[kExpandTiles], s_lend[kExpandTiles];  // inclusive ends
+    __shared__ uint32_t s_dense;
     const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
     const uint32_t first = blockIdx.x * a.expand_tiles;  // num_tiles < 2^31
     const uint32_t cnt = min(first + a.expand_tiles, a.num_tiles) - first;
-    uint64_t pos = a.toff[first];
-    if (a.toff[first + cnt] == pos) return;  // no hits in these tiles
-
-    // the wave counts and totals of this workgroup's tiles; the output offset
-    // of its first tile comes from the tile offsets
-    if (tid < kExpandTiles * WAVES)
-        (&s_wc[0][0])[tid] = (uint32_t)tid < cnt * WAVES ? a.wcnt[(uint64_t)first * WAVES + tid] : 0;
-    if (tid < kExpandTiles) {
-        uint32_t t = 0;
-        if ((uint32_t)tid < cnt)
-            for (int w = 0; w < WAVES; ++w) t += a.wcnt[((uint64_t)first + tid) * WAVES + w];
-        s_tot[tid] = t;
+    const uint64_t pos0 = a.toff[first];
+    const uint64_t pos_end = a.toff[first + cnt];
+    const uint32_t wc = (uint32_t)tid < cnt * WAVES ? a.wcnt[(uint64_t)first * WAVES + tid] : 0u;
+    const uint32_t tc = (uint32_t)tid < cnt ? a.tcnt[first + tid] : 0u;
+    if (pos_end == pos0) return;  // no hits in these tiles
+    if (tid < kExpandTiles * WAVES) (&s_wc[0][0])[tid] = wc;
+    if (wave == 0) {
+        // per tile: end of its positions (relative to pos0) and of its list
+        // in the flattened array (mask tiles add no list entries)
+        const bool list = tc <= kSlotWords;
+        const uint32_t rend = wave_incl_scan32(tc);
+        const uint32_t lend = wave_incl_scan32(list ? tc : 0u);
+        const uint64_t dense = ballot(!list);
+        if (lane < (int)kExpandTiles) {
+            s_tot[lane] = tc;
+            s_rend[lane] = rend;
+            s_lend[lane] = lend;
+        }
+        if (lane == 0) s_dense = dense != 0;
     }
     __syncthreads();
+    const uint32_t l = s_lend[kExpandTiles - 1];  // list entries in all
+
+    // list tiles: entry e of the flattened array lies in the first tile whose
+    // list ends past e; a thread's entries ascend, so its tile index does too
+    uint32_t ti = 0;
+#pragma unroll 1
+    for (uint32_t e0 = 0; e0 < l; e0 += 8 * kThreads) {
+        uint32_t v[8];
+        uint64_t at[8];
+        int64_t base[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const uint32_t e = e0 + u * kThreads + tid;
+            if (e < l)
+                while (s_lend[ti] <= e) ++ti;  // ends at the last list tile
+            const uint32_t lb = ti ? s_lend[ti - 1] : 0u, rb = ti ? s_rend[ti - 1] : 0u;
+            const uint64_t t = (uint64_t)first + ti;
+            const uint32_t j = e - lb;
+            v[u] = e < l ? a.slots[t * kSlotWords + j] : 0u;
+            at[u] = pos0 + rb + j;
+            base[u] = (int64_t)(t * kTile) - (int64_t)a.delta;
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const uint32_t e = e0 + u * kThreads + tid;
+            if (e < l && at[u] < a.cap) a.out[at[u]] = base[u] + v[u];
+        }
+    }
+    if (!s_dense) return;
 
     auto next_dense = [&](uint32_t i) {
         while (i < cnt && s_tot[i] <= kSlotWords) ++i;
@@ -265,41 +303,21 @@ __global__ __launch_bounds__(WAVES * kWave) void expand_kernel(ScanArgs a) {
     uint32_t pre[kPairs];
     uint32_t nd = next_dense(0);
     if (nd < cnt) load_masks(nd, pre);
-
 #pragma unroll 1
-    for (uint32_t i = 0; i < cnt; ++i) {
-        const uint32_t tot = s_tot[i];
-        if (tot == 0) continue;
+    for (uint32_t i = nd; i < cnt; i = nd) {
+        // tile i is the dense tile whose masks are in pre
         const uint64_t t = (uint64_t)first + i;
         const int64_t tile_pos0 = (int64_t)(t * kTile) - (int64_t)a.delta;
-        if (tot <= kSlotWords) {
-            const uint32_t *slot = a.slots + t * kSlotWords;
-            for (uint32_t j0 = 0; j0 < tot; j0 += 8 * kThreads) {
-                uint32_t r[8];
+        const uint64_t pos = pos0 + (i ? s_rend[i - 1] : 0u);
 #pragma unroll
-                for (int u = 0; u < 8; ++u) {
-                    const uint32_t j = j0 + u * kThreads + tid;
-                    r[u] = j < tot ? slot[j] : 0;
-                }
-#pragma unroll
-                for (int u = 0; u < 8; ++u) {
-                    const uint32_t j = j0 + u * kThreads + tid;
-                    if (j < tot && pos + j < a.cap) a.out[pos + j] = tile_pos0 + r[u];
-                }
-            }
-        } else {
-            // tile i is the dense tile whose masks are in pre
-#pragma unroll
-            for (int p = 0; p < kPairs; ++p) s_mk[wave][p][lane] = pre[p];
-            nd = next_dense(i + 1);
-            if (nd < cnt) load_masks(nd, pre);
-            uint32_t before = 0;
-            for (int w = 0; w < wave; ++w) before += s_wc[i][w];
-            if (s_wc[i][wave])
-                write_tile<PIECES, kWave>(s_mk[wave], s_stage[wave], a, pos + before,
-                                          tile_pos0 + (int64_t)wave * kWaveSpan, lane, lane);
-        }
-        pos += tot;
+        for (int p = 0; p < kPairs; ++p) s_mk[wave][p][lane] = pre[p];
+        nd = next_dense(i + 1);
+        if (nd < cnt) load_masks(nd, pre);
+        uint32_t before = 0;
+        for (int w = 0; w < wave; ++w) before += s_wc[i][w];
+        if (s_wc[i][wave])
+            write_tile<PIECES, kWave>(s_mk[wave], s_stage[wave], a, pos + before,
+                                      tile_pos0 + (int64_t)wave * kWaveSpan, lane, lane);
     }
 }
 
@@ -553,10 +571,14 @@ static ExpandFn pick_expand(TileConfig cfg) {
 hipError_t launch_expand(ScanArgs a, TileConfig cfg, hipStream_t s) {
     ExpandFn fn = pick_expand(cfg);
     if (!fn) return hipErrorInvalidValue;
-    // A few positions per tile: 8 tiles per workgroup, fewer workgroups to
-    // launch.  More: one tile each, so that every list is copied by its own
-    // workgroup in parallel.
-    a.expand_tiles = a.cap <= (uint64_t)a.num_tiles * kExpandFewPerTile ? kExpandTiles : 1;
+    // Lists: 8 to kExpandTiles tiles per workgroup, copied together, enough
+    // that the grid fits in about one round of resident workgroups (three
+    // per CU).  Outputs dense enough that most tiles park masks: one tile
+    // each, so that different tiles' masks are expanded in parallel.
+    const uint64_t slot_words = (uint64_t)cfg.waves * cfg.pieces * kWavePiece / 32;
+    uint32_t e = (uint32_t)((a.num_tiles + kExpandRound - 1) / kExpandRound);
+    e = e < 8 ? 8 : (e > kExpandTiles ? kExpandTiles : e);
+    a.expand_tiles = a.cap <= (uint64_t)a.num_tiles * (slot_words / 2) ? e : 1;
     const uint32_t grid = (a.num_tiles + a.expand_tiles - 1) / a.expand_tiles;
     hipLaunchKernelGGL(fn, dim3(grid), dim3(cfg.waves * kWave), 0, s, a);
     return hipGetLastError();
