@@ -76,9 +76,9 @@ typedef struct epsm_plan_s *epsm_plan_t;
 /* Never use the strided filter (see EPSM_VARIANT_STRIDE); long patterns then
  * use the per-block fingerprint filter.  Output is the same. */
 #define EPSM_PLAN_NO_STRIDE 0x20u
-/* Direct variant: filter on a 4-byte prefix even for m >= 8 (the default
- * there compares the first 8 bytes as one 64-bit word, Section 3.2's packed
- * compare at twice the width).  Output is the same. */
+/* Direct variant: filter on a 4-byte prefix even for m >= 5 (the default
+ * there compares the first min(m, 8) bytes as one 64-bit word, Section 3.2's
+ * packed compare at twice the width).  Output is the same. */
 #define EPSM_PLAN_PREFIX4 0x40u
 
 /* Variants */
@@ -136,7 +136,8 @@ typedef struct {
     uint32_t kernel_class;   /* EPSM_CLASS_* of the plan's scan kernel */
     uint32_t stride;         /* EPSM_VARIANT_STRIDE: bytes between inspected blocks, else 0 */
     uint32_t prefix_bytes;   /* EPSM_VARIANT_DIRECT: bytes of the prefix compare
-                                (min(m, 4), or 8 for m >= 8), else 0 */
+                                (min(m, 8); 4 for m > 4 with EPSM_PLAN_PREFIX4
+                                or m > 16), else 0 */
 } epsm_plan_info;
 
 /* Copy the plan's description to *info (host memory). */
@@ -263,7 +264,7 @@ uint32_t epsm_tile_configs(uint32_t *waves, uint32_t *pieces, uint32_t capacity)
  * would be longer) without waiting; a one-workgroup scan of the tile counts
  * then gives each tile its offset, and an expand kernel writes the positions;
  * fastest for sparse output.  AUTO: two-phase for texts of at least 32 tiles
- * with out_capacity <= n / 32 (the capacity bounds the positions written),
+ * with out_capacity <= n / 128 (the capacity bounds the positions written),
  * else single pass. */
 #define EPSM_WRITE_AUTO 0u
 #define EPSM_WRITE_SINGLE_PASS 1u

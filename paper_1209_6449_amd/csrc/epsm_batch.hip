@@ -25,6 +25,9 @@ __device__ __forceinline__ uint32_t any_mask(const uint32_t (&w)[kBatchNL * 4 + 
         case 1: return direct_mask<kBatchNL, 1, 1>(w, p);
         case 2: return direct_mask<kBatchNL, 2, 1>(w, p);
         case 3: return direct_mask<kBatchNL, 3, 1>(w, p);
+        case 5:
+        case 6:
+        case 7: return direct_mask<kBatchNL, 7, 2>(w, p);
         case 8:
             switch (p.nw) {
                 case 2: return direct_mask<kBatchNL, 8, 2>(w, p);

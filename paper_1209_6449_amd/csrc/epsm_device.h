@@ -123,6 +123,9 @@ __device__ __forceinline__ uint32_t direct_mask(const uint32_t (&w)[NL * 4 + 1],
             c = (window(w, k) & 0xFFFFu) == p.pw[0];
         } else if constexpr (PK == 8) {
             c = window64(w, k) == pattern64(p, 0);  // m >= 8: no mask
+        } else if constexpr (PK == 7) {
+            // m = 5..7: bytes 0..7 with the high word masked to the pattern
+            c = ((((uint64_t)(window(w, k + 4) & p.pmask[1])) << 32) | window(w, k)) == pattern64(p, 0);
         } else if constexpr (PK == 3) {
             // bytes k..k+2 of the run and a zero top byte in one v_perm
             const uint32_t sel = (uint32_t)r | ((uint32_t)(r + 1) << 8) |
@@ -135,7 +138,7 @@ __device__ __forceinline__ uint32_t direct_mask(const uint32_t (&w)[NL * 4 + 1],
         any |= b[k];
     }
     if (any == 0) return 0u;
-    constexpr int J0 = PK == 8 ? 2 : 1;  // words the prefix compare covers
+    constexpr int J0 = PK >= 7 ? 2 : 1;  // words the prefix compare covers
     if constexpr (PK >= 4 && (NW == 0 || NW > J0)) {
         any = 0;
 #pragma unroll

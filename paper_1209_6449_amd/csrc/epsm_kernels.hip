@@ -497,6 +497,9 @@ static ScanFn pick(const DevPlan &p) {
         case 1: return scan_kernel<WAVES, 2, PIECES / 2, 2, 1, 1, 1>;
         case 2: return scan_kernel<WAVES, 2, PIECES / 2, 2, 1, 2, 1>;
         case 3: return scan_kernel<WAVES, 2, PIECES / 2, 2, 1, 3, 1>;
+        case 5:
+        case 6:
+        case 7: return scan_kernel<WAVES, 2, PIECES / 2, 2, 1, 7, 2>;
         case 8:
             switch (p.nw) {
                 case 2: return scan_kernel<WAVES, 2, PIECES / 2, 2, 1, 8, 2>;

@@ -90,13 +90,13 @@ def test_collide_mode_puts_every_offset_in_bucket_zero():
 
 
 @pytest.mark.parametrize("m,flags,width", [
-    (1, 0, 1), (3, 0, 3), (4, 0, 4), (7, 0, 4), (8, 0, 8), (15, 0, 8),
-    (8, epsm.PLAN_PREFIX4, 4), (15, epsm.PLAN_PREFIX4, 4), (16, 0, 0),
+    (1, 0, 1), (3, 0, 3), (4, 0, 4), (5, 0, 5), (7, 0, 7), (8, 0, 8), (15, 0, 8),
+    (5, epsm.PLAN_PREFIX4, 4), (8, epsm.PLAN_PREFIX4, 4), (15, epsm.PLAN_PREFIX4, 4), (16, 0, 0),
     (20, epsm.PLAN_FORCE_DIRECT, 4),
 ])
 def test_direct_prefix_width(m, flags, width):
-    """The direct filter compares min(m, 4) prefix bytes, or 8 (one 64-bit
-    word) for m >= 8 unless EPSM_PLAN_PREFIX4; a register run of three loads
+    """The direct filter compares min(m, 8) prefix bytes (one 64-bit word for
+    m >= 5) unless EPSM_PLAN_PREFIX4 (4); a register run of three loads
     (direct m > 16) keeps 4; other variants report 0."""
     assert host_plan(bytes((5 * i + 2) % 256 for i in range(m)), flags)["prefix_bytes"] == width
 

@@ -140,10 +140,10 @@ def test_forced_variants_agree(epsm, m):
     check(epsm, text, p, epsm.PLAN_FORCE_FINGERPRINT | epsm.PLAN_COLLIDE, label="collide")
 
 
-@pytest.mark.parametrize("m", [8, 9, 11, 12, 13, 15])
+@pytest.mark.parametrize("m", [5, 6, 7, 8, 9, 11, 12, 13, 15])
 @pytest.mark.parametrize("sigma", [1, 2, 4, 256])
 def test_prefix_widths_agree(epsm, m, sigma):
-    """The direct filter's 8-byte prefix (default for m >= 8) and its 4-byte
+    """The direct filter's 64-bit prefix (default for m >= 5) and its 4-byte
     prefix (EPSM_PLAN_PREFIX4) both equal the oracle: dense candidates on
     small alphabets, tiles with a ragged tail, patterns cut at the ends."""
     rng = np.random.default_rng(1000 * sigma + m)
