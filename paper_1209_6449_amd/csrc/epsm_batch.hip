@@ -17,7 +17,10 @@ namespace epsm {
 constexpr int kBatchNL = 3;  // 48 bytes per lane: any m <= 32 verified from registers
 constexpr uint32_t kPairChunk = 32;  // pair descriptors staged in LDS at a time
 
-// Mask of one lane piece for a runtime-described pattern.
+// Mask of one lane piece for a runtime-described pattern.  Plans with a
+// 64-bit prefix (pk 5..8) are filtered on their first word and verified: the
+// 64-bit variants in this kernel, which holds every variant at once, took
+// it from 105 to 153 VGPRs (three waves per SIMD instead of four).
 __device__ __forceinline__ uint32_t any_mask(const uint32_t (&w)[kBatchNL * 4 + 1], const DevPlan &p) {
     if (p.variant == 2) return fingerprint_mask<kBatchNL>(w, p, p.table);
     if (p.nl == 3) return direct_mask<kBatchNL, 4, 0>(w, p);
@@ -25,16 +28,7 @@ __device__ __forceinline__ uint32_t any_mask(const uint32_t (&w)[kBatchNL * 4 + 
         case 1: return direct_mask<kBatchNL, 1, 1>(w, p);
         case 2: return direct_mask<kBatchNL, 2, 1>(w, p);
         case 3: return direct_mask<kBatchNL, 3, 1>(w, p);
-        case 5:
-        case 6:
-        case 7: return direct_mask<kBatchNL, 7, 2>(w, p);
-        case 8:
-            switch (p.nw) {
-                case 2: return direct_mask<kBatchNL, 8, 2>(w, p);
-                case 3: return direct_mask<kBatchNL, 8, 3>(w, p);
-                default: return direct_mask<kBatchNL, 8, 4>(w, p);
-            }
-        default: break;
+        default: break;  // 64-bit prefixes (pk 5..8) take the 4-byte path here
     }
     switch (p.nw) {
         case 1: return direct_mask<kBatchNL, 4, 1>(w, p);
