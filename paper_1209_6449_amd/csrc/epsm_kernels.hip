@@ -114,7 +114,8 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t tile_rsrc(const ScanArgs &a, u
 // whose LDS admits fewer waves (4x32, 16x8, 16x16) do not reach the target;
 // their register use is left as it is.
 template <int WAVES, int U, int C, int NL, int VAR, int PK, int NW>
-__global__ __launch_bounds__(WAVES * kWave) __attribute__((amdgpu_waves_per_eu(NL <= 2 ? 6 : 4)))
+__global__ __launch_bounds__(WAVES * kWave)
+__attribute__((amdgpu_waves_per_eu(NL > 2 ? 4 : 6)))
 void scan_kernel(ScanArgs a) {
     constexpr int kThreads = WAVES * kWave;
     constexpr int kPieces = U * C;  // pieces per wave per tile
@@ -140,7 +141,7 @@ void scan_kernel(ScanArgs a) {
     const bool tail = a.plan.m > (VAR == 3 ? 16u : 4u) * a.plan.nw;
     auto load = [&](uint32_t (&w)[U][NL * 4 + 1], uint32_t off) {
         if constexpr (VAR == 3) load_chunk_dna<U>(w, rsrc, off >> kShift);
-        else load_chunk<U, NL>(w, rsrc, off);
+        else load_chunk<U, NL, kStreamRun<VAR, PK, NW>>(w, rsrc, off);
     };
 
     uint32_t wa[U][NL * 4 + 1], wb[U][NL * 4 + 1];
