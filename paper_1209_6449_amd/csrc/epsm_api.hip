@@ -632,6 +632,19 @@ epsm_status epsm_plan(const uint8_t *pattern, uint64_t m, uint32_t flags, epsm_p
             d.pw[j] = wv;
             d.pmask[j] = mv;
         }
+        if (m >= 16) {
+            // Section 3.4's filter over packed symbols: every occurrence holds
+            // an aligned 8-symbol block at pattern offset j in [0, 7]; bit j of
+            // entry v is set iff the block of symbols j..j+7 (16 bits, symbol t
+            // at bits 2t) hashes to v
+            d.hash_bits = kDnaHashBits;
+            p->table.assign((size_t)1 << kDnaHashBits, 0);
+            for (uint32_t j = 0; j < 8; ++j) {
+                uint32_t block = 0;
+                for (uint32_t t = 0; t < 8; ++t) block |= (uint32_t)pattern[j + t] << (2 * t);
+                p->table[fp_hash(block, 0, kDnaHashBits)] |= (uint16_t)(1u << j);
+            }
+        }
     }
     if (fingerprint) {
         // Section 3.4: L[v] = { j : h(p[j..j+7]) = v }, offsets j in [0, 7].

@@ -195,6 +195,36 @@ __device__ __forceinline__ uint32_t dna_window(const uint32_t (&w)[5], int j, in
 // (masked below m unless FULL, i.e. m >= 16) against each of the 16 windows,
 // then the next one or two pattern words where some lane of the wave still
 // has a candidate.
+// Packed DNA, m >= 16: the 8-symbol block filter (Section 3.4 over 2-bit
+// symbols).  An occurrence at start s holds the aligned block at the first
+// multiple of 8 at or after s, at pattern offset j = q - s in [0, 7].  The
+// lane's starts 0..15 are covered by its blocks at symbols 0, 8 and 16 (the
+// low and high halves of w[0], the low half of w[1]): bit j of the block at
+// 8i marks start 8i - j, kept when it lies in 0..15.  Each lane then checks
+// its own candidates against up to three pattern words, with the window
+// shift a per-lane register (every window lies within w[j], w[j + 1]).
+__device__ __forceinline__ uint32_t dna_block_mask(const uint32_t (&w)[5], const DevPlan &p,
+                                                   const uint16_t *tab) {
+    const uint32_t t0 = tab[fp_hash(w[0] & 0xFFFFu, 0, p.hash_bits)];
+    const uint32_t t1 = tab[fp_hash(w[0] >> 16, 0, p.hash_bits)];
+    const uint32_t t2 = tab[fp_hash(w[1] & 0xFFFFu, 0, p.hash_bits)];
+    // bit j -> start 8 - j (t1) or 16 - j (t2, j >= 1): reverse, then shift
+    uint32_t cand = (t0 & 1u) | ((__builtin_bitreverse32(t1) >> 23) & 0x1FEu) |
+                    ((__builtin_bitreverse32(t2) >> 15) & 0xFE00u);
+    uint32_t mk = 0;
+    while (cand) {
+        const uint32_t k = __builtin_ctz(cand);
+        cand &= cand - 1;
+        bool ok = true;
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+            if (j < (int)p.nw)
+                ok = ok && (__builtin_amdgcn_alignbit(w[j + 1], w[j], 2 * k) & p.pmask[j]) == p.pw[j];
+        mk |= ok ? 1u << k : 0u;
+    }
+    return mk;
+}
+
 template <bool FULL>
 __device__ __forceinline__ uint32_t dna_mask(const uint32_t (&w)[5], const DevPlan &p) {
     uint64_t b[16];
@@ -482,7 +512,8 @@ __device__ __forceinline__ uint32_t process_chunk(uint32_t (&w)[U][NL * 4 + 1], 
         uint32_t mk;
         if constexpr (VAR == 1) mk = direct_mask<NL, PK, NW>(w[u], a.plan);
         else if constexpr (VAR == 2) mk = fingerprint_mask<NL>(w[u], a.plan, tab);
-        else mk = dna_mask<PK == 16>(w[u], a.plan);
+        else if constexpr (PK == 16) mk = dna_block_mask(w[u], a.plan, tab);
+        else mk = dna_mask<false>(w[u], a.plan);
         const int piece = c * U + u;
         const uint64_t s0 = lane_start + (uint64_t)piece * kWavePiece;
         // only the first tile holds starts below delta and only the last

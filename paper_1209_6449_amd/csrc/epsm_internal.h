@@ -94,6 +94,9 @@ constexpr uint32_t kStrideBlocksPerLane = 4;
 constexpr uint64_t kStrideBlocksPerTile = (uint64_t)kStrideThreads * kStrideBlocksPerLane;
 constexpr uint32_t kStrideMin = 256, kStrideMax = 2048;  // S: powers of two, S <= m - 7
 constexpr uint32_t kStrideHashBits = 12;
+// Packed DNA, m >= 16: buckets of the 8-symbol block filter (2^k u16 entries
+// in LDS, as the byte fingerprint table).
+constexpr uint32_t kDnaHashBits = 11;
 
 struct StrideArgs {
     const uint8_t *base;      // 16-byte aligned address at or below the text start

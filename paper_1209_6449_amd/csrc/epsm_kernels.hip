@@ -146,7 +146,7 @@ void scan_kernel(ScanArgs a) {
 
     uint32_t wa[U][NL * 4 + 1], wb[U][NL * 4 + 1];
     load(wa, lane_off);
-    if constexpr (VAR == 2) {
+    if constexpr (VAR == 2 || (VAR == 3 && PK == 16)) {
         const uint32_t rows = (1u << a.plan.hash_bits) / 8;  // 16-byte rows of the table
         const u32x4 *src = reinterpret_cast<const u32x4 *>(a.plan.table);
         u32x4 *dst = reinterpret_cast<u32x4 *>(s_table);
@@ -547,7 +547,7 @@ bool tile_config_supported(TileConfig cfg) {
 }
 
 static size_t table_bytes(const DevPlan &p) {
-    return p.variant == 2 ? ((size_t)2 << p.hash_bits) : 0;
+    return (p.variant == 2 || (p.variant == 3 && p.pk == 16)) ? ((size_t)2 << p.hash_bits) : 0;
 }
 
 int scan_blocks_per_cu(TileConfig cfg, const DevPlan &p) {

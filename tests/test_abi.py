@@ -194,11 +194,23 @@ def test_dna_plan_packs_codes_two_bits_each(m):
     codes = rng.integers(0, 4, m).astype(np.uint8)
     info = host_plan(codes.tobytes(), epsm.PLAN_DNA)
     assert info["variant"] == epsm.VARIANT_DNA and info["kernel_class"] == epsm.CLASS_DNA
-    assert info["prefix_words"] == min((m + 15) // 16, 3) and info["table"] is None
+    assert info["prefix_words"] == min((m + 15) // 16, 3)
     for j in range(8):
         syms = codes[16 * j:16 * j + 16]
         assert info["words"][j] == sum(int(c) << (2 * t) for t, c in enumerate(syms))
         assert info["masks"][j] == sum(3 << (2 * t) for t in range(len(syms)))
+    if m < 16:
+        assert info["table"] is None and info["hash_bits"] == 0
+        return
+    # the 8-symbol block filter: bit j of the bucket of block j..j+7
+    k = info["hash_bits"]
+    assert k == 11 and len(info["table"]) == 1 << k
+    L = epsm.lib()
+    exp = [0] * (1 << k)
+    for j in range(8):
+        block = sum(int(codes[j + t]) << (2 * t) for t in range(8))
+        exp[L.epsm_fingerprint(block, 0, k, 0)] |= 1 << j
+    assert info["table"] == exp
 
 
 @pytest.mark.parametrize("pattern,flags", [
