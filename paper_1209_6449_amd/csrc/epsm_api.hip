@@ -263,6 +263,31 @@ epsm_status run_search(epsm_plan_t plan, const uint8_t *d_text, uint64_t n, int6
     a.cap = write ? cap : 0;
     a.n_hits = d_n_hits;
     a.plan = plan->dev;
+    if (dna && plan->dev.pk == 16) {
+        // packed, block filter: the wide-lane kernel; positions by a count
+        // pass (tile and wave counts), the tile offsets, and a write pass
+        // over the tiles with hits
+        const uint64_t tsym = dna_wide_tile_symbols();
+        const uint64_t wtiles = (a.last + 1 + tsym - 1) / tsym;
+        if (wtiles > 0x7FFFFFFFull) return fail(EPSM_EUNSUPPORTED, "text too long for the tile grid");
+        a.num_tiles = (uint32_t)wtiles;
+        a.write = write ? kWriteTwoPhase : kWriteNone;
+        const size_t cnt_bytes = (wtiles * sizeof(uint32_t) + 255) & ~size_t(255);
+        const size_t off_bytes = ((wtiles + 1) * sizeof(uint64_t) + 255) & ~size_t(255);
+        const size_t wave_bytes = wtiles * dna_wide_waves() * sizeof(uint32_t);
+        uint8_t *ws = nullptr;
+        st = workspace_for(stream, cnt_bytes + (write ? off_bytes + wave_bytes : 0), &ws);
+        if (st != EPSM_OK) return st;
+        a.tcnt = (uint32_t *)ws;
+        a.toff = (uint64_t *)(ws + cnt_bytes);
+        a.wcnt = (uint32_t *)(ws + cnt_bytes + off_bytes);
+        hipError_t e = launch_dna_wide(a, write ? 1 : 0, stream);
+        if (e == hipSuccess)
+            e = write ? launch_tile_offsets(a.tcnt, a.num_tiles, a.toff, d_n_hits, stream)
+                      : launch_sum_tiles(a.tcnt, a.num_tiles, d_n_hits, stream);
+        if (e == hipSuccess && write) e = launch_dna_wide(a, 2, stream);
+        return e == hipSuccess ? EPSM_OK : hip_fail(e, "launch(dna wide)");
+    }
     const SearchChoice ch = choice_for(plan->dev, !write, n);
     const TileConfig tile = ch.tile;
     const uint64_t tile_bytes = (uint64_t)tile.bytes();

@@ -212,6 +212,13 @@ hipError_t launch_set_u64(uint64_t *p, uint64_t value, hipStream_t s);
 hipError_t launch_pack_dna(const uint8_t *codes, uint64_t n, uint8_t *packed, hipStream_t s);
 // *out = sum of tcnt[0 .. tiles) (one workgroup).
 hipError_t launch_sum_tiles(const uint32_t *tcnt, uint32_t tiles, uint64_t *out, hipStream_t s);
+// Packed DNA, m >= 16, wide lanes (a.num_tiles tiles of
+// dna_wide_tile_symbols() symbols, dna_wide_waves() waves each).  mode 0:
+// count per tile into a.tcnt; 1: also per wave into a.wcnt; 2: write the
+// positions from a.toff (exclusive tile offsets) and a.wcnt.
+uint64_t dna_wide_tile_symbols();
+uint32_t dna_wide_waves();
+hipError_t launch_dna_wide(const ScanArgs &a, int mode, hipStream_t s);
 // toff[i] = sum of tcnt[0 .. i) for i <= tiles, and *total = toff[tiles]
 // (one workgroup).
 hipError_t launch_tile_offsets(const uint32_t *tcnt, uint32_t tiles, uint64_t *toff, uint64_t *total,

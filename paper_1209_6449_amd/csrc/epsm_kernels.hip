@@ -439,6 +439,166 @@ hipError_t launch_sum_tiles(const uint32_t *tcnt, uint32_t tiles, uint64_t *out,
     return hipGetLastError();
 }
 
+// Packed DNA, m >= 16: the block filter with wide lanes.  A piece is 4096
+// symbols (1 KiB); lane L owns starts [64 L, 64 L + 64), the 16 bytes it
+// loads (one non-temporal load, no overlap between lanes); the 64 symbols
+// after them are lane L + 1's (DPP wave_shl:1), lane 63's the next piece's
+// first bytes, one wave-uniform address.  The nine aligned 8-symbol blocks
+// at symbols 0, 8, ..., 64 of the run cover the lane's starts: bit j of the
+// block at 8i marks start 8i - j.  Candidates are checked per lane, the
+// run's words picked by selects (a runtime register index would move the
+// run to scratch).
+// Modes: kWideCount stores each tile's count; kWideCountWaves also each
+// wave's (for a later write); kWideWrite re-scans the tiles with hits and
+// writes their positions from the tile offsets and wave counts.  Within a
+// piece the starts are ordered by lane, then bit, so a lane's hits are
+// consecutive in the output and each lane writes its own run.
+constexpr int kWideWaves = 8;
+constexpr int kWidePieces = 8;                      // pieces per wave and tile
+constexpr uint32_t kWidePieceSym = 64 * kWave;      // 4096 symbols = 1 KiB
+constexpr uint64_t kWideTileSym = (uint64_t)kWideWaves * kWidePieces * kWidePieceSym;
+constexpr int kWideCount = 0, kWideCountWaves = 1, kWideWrite = 2;
+
+__device__ __forceinline__ uint32_t pick4(const uint32_t (&w)[9], uint32_t q, int j) {
+    // w[q + j] for q in 0..3 (j fixed), without a runtime register index
+    const uint32_t a = w[j], b = w[j + 1], c = w[j + 2], d = w[j + 3];
+    return q == 0 ? a : q == 1 ? b : q == 2 ? c : d;
+}
+
+template <int MODE>
+__global__ __launch_bounds__(kWideWaves * kWave) void dna_wide_kernel(ScanArgs a) {
+    extern __shared__ __attribute__((aligned(16))) uint16_t s_table[];
+    __shared__ uint32_t s_wave[kWideWaves];
+    const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
+    const uint32_t tile = blockIdx.x;
+    uint64_t pos = 0;  // write: output index of this wave's next piece
+    if constexpr (MODE == kWideWrite) {
+        pos = a.toff[tile];
+        if (a.toff[tile + 1] == pos) return;  // no hits in this tile
+        for (int i = 0; i < wave; ++i) pos += a.wcnt[(uint64_t)tile * kWideWaves + i];
+    }
+    const uint64_t tile_sym = (uint64_t)tile * kWideTileSym;
+    const __amdgpu_buffer_rsrc_t rsrc = tile_rsrc(a, tile_sym >> 2);
+    {
+        const uint32_t rows = (1u << a.plan.hash_bits) / 8;
+        const u32x4 *src = reinterpret_cast<const u32x4 *>(a.plan.table);
+        u32x4 *dst = reinterpret_cast<u32x4 *>(s_table);
+        for (uint32_t i = tid; i < rows; i += kWideWaves * kWave) dst[i] = src[i];
+    }
+    __syncthreads();
+    const uint32_t wave_byte = (uint32_t)wave * kWidePieces * (kWidePieceSym / 4);
+    const uint32_t lane_byte = wave_byte + (uint32_t)lane * 16;
+    const bool edge = tile == 0 || tile == a.num_tiles - 1;
+    const uint32_t nw = a.plan.nw;
+    auto load = [&](uint32_t (&w)[9], int p) {
+        const u32x4 v = __builtin_amdgcn_raw_buffer_load_b128(rsrc, (int)(lane_byte + p * 1024), 0, kStreamLoad);
+        const u32x4 h = __builtin_amdgcn_raw_buffer_load_b128(rsrc, (int)(wave_byte + (p + 1) * 1024), 0,
+                                                              kStreamLoad);
+        w[0] = v.x; w[1] = v.y; w[2] = v.z; w[3] = v.w;
+        w[4] = h.x; w[5] = h.y; w[6] = h.z; w[7] = h.w;
+        w[8] = 0;
+    };
+    // hits of the lane's 64 starts in piece p (base coordinate s0 = bit 0)
+    auto piece = [&](uint32_t (&w)[9], uint64_t s0) -> uint64_t {
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+            w[4 + j] = (uint32_t)__builtin_amdgcn_update_dpp((int)w[4 + j], (int)w[j], 0x130, 0xF, 0xF, false);
+        uint64_t cand = s_table[fp_hash(w[0] & 0xFFFFu, 0, a.plan.hash_bits)] & 1u;
+#pragma unroll
+        for (int i = 1; i <= 8; ++i) {
+            const uint32_t block = (w[i >> 1] >> (16 * (i & 1))) & 0xFFFFu;
+            const uint32_t t = s_table[fp_hash(block, 0, a.plan.hash_bits)];
+            cand |= (uint64_t)(__builtin_bitreverse32(t) >> 24) << (8 * i - 7);
+        }
+        if (edge) {
+            uint32_t lo = 0, hi = 64;
+            if (a.delta > s0) lo = a.delta - s0 > 64 ? 64u : (uint32_t)(a.delta - s0);
+            if (a.last < s0) hi = 0;
+            else if (a.last - s0 < 63) hi = (uint32_t)(a.last - s0) + 1;
+            const uint64_t below_hi = hi >= 64 ? ~0ull : ((1ull << hi) - 1);
+            const uint64_t below_lo = lo >= 64 ? ~0ull : ((1ull << lo) - 1);
+            cand &= below_hi & ~below_lo;
+        }
+        uint64_t hits = 0;
+        while (cand) {
+            const uint32_t k = (uint32_t)__builtin_ctzll(cand);
+            cand &= cand - 1;
+            const uint32_t q = k >> 4, sh = 2 * (k & 15);
+            bool ok = true;
+#pragma unroll
+            for (int j = 0; j < 3; ++j)
+                if (j < (int)nw) {
+                    const uint32_t x = __builtin_amdgcn_alignbit(pick4(w, q, j + 1), pick4(w, q, j), sh);
+                    ok = ok && (x & a.plan.pmask[j]) == a.plan.pw[j];
+                }
+            if (ok && a.plan.m > 48) {
+                const uint64_t s = s0 + k;
+                for (uint64_t j = 48; j < a.plan.m && ok; ++j) {
+                    const uint64_t c = s + j;
+                    ok = ((a.base[c >> 2] >> (2 * (c & 3))) & 3u) == a.plan.pattern[j];
+                }
+            }
+            hits |= ok ? 1ull << k : 0ull;
+        }
+        return hits;
+    };
+    const uint64_t wave_sym = tile_sym + (uint64_t)wave * kWidePieces * kWidePieceSym + (uint64_t)lane * 64;
+    uint32_t cnt = 0;
+    auto consume = [&](uint64_t hits, uint64_t s0) {
+        const uint32_t c = (uint32_t)__popcll(hits);
+        if constexpr (MODE != kWideWrite) {
+            cnt += c;
+        } else {
+            const uint32_t incl = wave_incl_scan32(c);
+            uint64_t at = pos + (incl - c);
+            pos += last_lane(incl);
+            const int64_t p0 = (int64_t)s0 - (int64_t)a.delta;
+            while (hits) {
+                const uint32_t k = (uint32_t)__builtin_ctzll(hits);
+                hits &= hits - 1;
+                if (at < a.cap) a.out[at] = p0 + k;
+                ++at;
+            }
+        }
+    };
+    uint32_t wa[9], wb[9];
+    load(wa, 0);
+#pragma unroll 1
+    for (int p = 0; p < kWidePieces; p += 2) {
+        load(wb, p + 1);
+        const uint64_t sa = wave_sym + (uint64_t)p * kWidePieceSym;
+        consume(piece(wa, sa), sa);
+        if (p + 2 < kWidePieces) load(wa, p + 2);
+        consume(piece(wb, sa + kWidePieceSym), sa + kWidePieceSym);
+    }
+    if constexpr (MODE != kWideWrite) {
+        const uint32_t wt = wave_sum32(cnt);
+        if constexpr (MODE == kWideCountWaves)
+            if (lane == 0) a.wcnt[(uint64_t)tile * kWideWaves + wave] = wt;
+        if (lane == 0) s_wave[wave] = wt;
+        __syncthreads();
+        if (tid == 0) {
+            uint32_t t = 0;
+#pragma unroll
+            for (int i = 0; i < kWideWaves; ++i) t += s_wave[i];
+            a.tcnt[tile] = t;
+        }
+    }
+}
+
+uint64_t dna_wide_tile_symbols() { return kWideTileSym; }
+uint32_t dna_wide_waves() { return kWideWaves; }
+
+hipError_t launch_dna_wide(const ScanArgs &a, int mode, hipStream_t s) {
+    if (a.num_tiles == 0) return hipSuccess;
+    const dim3 grid(a.num_tiles), block(kWideWaves * kWave);
+    const size_t lds = (size_t)2 << a.plan.hash_bits;
+    if (mode == kWideCount) hipLaunchKernelGGL(dna_wide_kernel<kWideCount>, grid, block, lds, s, a);
+    else if (mode == kWideCountWaves) hipLaunchKernelGGL(dna_wide_kernel<kWideCountWaves>, grid, block, lds, s, a);
+    else hipLaunchKernelGGL(dna_wide_kernel<kWideWrite>, grid, block, lds, s, a);
+    return hipGetLastError();
+}
+
 __global__ void zero_u64_kernel(uint64_t *p, uint64_t count) {
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += stride) p[i] = 0;
