@@ -125,7 +125,7 @@ typedef struct {
     uint32_t variant;        /* EPSM_VARIANT_* */
     uint32_t flags;          /* flags the plan was built with */
     uint32_t hash_bits;      /* k of the fingerprint variant, or of the block
-                                filter of DNA plans with m >= 16 (else 0) */
+                                filter of DNA plans with m >= 8 (else 0) */
     uint32_t prefix_words;   /* 32-bit pattern words compared in the filter */
     uint32_t words[8];       /* pattern bytes 4i..4i+3, little endian, 0 past m */
     uint32_t masks[8];       /* 0xFF in each byte lane that lies below m */
@@ -134,8 +134,10 @@ typedef struct {
                                 bucket v; for DNA plans with m >= 16, bit j of
                                 entry v is set iff the 8-symbol block j..j+7
                                 (symbol t at bits 2t) hashes to v
-                                (epsm_fingerprint(block, 0, k, 0)); NULL
-                                otherwise.  Owned by the plan. */
+                                (epsm_fingerprint(block, 0, k, 0)); with
+                                8 <= m < 16 (k = 8), iff the 4-symbol block
+                                j..j+3 equals v; NULL otherwise.  Owned by the
+                                plan. */
     int32_t device;          /* HIP device of the device tables, -1 if host only */
     uint32_t kernel_class;   /* EPSM_CLASS_* of the plan's scan kernel */
     uint32_t stride;         /* EPSM_VARIANT_STRIDE: bytes between inspected blocks, else 0 */

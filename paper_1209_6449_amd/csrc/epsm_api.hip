@@ -263,12 +263,14 @@ epsm_status run_search(epsm_plan_t plan, const uint8_t *d_text, uint64_t n, int6
     a.cap = write ? cap : 0;
     a.n_hits = d_n_hits;
     a.plan = plan->dev;
-    if (dna && plan->dev.pk == 16) {
+    const uint64_t wsym = dna_wide_tile_symbols();
+    const uint64_t wtiles = (a.last + 1 + wsym - 1) / wsym;
+    if (dna && (plan->dev.pk == 16 || plan->dev.pk == 8) && (!write || cap <= wtiles / 2)) {
         // packed, block filter: the wide-lane kernel; positions by a count
         // pass (tile and wave counts), the tile offsets, and a write pass
-        // over the tiles with hits
-        const uint64_t tsym = dna_wide_tile_symbols();
-        const uint64_t wtiles = (a.last + 1 + tsym - 1) / tsym;
+        // over the tiles with hits.  The write pass reads its tiles again,
+        // so it is used only when most tiles hold no position (capacity at
+        // most half the tiles); denser outputs take the scan below.
         if (wtiles > 0x7FFFFFFFull) return fail(EPSM_EUNSUPPORTED, "text too long for the tile grid");
         a.num_tiles = (uint32_t)wtiles;
         a.write = write ? kWriteTwoPhase : kWriteNone;
@@ -668,6 +670,18 @@ epsm_status epsm_plan(const uint8_t *pattern, uint64_t m, uint32_t flags, epsm_p
                 uint32_t block = 0;
                 for (uint32_t t = 0; t < 8; ++t) block |= (uint32_t)pattern[j + t] << (2 * t);
                 p->table[fp_hash(block, 0, kDnaHashBits)] |= (uint16_t)(1u << j);
+            }
+        } else if (m >= 8) {
+            // the same with 4-symbol blocks at offsets j in [0, 3] (every
+            // occurrence of m >= 7 holds one); an 8-bit block indexes the
+            // 256-entry table directly
+            d.pk = 8;
+            d.hash_bits = 8;
+            p->table.assign((size_t)1 << 8, 0);
+            for (uint32_t j = 0; j < 4; ++j) {
+                uint32_t block = 0;
+                for (uint32_t t = 0; t < 4; ++t) block |= (uint32_t)pattern[j + t] << (2 * t);
+                p->table[block] |= (uint16_t)(1u << j);
             }
         }
     }

@@ -465,8 +465,11 @@ __device__ __forceinline__ uint32_t pick4(const uint32_t (&w)[9], uint32_t q, in
     return q == 0 ? a : q == 1 ? b : q == 2 ? c : d;
 }
 
-template <int MODE>
+template <int MODE, int BLOCK>
 __global__ __launch_bounds__(kWideWaves * kWave) void dna_wide_kernel(ScanArgs a) {
+    static_assert(BLOCK == 4 || BLOCK == 8, "blocks of 4 (8-bit, direct index) or 8 symbols (hashed)");
+    constexpr int kBlocks = 64 / BLOCK;  // blocks at symbols BLOCK * i, i = 0..kBlocks
+    constexpr uint32_t kBlockMask = BLOCK == 8 ? 0xFFFFu : 0xFFu;
     extern __shared__ __attribute__((aligned(16))) uint16_t s_table[];
     __shared__ uint32_t s_wave[kWideWaves];
     const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
@@ -503,12 +506,16 @@ __global__ __launch_bounds__(kWideWaves * kWave) void dna_wide_kernel(ScanArgs a
 #pragma unroll
         for (int j = 0; j < 4; ++j)
             w[4 + j] = (uint32_t)__builtin_amdgcn_update_dpp((int)w[4 + j], (int)w[j], 0x130, 0xF, 0xF, false);
-        uint64_t cand = s_table[fp_hash(w[0] & 0xFFFFu, 0, a.plan.hash_bits)] & 1u;
+        auto entry = [&](uint32_t block) -> uint32_t {
+            return s_table[BLOCK == 8 ? fp_hash(block, 0, a.plan.hash_bits) : block];
+        };
+        uint64_t cand = entry(w[0] & kBlockMask) & 1u;
 #pragma unroll
-        for (int i = 1; i <= 8; ++i) {
-            const uint32_t block = (w[i >> 1] >> (16 * (i & 1))) & 0xFFFFu;
-            const uint32_t t = s_table[fp_hash(block, 0, a.plan.hash_bits)];
-            cand |= (uint64_t)(__builtin_bitreverse32(t) >> 24) << (8 * i - 7);
+        for (int i = 1; i <= kBlocks; ++i) {
+            constexpr int kPerWord = 16 / BLOCK;
+            const uint32_t block = (w[i / kPerWord] >> (2 * BLOCK * (i % kPerWord))) & kBlockMask;
+            // bit j -> start BLOCK * i - j: reverse the BLOCK low bits, then shift
+            cand |= (uint64_t)(__builtin_bitreverse32(entry(block)) >> (32 - BLOCK)) << (BLOCK * i - (BLOCK - 1));
         }
         if (edge) {
             uint32_t lo = 0, hi = 64;
@@ -589,13 +596,20 @@ __global__ __launch_bounds__(kWideWaves * kWave) void dna_wide_kernel(ScanArgs a
 uint64_t dna_wide_tile_symbols() { return kWideTileSym; }
 uint32_t dna_wide_waves() { return kWideWaves; }
 
-hipError_t launch_dna_wide(const ScanArgs &a, int mode, hipStream_t s) {
-    if (a.num_tiles == 0) return hipSuccess;
+template <int BLOCK>
+static void launch_dna_wide_block(const ScanArgs &a, int mode, hipStream_t s) {
     const dim3 grid(a.num_tiles), block(kWideWaves * kWave);
     const size_t lds = (size_t)2 << a.plan.hash_bits;
-    if (mode == kWideCount) hipLaunchKernelGGL(dna_wide_kernel<kWideCount>, grid, block, lds, s, a);
-    else if (mode == kWideCountWaves) hipLaunchKernelGGL(dna_wide_kernel<kWideCountWaves>, grid, block, lds, s, a);
-    else hipLaunchKernelGGL(dna_wide_kernel<kWideWrite>, grid, block, lds, s, a);
+    if (mode == kWideCount) hipLaunchKernelGGL((dna_wide_kernel<kWideCount, BLOCK>), grid, block, lds, s, a);
+    else if (mode == kWideCountWaves)
+        hipLaunchKernelGGL((dna_wide_kernel<kWideCountWaves, BLOCK>), grid, block, lds, s, a);
+    else hipLaunchKernelGGL((dna_wide_kernel<kWideWrite, BLOCK>), grid, block, lds, s, a);
+}
+
+hipError_t launch_dna_wide(const ScanArgs &a, int mode, hipStream_t s) {
+    if (a.num_tiles == 0) return hipSuccess;
+    if (a.plan.pk == 16) launch_dna_wide_block<8>(a, mode, s);
+    else launch_dna_wide_block<4>(a, mode, s);
     return hipGetLastError();
 }
 

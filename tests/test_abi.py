@@ -188,7 +188,7 @@ def test_kernel_class_of_plan(m, flags, cls):
     assert host_plan(bytes((3 * i + 1) % 256 for i in range(m)), flags)["kernel_class"] == cls
 
 
-@pytest.mark.parametrize("m", [1, 7, 16, 17, 33, 48, 49, 100])
+@pytest.mark.parametrize("m", [1, 7, 8, 12, 15, 16, 17, 33, 48, 49, 100])
 def test_dna_plan_packs_codes_two_bits_each(m):
     rng = np.random.default_rng(m)
     codes = rng.integers(0, 4, m).astype(np.uint8)
@@ -199,8 +199,16 @@ def test_dna_plan_packs_codes_two_bits_each(m):
         syms = codes[16 * j:16 * j + 16]
         assert info["words"][j] == sum(int(c) << (2 * t) for t, c in enumerate(syms))
         assert info["masks"][j] == sum(3 << (2 * t) for t in range(len(syms)))
-    if m < 16:
+    if m < 8:
         assert info["table"] is None and info["hash_bits"] == 0
+        return
+    if m < 16:
+        # 4-symbol blocks index the 256-entry table directly: bit j of block j..j+3
+        assert info["hash_bits"] == 8 and len(info["table"]) == 256
+        exp = [0] * 256
+        for j in range(4):
+            exp[sum(int(codes[j + t]) << (2 * t) for t in range(4))] |= 1 << j
+        assert info["table"] == exp
         return
     # the 8-symbol block filter: bit j of the bucket of block j..j+7
     k = info["hash_bits"]

@@ -68,7 +68,7 @@ def check(epsm, codes, pattern, offset=0, label=""):
     return exp.size
 
 
-MS = [1, 2, 5, 15, 16, 17, 31, 32, 33, 47, 48, 49, 64, 100]
+MS = [1, 2, 5, 7, 8, 11, 15, 16, 17, 31, 32, 33, 47, 48, 49, 64, 100]
 
 
 @pytest.mark.parametrize("m", MS)
@@ -132,3 +132,36 @@ def test_dna_plan_and_byte_search_do_not_mix(epsm):
         epsm.count_dna_into(epsm.Plan(b"\x01"), t, 64, hits)
     with pytest.raises(epsm.EpsmError):
         epsm.search_batch([t], [(0, epsm.Plan(b"\x01", epsm.PLAN_DNA))])
+
+
+@pytest.mark.parametrize("m", [8, 12, 15, 16, 20, 33, 49])
+def test_wide_write_path_planted(epsm, m):
+    """Sparse outputs take the wide-lane write pass (count pass, tile offsets,
+    then only the tiles with hits): 2^25 + 12345 symbols (129 tiles of 2^18),
+    the pattern planted at both ends, around tile and piece boundaries and at
+    lane starts of one piece; unaligned packed starts; truncated output keeps
+    the ascending prefix.  (m = 8 has about 500 random hits here, so its
+    positions take the scan path instead.)"""
+    rng = np.random.default_rng(7000 + m)
+    n = (1 << 25) + 12345
+    codes = rng.integers(0, 4, n).astype(np.uint8)
+    pattern = rng.integers(0, 4, m).astype(np.uint8)
+    tile, piece = 1 << 18, 4096
+    spots = [0, n - m, 1, 63, 64, 65, piece - 1, piece, 5 * piece + 17]
+    spots += [k * tile + d for k in (1, 2, 63, 127) for d in (-m, -1, 0, 1, 30)]
+    spots += [3 * tile + 4096 + 64 * lane for lane in range(0, 64, 9)]
+    for o in spots:
+        if 0 <= o <= n - m:
+            codes[o:o + m] = pattern
+    for offset in (0, 5):
+        check(epsm, codes, pattern.tobytes(), offset=offset, label="wide planted")
+    exp = oracle.positions(codes, pattern.tobytes())
+    packed = packed_on_gpu(epsm, codes, 3)
+    plan = epsm.Plan(pattern.tobytes(), epsm.PLAN_DNA)
+    for cap in (1, exp.size // 2):
+        out = torch.full((cap + 2,), -7, dtype=torch.int64, device="cuda")
+        nh = torch.zeros(1, dtype=torch.int64, device="cuda")
+        epsm.search_dna_into(plan, packed, n, out[:cap], nh)
+        assert int(nh.item()) == exp.size
+        got = out.cpu().numpy()
+        assert np.array_equal(got[:cap], exp[:cap]) and (got[cap:] == -7).all(), cap
