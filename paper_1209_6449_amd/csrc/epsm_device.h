@@ -38,12 +38,9 @@ __device__ __forceinline__ uint64_t window64(const uint32_t (&w)[N], int k) {
     return ((uint64_t)window(w, k + 4) << 32) | window(w, k);
 }
 
-// Pattern words j, j+1 and their byte masks as 64-bit values.
+// Pattern words j, j+1 as one 64-bit value.
 __device__ __forceinline__ uint64_t pattern64(const DevPlan &p, int j) {
     return ((uint64_t)p.pw[j + 1] << 32) | p.pw[j];
-}
-__device__ __forceinline__ uint64_t mask64(const DevPlan &p, int j) {
-    return ((uint64_t)p.pmask[j + 1] << 32) | p.pmask[j];
 }
 
 // Narrow a wave mask of candidates at lane byte k with pattern words

@@ -226,7 +226,6 @@ hipError_t launch_tile_offsets(const uint32_t *tcnt, uint32_t tiles, uint64_t *t
 hipError_t launch_scan(const ScanArgs &a, TileConfig cfg, int grid, hipStream_t s);
 // Third step of a two-phase search (after tile_offsets_kernel): slots -> positions.
 hipError_t launch_expand(ScanArgs a, TileConfig cfg, hipStream_t s);
-int scan_blocks_per_cu(TileConfig cfg, const DevPlan &p);
 bool tile_config_supported(TileConfig cfg);
 // The tile configurations compiled into the library, default first; returns
 // how many there are (writes at most capacity of them).

@@ -724,16 +724,6 @@ static size_t table_bytes(const DevPlan &p) {
     return (p.variant == 2 || (p.variant == 3 && p.pk == 16)) ? ((size_t)2 << p.hash_bits) : 0;
 }
 
-int scan_blocks_per_cu(TileConfig cfg, const DevPlan &p) {
-    ScanFn fn = pick_fn(cfg, p);
-    if (!fn) return 0;
-    int blocks = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, fn, cfg.waves * kWave,
-                                                     table_bytes(p)) != hipSuccess)
-        return 0;
-    return blocks;
-}
-
 typedef void (*ExpandFn)(ScanArgs);
 
 static ExpandFn pick_expand(TileConfig cfg) {
