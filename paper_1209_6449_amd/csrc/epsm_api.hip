@@ -265,24 +265,28 @@ epsm_status run_search(epsm_plan_t plan, const uint8_t *d_text, uint64_t n, int6
     a.plan = plan->dev;
     const uint64_t wsym = dna_wide_tile_symbols();
     const uint64_t wtiles = (a.last + 1 + wsym - 1) / wsym;
-    if (dna && (plan->dev.pk == 16 || plan->dev.pk == 8) && (!write || cap <= wtiles / 2)) {
+    if (dna && (plan->dev.pk == 16 || plan->dev.pk == 8) &&
+        (!write || cap <= wtiles * kDnaWideMaxPerTile)) {
         // packed, block filter: the wide-lane kernel; positions by a count
-        // pass (tile and wave counts), the tile offsets, and a write pass
-        // over the tiles with hits.  The write pass reads its tiles again,
-        // so it is used only when most tiles hold no position (capacity at
-        // most half the tiles); denser outputs take the scan below.
+        // pass (tile and wave counts, and up to 64 hits of each wave parked),
+        // the tile offsets, and a write pass over the tiles with hits that
+        // copies the parked hits and re-reads only the spans of waves with
+        // more.  Denser outputs (capacity above kDnaWideMaxPerTile per tile)
+        // take the scan below.
         if (wtiles > 0x7FFFFFFFull) return fail(EPSM_EUNSUPPORTED, "text too long for the tile grid");
         a.num_tiles = (uint32_t)wtiles;
         a.write = write ? kWriteTwoPhase : kWriteNone;
         const size_t cnt_bytes = (wtiles * sizeof(uint32_t) + 255) & ~size_t(255);
         const size_t off_bytes = ((wtiles + 1) * sizeof(uint64_t) + 255) & ~size_t(255);
-        const size_t wave_bytes = wtiles * dna_wide_waves() * sizeof(uint32_t);
+        const size_t wave_bytes = (wtiles * dna_wide_waves() * sizeof(uint32_t) + 255) & ~size_t(255);
+        const size_t slot_bytes = wtiles * dna_wide_waves() * dna_wide_slot() * sizeof(uint32_t);
         uint8_t *ws = nullptr;
-        st = workspace_for(stream, cnt_bytes + (write ? off_bytes + wave_bytes : 0), &ws);
+        st = workspace_for(stream, cnt_bytes + (write ? off_bytes + wave_bytes + slot_bytes : 0), &ws);
         if (st != EPSM_OK) return st;
         a.tcnt = (uint32_t *)ws;
         a.toff = (uint64_t *)(ws + cnt_bytes);
         a.wcnt = (uint32_t *)(ws + cnt_bytes + off_bytes);
+        a.slots = (uint32_t *)(ws + cnt_bytes + off_bytes + wave_bytes);
         hipError_t e = launch_dna_wide(a, write ? 1 : 0, stream);
         if (e == hipSuccess)
             e = write ? launch_tile_offsets(a.tcnt, a.num_tiles, a.toff, d_n_hits, stream)

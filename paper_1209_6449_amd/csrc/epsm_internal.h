@@ -218,6 +218,10 @@ hipError_t launch_sum_tiles(const uint32_t *tcnt, uint32_t tiles, uint64_t *out,
 // positions from a.toff (exclusive tile offsets) and a.wcnt.
 uint64_t dna_wide_tile_symbols();
 uint32_t dna_wide_waves();
+uint32_t dna_wide_slot();  // parked hits per wave (mode 1 writes a.slots)
+// Positions per tile (on average, from the output capacity) up to which
+// packed searches take the wide-lane write.
+constexpr uint64_t kDnaWideMaxPerTile = 128;
 hipError_t launch_dna_wide(const ScanArgs &a, int mode, hipStream_t s);
 // toff[i] = sum of tcnt[0 .. i) for i <= tiles, and *total = toff[tiles]
 // (one workgroup).

@@ -449,15 +449,18 @@ hipError_t launch_sum_tiles(const uint32_t *tcnt, uint32_t tiles, uint64_t *out,
 // run's words picked by selects (a runtime register index would move the
 // run to scratch).
 // Modes: kWideCount stores each tile's count; kWideCountWaves also each
-// wave's (for a later write); kWideWrite re-scans the tiles with hits and
-// writes their positions from the tile offsets and wave counts.  Within a
-// piece the starts are ordered by lane, then bit, so a lane's hits are
-// consecutive in the output and each lane writes its own run.
+// wave's, and parks up to kWideSlot of a wave's hits (offsets in the tile,
+// ascending) in its slot; kWideWrite writes the positions of the tiles with
+// hits from the tile offsets and wave counts: a wave whose hits fit its slot
+// copies them, a wave with more re-scans its span.  Within a piece the
+// starts are ordered by lane, then bit, so a lane's hits are consecutive in
+// the output and each lane writes its own run.
 constexpr int kWideWaves = 8;
 constexpr int kWidePieces = 8;                      // pieces per wave and tile
 constexpr uint32_t kWidePieceSym = 64 * kWave;      // 4096 symbols = 1 KiB
 constexpr uint64_t kWideTileSym = (uint64_t)kWideWaves * kWidePieces * kWidePieceSym;
 constexpr int kWideCount = 0, kWideCountWaves = 1, kWideWrite = 2;
+constexpr uint32_t kWideSlot = 64;  // parked hit offsets per wave
 
 __device__ __forceinline__ uint32_t pick4(const uint32_t (&w)[9], uint32_t q, int j) {
     // w[q + j] for q in 0..3 (j fixed), without a runtime register index
@@ -474,13 +477,16 @@ __global__ __launch_bounds__(kWideWaves * kWave) void dna_wide_kernel(ScanArgs a
     __shared__ uint32_t s_wave[kWideWaves];
     const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
     const uint32_t tile = blockIdx.x;
+    const uint64_t tile_sym = (uint64_t)tile * kWideTileSym;
+    uint32_t *slot = a.slots + ((uint64_t)tile * kWideWaves + wave) * kWideSlot;
     uint64_t pos = 0;  // write: output index of this wave's next piece
+    uint32_t mine = 0;  // write: this wave's hits
     if constexpr (MODE == kWideWrite) {
         pos = a.toff[tile];
-        if (a.toff[tile + 1] == pos) return;  // no hits in this tile
+        if (a.toff[tile + 1] == pos) return;  // no hits in this tile (uniform)
         for (int i = 0; i < wave; ++i) pos += a.wcnt[(uint64_t)tile * kWideWaves + i];
+        mine = a.wcnt[(uint64_t)tile * kWideWaves + wave];
     }
-    const uint64_t tile_sym = (uint64_t)tile * kWideTileSym;
     const __amdgpu_buffer_rsrc_t rsrc = tile_rsrc(a, tile_sym >> 2);
     {
         const uint32_t rows = (1u << a.plan.hash_bits) / 8;
@@ -488,7 +494,16 @@ __global__ __launch_bounds__(kWideWaves * kWave) void dna_wide_kernel(ScanArgs a
         u32x4 *dst = reinterpret_cast<u32x4 *>(s_table);
         for (uint32_t i = tid; i < rows; i += kWideWaves * kWave) dst[i] = src[i];
     }
-    __syncthreads();
+    __syncthreads();  // the last barrier: waves may leave after it
+    if constexpr (MODE == kWideWrite) {
+        if (mine <= kWideSlot) {
+            // the wave's hits are parked: copy them, no text read
+            const int64_t p0 = (int64_t)tile_sym - (int64_t)a.delta;
+            for (uint32_t i = lane; i < mine; i += kWave)
+                if (pos + i < a.cap) a.out[pos + i] = p0 + slot[i];
+            return;
+        }
+    }
     const uint32_t wave_byte = (uint32_t)wave * kWidePieces * (kWidePieceSym / 4);
     const uint32_t lane_byte = wave_byte + (uint32_t)lane * 16;
     const bool edge = tile == 0 || tile == a.num_tiles - 1;
@@ -550,11 +565,25 @@ __global__ __launch_bounds__(kWideWaves * kWave) void dna_wide_kernel(ScanArgs a
         return hits;
     };
     const uint64_t wave_sym = tile_sym + (uint64_t)wave * kWidePieces * kWidePieceSym + (uint64_t)lane * 64;
-    uint32_t cnt = 0;
+    uint32_t cnt = 0, parked = 0;  // parked: the wave's hits so far (count pass for a write)
     auto consume = [&](uint64_t hits, uint64_t s0) {
         const uint32_t c = (uint32_t)__popcll(hits);
         if constexpr (MODE != kWideWrite) {
             cnt += c;
+            if constexpr (MODE == kWideCountWaves) {
+                if (wave_any(c != 0)) {
+                    const uint32_t incl = wave_incl_scan32(c);
+                    uint32_t at = parked + (incl - c);
+                    parked += last_lane(incl);
+                    const uint32_t rel = (uint32_t)(s0 - tile_sym);
+                    while (hits) {
+                        const uint32_t k = (uint32_t)__builtin_ctzll(hits);
+                        hits &= hits - 1;
+                        if (at < kWideSlot) slot[at] = rel + k;
+                        ++at;
+                    }
+                }
+            }
         } else {
             const uint32_t incl = wave_incl_scan32(c);
             uint64_t at = pos + (incl - c);
@@ -595,6 +624,7 @@ __global__ __launch_bounds__(kWideWaves * kWave) void dna_wide_kernel(ScanArgs a
 
 uint64_t dna_wide_tile_symbols() { return kWideTileSym; }
 uint32_t dna_wide_waves() { return kWideWaves; }
+uint32_t dna_wide_slot() { return kWideSlot; }
 
 template <int BLOCK>
 static void launch_dna_wide_block(const ScanArgs &a, int mode, hipStream_t s) {

@@ -138,10 +138,10 @@ def test_dna_plan_and_byte_search_do_not_mix(epsm):
 def test_wide_write_path_planted(epsm, m):
     """Sparse outputs take the wide-lane write pass (count pass, tile offsets,
     then only the tiles with hits): 2^25 + 12345 symbols (129 tiles of 2^18),
-    the pattern planted at both ends, around tile and piece boundaries and at
-    lane starts of one piece; unaligned packed starts; truncated output keeps
-    the ascending prefix.  (m = 8 has about 500 random hits here, so its
-    positions take the scan path instead.)"""
+    the pattern planted at both ends, around tile and piece boundaries, at
+    lane starts of one piece, and back to back over 20000 symbols of one
+    wave's span (more hits than its slot parks: that wave re-reads its span);
+    unaligned packed starts; truncated output keeps the ascending prefix."""
     rng = np.random.default_rng(7000 + m)
     n = (1 << 25) + 12345
     codes = rng.integers(0, 4, n).astype(np.uint8)
@@ -153,6 +153,11 @@ def test_wide_write_path_planted(epsm, m):
     for o in spots:
         if 0 <= o <= n - m:
             codes[o:o + m] = pattern
+    # a dense stretch inside one wave's span (8 pieces of 4096 symbols): more
+    # hits than the wave's slot parks, so that wave re-reads its span
+    dense0 = 5 * tile + 2 * 32768 + 100
+    for o in range(dense0, dense0 + 20000 - m, m):
+        codes[o:o + m] = pattern
     for offset in (0, 5):
         check(epsm, codes, pattern.tobytes(), offset=offset, label="wide planted")
     exp = oracle.positions(codes, pattern.tobytes())
