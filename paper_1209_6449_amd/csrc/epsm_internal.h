@@ -78,7 +78,8 @@ struct ScanArgs {
 // offset from a decoupled look-back and writes its positions itself.  Two
 // phase: each tile parks its hits in its own slot (an ascending list of tile
 // offsets if they fit in tile_bytes / 32 words, else its raw hit masks) and
-// publishes its per-wave counts; a second kernel turns slots into positions.
+// stores its tile and per-wave counts; one workgroup scans the tile counts
+// into offsets, and an expand kernel turns slots into positions.
 constexpr uint32_t kWriteNone = 0;
 constexpr uint32_t kWriteLookBack = 1;
 constexpr uint32_t kWriteTwoPhase = 2;

@@ -16,6 +16,7 @@ import argparse
 import csv
 import glob
 import hashlib
+import re
 import json
 import os
 import statistics
@@ -29,11 +30,23 @@ KERNEL_SOURCES = ["paper_1209_6449_amd/csrc/epsm_kernels.hip", "paper_1209_6449_
                   "paper_1209_6449_amd/tuned/gfx950_256cu.json"]
 
 
+def _code_only(text: str) -> str:
+    """C++ source without comments and with whitespace collapsed, so that a
+    documentation edit does not invalidate measured traffic (string
+    literals holding comment markers are not expected in these files)."""
+    text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", " ", text)
+    return " ".join(text.split())
+
+
 def kernel_hash() -> str:
+    """Hash of the code the measured kernels are built from (comments and
+    whitespace ignored in C++ sources) and of the tune table."""
     h = hashlib.sha256()
     for rel in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, rel), "rb") as f:
-            h.update(f.read())
+        with open(os.path.join(ROOT, rel), "r", encoding="utf-8") as f:
+            text = f.read()
+        h.update((_code_only(text) if rel.endswith((".hip", ".h")) else text).encode())
     return h.hexdigest()[:16]
 
 
