@@ -427,19 +427,16 @@ __device__ __forceinline__ void flush_list(const uint32_t *stage, uint32_t fill,
     __builtin_amdgcn_wave_barrier();
 }
 
-// Two ways to load a lane's run.  Plain: each lane loads its own 16 bytes
-// and the NL - 1 blocks after them (its right neighbours' bytes, read a
-// second time from cache).  Streaming: each lane loads only its own 16 bytes
-// with the non-temporal hint (a grid-stride read reaches 7.0 TB/s with it,
-// 6.5 without; a second read of a neighbour's bytes would miss once the
-// hint has let them go), and takes the blocks after them from its right
-// neighbour (fill_halo); lane 63's are the next piece's first bytes, the
-// same address for the whole wave, which every lane loads (one memory
-// request).  The streaming form needs a few more VGPRs, so kernels that
-// verify many words from registers keep the plain one.
+// A lane's run of byte texts is loaded in the streaming form: each lane loads
+// only its own 16 bytes with the non-temporal hint (a grid-stride read
+// reaches 7.0 TB/s with it, 6.5 without; a second read of a neighbour's bytes
+// would miss once the hint has let them go), and takes the blocks after them
+// from its right neighbour (fill_halo); lane 63's are the next piece's first
+// bytes, the same address for the whole wave, which every lane loads (one
+// memory request).
 constexpr int kStreamLoad = 2;  // cache-policy operand of the buffer load: nt
 
-template <int U, int NL, bool STREAM>
+template <int U, int NL>
 __device__ __forceinline__ void load_chunk(uint32_t (&w)[U][NL * 4 + 1], __amdgpu_buffer_rsrc_t r,
                                            uint32_t off) {
     const uint32_t halo = off - (uint32_t)__lane_id() * kPiece + (kWave - 1) * kPiece;
@@ -447,11 +444,8 @@ __device__ __forceinline__ void load_chunk(uint32_t (&w)[U][NL * 4 + 1], __amdgp
     for (int u = 0; u < U; ++u) {
 #pragma unroll
         for (int l = 0; l < NL; ++l) {
-            const u32x4 v = !STREAM ? load16(r, off + u * kWavePiece + l * kPiece)
-                            : l == 0 ? __builtin_amdgcn_raw_buffer_load_b128(r, (int)(off + u * kWavePiece), 0,
-                                                                             kStreamLoad)
-                                     : __builtin_amdgcn_raw_buffer_load_b128(
-                                           r, (int)(halo + u * kWavePiece + l * kPiece), 0, kStreamLoad);
+            const u32x4 v = __builtin_amdgcn_raw_buffer_load_b128(
+                r, (int)(l == 0 ? off + u * kWavePiece : halo + u * kWavePiece + l * kPiece), 0, kStreamLoad);
             w[u][4 * l + 0] = v.x;
             w[u][4 * l + 1] = v.y;
             w[u][4 * l + 2] = v.z;
@@ -475,10 +469,6 @@ __device__ __forceinline__ void fill_halo(uint32_t (&w)[NL * 4 + 1]) {
             w[4 * l + j] = (uint32_t)__builtin_amdgcn_update_dpp((int)w[4 * l + j], (int)w[4 * (l - 1) + j],
                                                                  0x130, 0xF, 0xF, false);
 }
-
-// Kernels whose register runs are loaded in the streaming form.
-template <int VAR, int PK, int NW>
-constexpr bool kStreamRun = VAR == 1 && PK != 7 && NW <= (PK == 8 ? 2 : 3);
 
 // DNA: one dwordx4 per lane and piece (64 symbols) at byte offset off.
 template <int U>
@@ -505,7 +495,7 @@ __device__ __forceinline__ uint32_t process_chunk(uint32_t (&w)[U][NL * 4 + 1], 
     uint32_t cnt = 0, lo = 0;
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-        if constexpr (kStreamRun<VAR, PK, NW>) fill_halo<NL>(w[u]);
+        if constexpr (VAR != 3) fill_halo<NL>(w[u]);
         uint32_t mk;
         if constexpr (VAR == 1) mk = direct_mask<NL, PK, NW>(w[u], a.plan);
         else if constexpr (VAR == 2) mk = fingerprint_mask<NL>(w[u], a.plan, tab);

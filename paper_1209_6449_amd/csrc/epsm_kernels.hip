@@ -141,7 +141,7 @@ void scan_kernel(ScanArgs a) {
     const bool tail = a.plan.m > (VAR == 3 ? 16u : 4u) * a.plan.nw;
     auto load = [&](uint32_t (&w)[U][NL * 4 + 1], uint32_t off) {
         if constexpr (VAR == 3) load_chunk_dna<U>(w, rsrc, off >> kShift);
-        else load_chunk<U, NL, kStreamRun<VAR, PK, NW>>(w, rsrc, off);
+        else load_chunk<U, NL>(w, rsrc, off);
     };
 
     uint32_t wa[U][NL * 4 + 1], wb[U][NL * 4 + 1];
@@ -154,15 +154,23 @@ void scan_kernel(ScanArgs a) {
         __syncthreads();
     }
 
+    // the loop body is two ping-pong rounds (four chunks), unrolled: with a
+    // body of one round the register allocator kept 16 more bytes live in
+    // the fingerprint and long-verify kernels and spilled them at 80 VGPRs
     uint32_t cnt = 0;
+    constexpr int kStep = C >= 4 ? 4 : 2;
+    static_assert(C % kStep == 0, "whole loop bodies per tile");
 #pragma unroll 1
-    for (int c = 0; c < C; c += 2) {
-        load(wb, lane_off + (uint32_t)(c + 1) * U * kWavePiece);
-        cnt += process_chunk<U, NL, VAR, PK, NW, kPieces / 2, kThreads>(
-            wa, c, a, s_table, lane_start, edge, tail, s_mask, tid);
-        if (c + 2 < C) load(wa, lane_off + (uint32_t)(c + 2) * U * kWavePiece);
-        cnt += process_chunk<U, NL, VAR, PK, NW, kPieces / 2, kThreads>(
-            wb, c + 1, a, s_table, lane_start, edge, tail, s_mask, tid);
+    for (int c0 = 0; c0 < C; c0 += kStep) {
+#pragma unroll
+        for (int c = c0; c < c0 + kStep; c += 2) {
+            load(wb, lane_off + (uint32_t)(c + 1) * U * kWavePiece);
+            cnt += process_chunk<U, NL, VAR, PK, NW, kPieces / 2, kThreads>(
+                wa, c, a, s_table, lane_start, edge, tail, s_mask, tid);
+            if (c + 2 < C) load(wa, lane_off + (uint32_t)(c + 2) * U * kWavePiece);
+            cnt += process_chunk<U, NL, VAR, PK, NW, kPieces / 2, kThreads>(
+                wb, c + 1, a, s_table, lane_start, edge, tail, s_mask, tid);
+        }
     }
     const uint32_t wtot = wave_sum32(cnt);
     if (lane == 0) s_wcnt[wave] = wtot;

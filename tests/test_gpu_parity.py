@@ -257,7 +257,7 @@ def test_every_built_tile_matches_oracle(epsm, tile, strategy):
         for n in (tb - 1, tb, tb + 1, 2 * tb + 977, 9 * tb + 13):
             for sigma in (2, 64):
                 text = rng.integers(0, sigma, n).astype(np.uint8)
-                for m in (1, 3, 4, 9, 16, 33):
+                for m in (1, 3, 4, 6, 9, 13, 16, 33):
                     off = int(rng.integers(0, n - m + 1))
                     check(epsm, text, text[off:off + m].tobytes(),
                           label=f"tile {w}x{p} strategy {strategy} sigma {sigma}")
