@@ -265,9 +265,10 @@ epsm_status run_search(epsm_plan_t plan, const uint8_t *d_text, uint64_t n, int6
     a.plan = plan->dev;
     const uint64_t wsym = dna_wide_tile_symbols();
     const uint64_t wtiles = (a.last + 1 + wsym - 1) / wsym;
-    if (dna && (plan->dev.pk == 16 || plan->dev.pk == 8) &&
+    if (dna && (plan->dev.pk == 16 || plan->dev.pk == 8 || plan->dev.m < 8) &&
         (!write || cap <= wtiles * kDnaWideMaxPerTile)) {
-        // packed, block filter: the wide-lane kernel; positions by a count
+        // packed, block filter or (m < 8) direct compare: the wide-lane
+        // kernel; positions by a count
         // pass (tile and wave counts, and up to 64 hits of each wave parked),
         // the tile offsets, and a write pass over the tiles with hits that
         // copies the parked hits and re-reads only the spans of waves with

@@ -476,10 +476,41 @@ __device__ __forceinline__ uint32_t pick4(const uint32_t (&w)[9], uint32_t q, in
     return q == 0 ? a : q == 1 ? b : q == 2 ? c : d;
 }
 
+// Packed DNA, m < 8: every start compared directly, the 16 starts of a word
+// at once.  For pattern symbol j the run shifted by j symbols is XOR-ed with
+// p[j] repeated in every 2-bit field; start i of word q matches iff field i
+// of the OR of these differences over j < m is zero.  The zero fields are
+// then gathered into 16 bits (the inverse of a 2-bit Morton spread).
+__device__ __forceinline__ uint64_t dna_direct_hits(const uint32_t (&w)[9], const DevPlan &p) {
+    uint32_t rep[7], keep[7];  // wave-uniform
+#pragma unroll
+    for (int j = 0; j < 7; ++j) {
+        rep[j] = ((p.pw[0] >> (2 * j)) & 3u) * 0x55555555u;
+        keep[j] = (uint32_t)j < p.m ? ~0u : 0u;
+    }
+    uint64_t hits = 0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        uint32_t acc = w[q] ^ rep[0];
+#pragma unroll
+        for (int j = 1; j < 7; ++j)
+            acc |= (__builtin_amdgcn_alignbit(w[q + 1], w[q], 2 * j) ^ rep[j]) & keep[j];
+        uint32_t z = ~(acc | (acc >> 1)) & 0x55555555u;
+        z = (z | (z >> 1)) & 0x33333333u;
+        z = (z | (z >> 2)) & 0x0F0F0F0Fu;
+        z = (z | (z >> 4)) & 0x00FF00FFu;
+        z = (z | (z >> 8)) & 0x0000FFFFu;
+        hits |= (uint64_t)z << (16 * q);
+    }
+    return hits;
+}
+
+// BLOCK: 8 (m >= 16, hashed 8-symbol blocks), 4 (8 <= m < 16, 4-symbol
+// blocks indexing the table directly) or 0 (m < 8, dna_direct_hits).
 template <int MODE, int BLOCK>
 __global__ __launch_bounds__(kWideWaves * kWave) void dna_wide_kernel(ScanArgs a) {
-    static_assert(BLOCK == 4 || BLOCK == 8, "blocks of 4 (8-bit, direct index) or 8 symbols (hashed)");
-    constexpr int kBlocks = 64 / BLOCK;  // blocks at symbols BLOCK * i, i = 0..kBlocks
+    static_assert(BLOCK == 0 || BLOCK == 4 || BLOCK == 8, "direct, 4-symbol or 8-symbol blocks");
+    constexpr int kBlocks = BLOCK ? 64 / BLOCK : 0;  // blocks at symbols BLOCK * i, i = 0..kBlocks
     constexpr uint32_t kBlockMask = BLOCK == 8 ? 0xFFFFu : 0xFFu;
     extern __shared__ __attribute__((aligned(16))) uint16_t s_table[];
     __shared__ uint32_t s_wave[kWideWaves];
@@ -496,7 +527,7 @@ __global__ __launch_bounds__(kWideWaves * kWave) void dna_wide_kernel(ScanArgs a
         mine = a.wcnt[(uint64_t)tile * kWideWaves + wave];
     }
     const __amdgpu_buffer_rsrc_t rsrc = tile_rsrc(a, tile_sym >> 2);
-    {
+    if constexpr (BLOCK != 0) {
         const uint32_t rows = (1u << a.plan.hash_bits) / 8;
         const u32x4 *src = reinterpret_cast<const u32x4 *>(a.plan.table);
         u32x4 *dst = reinterpret_cast<u32x4 *>(s_table);
@@ -529,16 +560,22 @@ __global__ __launch_bounds__(kWideWaves * kWave) void dna_wide_kernel(ScanArgs a
 #pragma unroll
         for (int j = 0; j < 4; ++j)
             w[4 + j] = (uint32_t)__builtin_amdgcn_update_dpp((int)w[4 + j], (int)w[j], 0x130, 0xF, 0xF, false);
-        auto entry = [&](uint32_t block) -> uint32_t {
-            return s_table[BLOCK == 8 ? fp_hash(block, 0, a.plan.hash_bits) : block];
-        };
-        uint64_t cand = entry(w[0] & kBlockMask) & 1u;
+        uint64_t cand = 0;
+        if constexpr (BLOCK == 0) {
+            cand = dna_direct_hits(w, a.plan);
+        } else {
+            auto entry = [&](uint32_t block) -> uint32_t {
+                return s_table[BLOCK == 8 ? fp_hash(block, 0, a.plan.hash_bits) : block];
+            };
+            cand = entry(w[0] & kBlockMask) & 1u;
 #pragma unroll
-        for (int i = 1; i <= kBlocks; ++i) {
-            constexpr int kPerWord = 16 / BLOCK;
-            const uint32_t block = (w[i / kPerWord] >> (2 * BLOCK * (i % kPerWord))) & kBlockMask;
-            // bit j -> start BLOCK * i - j: reverse the BLOCK low bits, then shift
-            cand |= (uint64_t)(__builtin_bitreverse32(entry(block)) >> (32 - BLOCK)) << (BLOCK * i - (BLOCK - 1));
+            for (int i = 1; i <= kBlocks; ++i) {
+                constexpr int kPerWord = 16 / BLOCK;
+                const uint32_t block = (w[i / kPerWord] >> (2 * BLOCK * (i % kPerWord))) & kBlockMask;
+                // bit j -> start BLOCK * i - j: reverse the BLOCK low bits, then shift
+                cand |= (uint64_t)(__builtin_bitreverse32(entry(block)) >> (32 - BLOCK))
+                        << (BLOCK * i - (BLOCK - 1));
+            }
         }
         if (edge) {
             uint32_t lo = 0, hi = 64;
@@ -549,6 +586,7 @@ __global__ __launch_bounds__(kWideWaves * kWave) void dna_wide_kernel(ScanArgs a
             const uint64_t below_lo = lo >= 64 ? ~0ull : ((1ull << lo) - 1);
             cand &= below_hi & ~below_lo;
         }
+        if constexpr (BLOCK == 0) return cand;  // exact already
         uint64_t hits = 0;
         while (cand) {
             const uint32_t k = (uint32_t)__builtin_ctzll(cand);
@@ -637,7 +675,7 @@ uint32_t dna_wide_slot() { return kWideSlot; }
 template <int BLOCK>
 static void launch_dna_wide_block(const ScanArgs &a, int mode, hipStream_t s) {
     const dim3 grid(a.num_tiles), block(kWideWaves * kWave);
-    const size_t lds = (size_t)2 << a.plan.hash_bits;
+    const size_t lds = BLOCK ? (size_t)2 << a.plan.hash_bits : 0;
     if (mode == kWideCount) hipLaunchKernelGGL((dna_wide_kernel<kWideCount, BLOCK>), grid, block, lds, s, a);
     else if (mode == kWideCountWaves)
         hipLaunchKernelGGL((dna_wide_kernel<kWideCountWaves, BLOCK>), grid, block, lds, s, a);
@@ -647,7 +685,8 @@ static void launch_dna_wide_block(const ScanArgs &a, int mode, hipStream_t s) {
 hipError_t launch_dna_wide(const ScanArgs &a, int mode, hipStream_t s) {
     if (a.num_tiles == 0) return hipSuccess;
     if (a.plan.pk == 16) launch_dna_wide_block<8>(a, mode, s);
-    else launch_dna_wide_block<4>(a, mode, s);
+    else if (a.plan.pk == 8) launch_dna_wide_block<4>(a, mode, s);
+    else launch_dna_wide_block<0>(a, mode, s);
     return hipGetLastError();
 }
 

@@ -134,18 +134,22 @@ def test_dna_plan_and_byte_search_do_not_mix(epsm):
         epsm.search_batch([t], [(0, epsm.Plan(b"\x01", epsm.PLAN_DNA))])
 
 
-@pytest.mark.parametrize("m", [8, 12, 15, 16, 20, 33, 49])
+@pytest.mark.parametrize("m", [3, 6, 7, 8, 12, 15, 16, 20, 33, 49])
 def test_wide_write_path_planted(epsm, m):
     """Sparse outputs take the wide-lane write pass (count pass, tile offsets,
     then only the tiles with hits): 2^25 + 12345 symbols (129 tiles of 2^18),
     the pattern planted at both ends, around tile and piece boundaries, at
     lane starts of one piece, and back to back over 20000 symbols of one
     wave's span (more hits than its slot parks: that wave re-reads its span);
-    unaligned packed starts; truncated output keeps the ascending prefix."""
+    unaligned packed starts; truncated output keeps the ascending prefix.
+    Below m = 6 the text avoids symbol 3 and the pattern holds it, so only
+    the planted copies occur and the output stays sparse."""
     rng = np.random.default_rng(7000 + m)
     n = (1 << 25) + 12345
-    codes = rng.integers(0, 4, n).astype(np.uint8)
+    codes = rng.integers(0, 4 if m >= 6 else 3, n).astype(np.uint8)
     pattern = rng.integers(0, 4, m).astype(np.uint8)
+    if m < 6:
+        pattern[m // 2] = 3
     tile, piece = 1 << 18, 4096
     spots = [0, n - m, 1, 63, 64, 65, piece - 1, piece, 5 * piece + 17]
     spots += [k * tile + d for k in (1, 2, 63, 127) for d in (-m, -1, 0, 1, 30)]
