@@ -265,15 +265,13 @@ epsm_status run_search(epsm_plan_t plan, const uint8_t *d_text, uint64_t n, int6
     a.plan = plan->dev;
     const uint64_t wsym = dna_wide_tile_symbols();
     const uint64_t wtiles = (a.last + 1 + wsym - 1) / wsym;
-    if (dna && (plan->dev.pk == 16 || plan->dev.pk == 8 || plan->dev.m < 8) &&
-        (!write || cap <= wtiles * kDnaWideMaxPerTile)) {
-        // packed, block filter or (m < 8) direct compare: the wide-lane
-        // kernel; positions by a count
-        // pass (tile and wave counts, and up to 64 hits of each wave parked),
-        // the tile offsets, and a write pass over the tiles with hits that
-        // copies the parked hits and re-reads only the spans of waves with
-        // more.  Denser outputs (capacity above kDnaWideMaxPerTile per tile)
-        // take the scan below.
+    if (dna && (!write || cap <= wtiles * kDnaWideMaxPerTile)) {
+        // packed: the wide-lane kernel (block filter for m >= 8, direct
+        // compare below); positions by a count pass (tile and wave counts,
+        // and up to 64 hits of each wave parked), the tile offsets, and a
+        // write pass over the tiles with hits that copies the parked hits
+        // and re-reads only the spans of waves with more.  Denser outputs
+        // (capacity above kDnaWideMaxPerTile per tile) take the scan below.
         if (wtiles > 0x7FFFFFFFull) return fail(EPSM_EUNSUPPORTED, "text too long for the tile grid");
         a.num_tiles = (uint32_t)wtiles;
         a.write = write ? kWriteTwoPhase : kWriteNone;
