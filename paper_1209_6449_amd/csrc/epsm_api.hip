@@ -627,16 +627,17 @@ epsm_status epsm_plan(const uint8_t *pattern, uint64_t m, uint32_t flags, epsm_p
         d.pmask[j] = mask;
     }
     d.variant = fingerprint ? EPSM_VARIANT_FINGERPRINT : EPSM_VARIANT_DIRECT;
-    // three dwordx4 loads per lane only where the register run must hold 8
-    // pattern words (direct compare of m > 16); the fingerprint filter needs
-    // bytes 0..23 of the run, verifies 16 bytes from registers and the rest
-    // with the tail check, which keeps it at two loads and fewer VGPRs
+    // a lane's register run spans three 16-byte blocks only where it must
+    // hold 8 pattern words (direct compare of m > 16); the fingerprint
+    // filter needs bytes 0..23 of the run, verifies 16 bytes from registers
+    // and the rest with the tail check, which keeps it at two blocks and
+    // fewer VGPRs
     d.nl = (!fingerprint && m > 16) ? 3 : 2;
     const uint32_t nwmax = 4 * d.nl - 4;
     const uint64_t words = (m + 3) / 4;
     d.nw = (uint32_t)std::min<uint64_t>(words, nwmax);
     // prefix bytes of the direct filter: for m >= 5 one 64-bit compare of
-    // the first min(m, 8) bytes (a register run of two loads holds every
+    // the first min(m, 8) bytes (a register run of two blocks holds every
     // window it needs), so m <= 8 needs no verify at all
     d.pk = (uint32_t)std::min<uint64_t>(m, 4);
     if (!fingerprint && d.nl == 2 && m >= 5 && !(flags & EPSM_PLAN_PREFIX4))
