@@ -221,13 +221,12 @@ uint64_t dna_wide_tile_symbols();
 uint32_t dna_wide_waves();
 uint32_t dna_wide_slot();  // parked hits per wave (mode 1 writes a.slots)
 // Positions per tile (on average, from the output capacity) up to which
-// packed searches take the wide-lane write: one per 32 symbols.  Measured
+// packed searches take the wide-lane write: one per 16 symbols.  Measured
 // on 2^32 uniform symbols, its re-read of waves with more hits than their
-// slot beats the 16-start scan's write from 256 to 4096 positions per tile
-// (m = 5..3: 0.67 -> 0.32, 0.92 -> 0.69 ms) and loses from 16384 (m = 2:
-// 1.13 -> 1.65 ms), where lane-by-lane stores of dense runs cost more
-// than the staged, coalesced write.
-constexpr uint64_t kDnaWideMaxPerTile = 8192;
+// slot, written through the LDS stage, beats the 16-start scan's write from
+// 256 to 16384 positions per tile (m = 5, 4, 3, 2: 0.67 -> 0.32, 0.81 ->
+// 0.61, 0.92 -> 0.68, 1.13 -> 0.99 ms) and ties it at 65536 (m = 1: 2.5 ms).
+constexpr uint64_t kDnaWideMaxPerTile = 16384;
 hipError_t launch_dna_wide(const ScanArgs &a, int mode, hipStream_t s);
 // toff[i] = sum of tcnt[0 .. i) for i <= tiles, and *total = toff[tiles]
 // (one workgroup).

@@ -469,6 +469,10 @@ constexpr uint32_t kWidePieceSym = 64 * kWave;      // 4096 symbols = 1 KiB
 constexpr uint64_t kWideTileSym = (uint64_t)kWideWaves * kWidePieces * kWidePieceSym;
 constexpr int kWideCount = 0, kWideCountWaves = 1, kWideWrite = 2;
 constexpr uint32_t kWideSlot = 64;  // parked hit offsets per wave
+// write pass: a wave's hits are staged in LDS (offsets in its span) and
+// written by consecutive lanes; a piece with more hits than this is
+// written lane by lane
+constexpr uint32_t kWideStage = 1536;
 
 __device__ __forceinline__ uint32_t pick4(const uint32_t (&w)[9], uint32_t q, int j) {
     // w[q + j] for q in 0..3 (j fixed), without a runtime register index
@@ -518,7 +522,7 @@ __global__ __launch_bounds__(kWideWaves * kWave) void dna_wide_kernel(ScanArgs a
     const uint32_t tile = blockIdx.x;
     const uint64_t tile_sym = (uint64_t)tile * kWideTileSym;
     uint32_t *slot = a.slots + ((uint64_t)tile * kWideWaves + wave) * kWideSlot;
-    uint64_t pos = 0;  // write: output index of this wave's next piece
+    uint64_t pos = 0;  // write: output index of this wave's first hit
     uint32_t mine = 0;  // write: this wave's hits
     if constexpr (MODE == kWideWrite) {
         pos = a.toff[tile];
@@ -610,7 +614,15 @@ __global__ __launch_bounds__(kWideWaves * kWave) void dna_wide_kernel(ScanArgs a
         }
         return hits;
     };
-    const uint64_t wave_sym = tile_sym + (uint64_t)wave * kWidePieces * kWidePieceSym + (uint64_t)lane * 64;
+    const uint64_t wave_base = tile_sym + (uint64_t)wave * kWidePieces * kWidePieceSym;
+    const uint64_t wave_sym = wave_base + (uint64_t)lane * 64;
+    // write pass: the wave's LDS stage (after the table), its fill, and the
+    // hits already written from this wave's output base `pos`
+    uint32_t *stage = reinterpret_cast<uint32_t *>(s_table + (BLOCK ? (1u << a.plan.hash_bits) : 0u)) +
+                      (uint32_t)wave * kWideStage;
+    const int64_t wave_p0 = (int64_t)wave_base - (int64_t)a.delta;
+    uint32_t fill = 0;
+    uint64_t done = 0;
     uint32_t cnt = 0, parked = 0;  // parked: the wave's hits so far (count pass for a write)
     auto consume = [&](uint64_t hits, uint64_t s0) {
         const uint32_t c = (uint32_t)__popcll(hits);
@@ -632,15 +644,33 @@ __global__ __launch_bounds__(kWideWaves * kWave) void dna_wide_kernel(ScanArgs a
             }
         } else {
             const uint32_t incl = wave_incl_scan32(c);
-            uint64_t at = pos + (incl - c);
-            pos += last_lane(incl);
-            const int64_t p0 = (int64_t)s0 - (int64_t)a.delta;
+            const uint32_t tot = last_lane(incl);
+            if (tot == 0) return;
+            if (fill + tot > kWideStage) {
+                flush_stage(stage, fill, a.out, a.cap, pos + done, wave_p0, lane);
+                done += fill;
+                fill = 0;
+            }
+            if (tot > kWideStage) {
+                uint64_t at = pos + done + (incl - c);
+                const int64_t p0 = (int64_t)s0 - (int64_t)a.delta;
+                while (hits) {
+                    const uint32_t k = (uint32_t)__builtin_ctzll(hits);
+                    hits &= hits - 1;
+                    if (at < a.cap) a.out[at] = p0 + k;
+                    ++at;
+                }
+                done += tot;
+                return;
+            }
+            uint32_t at = fill + (incl - c);
+            const uint32_t rel = (uint32_t)(s0 - wave_base);
             while (hits) {
                 const uint32_t k = (uint32_t)__builtin_ctzll(hits);
                 hits &= hits - 1;
-                if (at < a.cap) a.out[at] = p0 + k;
-                ++at;
+                stage[at++] = rel + k;
             }
+            fill += tot;
         }
     };
     uint32_t wa[9], wb[9];
@@ -653,6 +683,8 @@ __global__ __launch_bounds__(kWideWaves * kWave) void dna_wide_kernel(ScanArgs a
         if (p + 2 < kWidePieces) load(wa, p + 2);
         consume(piece(wb, sa + kWidePieceSym), sa + kWidePieceSym);
     }
+    if constexpr (MODE == kWideWrite)
+        if (fill) flush_stage(stage, fill, a.out, a.cap, pos + done, wave_p0, lane);
     if constexpr (MODE != kWideWrite) {
         const uint32_t wt = wave_sum32(cnt);
         if constexpr (MODE == kWideCountWaves)
@@ -675,7 +707,8 @@ uint32_t dna_wide_slot() { return kWideSlot; }
 template <int BLOCK>
 static void launch_dna_wide_block(const ScanArgs &a, int mode, hipStream_t s) {
     const dim3 grid(a.num_tiles), block(kWideWaves * kWave);
-    const size_t lds = BLOCK ? (size_t)2 << a.plan.hash_bits : 0;
+    const size_t table = BLOCK ? (size_t)2 << a.plan.hash_bits : 0;
+    const size_t lds = table + (mode == kWideWrite ? (size_t)kWideWaves * kWideStage * sizeof(uint32_t) : 0);
     if (mode == kWideCount) hipLaunchKernelGGL((dna_wide_kernel<kWideCount, BLOCK>), grid, block, lds, s, a);
     else if (mode == kWideCountWaves)
         hipLaunchKernelGGL((dna_wide_kernel<kWideCountWaves, BLOCK>), grid, block, lds, s, a);
