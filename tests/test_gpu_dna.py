@@ -174,3 +174,33 @@ def test_wide_write_path_planted(epsm, m):
         assert int(nh.item()) == exp.size
         got = out.cpu().numpy()
         assert np.array_equal(got[:cap], exp[:cap]) and (got[cap:] == -7).all(), cap
+
+
+def test_wide_write_dense_pieces(epsm):
+    """Through the wide-lane write (sparse on average over 2^25 symbols), a
+    run of 20000 zero symbols in a text over {1, 2, 3}
+    gives pieces where every start hits for the pattern 00: those pieces
+    hold more hits than the wave's LDS stage and are written lane by lane,
+    between staged pieces at the run's ends; unaligned packed start and a
+    truncated output too."""
+    rng = np.random.default_rng(9100)
+    n = (1 << 25) + 999
+    codes = rng.integers(1, 4, n).astype(np.uint8)
+    run0 = 7 * (1 << 18) + 3 * 32768 + 1234  # inside one wave's span and the next
+    codes[run0:run0 + 20000] = 0
+    codes[5:7] = 0
+    codes[n - 2:] = 0
+    pattern = bytes([0, 0])
+    for offset in (0, 9):
+        assert check(epsm, codes, pattern, offset=offset, label="wide dense pieces") == 20001
+    exp = oracle.positions(codes, pattern)
+    packed = packed_on_gpu(epsm, codes, 0)
+    plan = epsm.Plan(pattern, epsm.PLAN_DNA)
+    cap = 10007
+    out = torch.full((cap + 2,), -7, dtype=torch.int64, device="cuda")
+    nh = torch.zeros(1, dtype=torch.int64, device="cuda")
+    epsm.search_dna_into(plan, packed, n, out[:cap], nh)
+    assert int(nh.item()) == exp.size
+    got = out.cpu().numpy()
+    assert np.array_equal(got[:cap], exp[:cap]) and (got[cap:] == -7).all()
+    epsm.stream_check()
