@@ -1,22 +1,29 @@
-"""Build libepsm.so (HIP, gfx950) in-tree with hipcc."""
+"""Build libepsm.so (HIP, gfx950) in-tree with hipcc.
+
+Each source is compiled to its own object (in parallel: the kernel file
+dominates), then the objects are linked into one shared library.  The
+objects live in a `_build` folder beside the output.
+"""
 from __future__ import annotations
 
 import os
 import subprocess
 import sys
+from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libepsm.so")
-SOURCES = ["epsm_kernels.hip", "epsm_batch.hip", "epsm_stride.hip", "epsm_api.hip", "epsm_serve.hip"]
+SOURCES = ["epsm_kernels.hip", "epsm_tile_8x16.hip", "epsm_tile_8x8.hip", "epsm_tile_4x16.hip",
+           "epsm_tile_4x32.hip", "epsm_tile_16x8.hip", "epsm_tile_16x16.hip", "epsm_batch.hip",
+           "epsm_stride.hip", "epsm_api.hip", "epsm_serve.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",
     "-O3",
     "-std=c++17",
     "-fPIC",
-    "-shared",
     "-Wall",
     # the six-waves-per-SIMD register target of the scan kernels is not met
     # by the tiles whose LDS allows fewer waves; that is expected
@@ -32,28 +39,43 @@ def hipcc() -> str:
     return path if os.path.exists(path) else "hipcc"
 
 
-def build(out: str = LIB, extra: list[str] | None = None, verbose: bool = False) -> str:
-    srcs = [os.path.join(CSRC, s) for s in SOURCES]
-    tmp = out + ".tmp"
-    cmd = [hipcc()] + HIPCC_FLAGS + (extra or []) + srcs + ["-o", tmp]
+def _run(cmd: list[str], verbose: bool) -> None:
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
+
+
+def build(out: str = LIB, extra: list[str] | None = None, verbose: bool = False) -> str:
+    """Compile every source (always, even if a library is present) and link `out`."""
+    objdir = os.path.join(os.path.dirname(os.path.abspath(out)), "_build",
+                          os.path.basename(out).replace(".", "_"))
+    os.makedirs(objdir, exist_ok=True)
+    flags = HIPCC_FLAGS + (extra or [])
+    objs = [os.path.join(objdir, s.replace(".hip", ".o")) for s in SOURCES]
+    jobs = [[hipcc()] + flags + ["-c", os.path.join(CSRC, s), "-o", o] for s, o in zip(SOURCES, objs)]
+    workers = max(1, min(len(jobs), int(os.environ.get("MAX_JOBS", "0")) or os.cpu_count() or 1))
+    with ThreadPoolExecutor(max_workers=workers) as ex:
+        for f in [ex.submit(_run, j, verbose) for j in jobs]:
+            f.result()
+    tmp = out + ".tmp"
+    _run([hipcc()] + flags + ["-shared"] + objs + ["-o", tmp], verbose)
     os.replace(tmp, out)
     return out
 
 
 def dump_isa(dest_dir: str) -> None:
-    """Write the gfx950 assembly of the kernels (for inspection)."""
+    """Write the gfx950 assembly of the default-tile scan kernels into dest_dir (for inspection)."""
     os.makedirs(dest_dir, exist_ok=True)
-    src = os.path.join(CSRC, "epsm_kernels.hip")
+    src = os.path.join(CSRC, "epsm_tile_8x16.hip")
     cmd = [hipcc(), "--offload-arch=gfx950", "-O3", "-std=c++17", "--cuda-device-only", "-S",
            "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-           "-I", os.path.join(ROOT, "include"), src, "-o", os.path.join(dest_dir, "epsm_kernels.s")]
+           "-I", os.path.join(ROOT, "include"), src, "-o", os.path.join(dest_dir, "epsm_tile_8x16.s")]
     subprocess.run(cmd, check=True)
 
 
 if __name__ == "__main__":
     build(verbose=True)
     if len(sys.argv) > 1 and sys.argv[1] == "--isa":
-        dump_isa(sys.argv[2] if len(sys.argv) > 2 else "_work/isa")
+        if len(sys.argv) < 3:
+            sys.exit("usage: build.py --isa DEST_DIR")
+        dump_isa(sys.argv[2])

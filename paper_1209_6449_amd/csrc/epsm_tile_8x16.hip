@@ -1,0 +1,4 @@
+// Scan and expand kernels of the 8 x 16 KiB tile (see epsm_scan.h).
+#include "epsm_scan.h"
+
+EPSM_TILE_TU(8, 16)
