@@ -22,8 +22,16 @@
  *    plan was created on); other pointers are host pointers.
  *  - stream: a hipStream_t cast to void* (NULL = the default stream).  Every
  *    search call is asynchronous and stream ordered; results are valid after
- *    the stream is synchronised.  No call synchronises the stream, except
- *    where stated.
+ *    the stream is synchronised.  No search call (epsm_search, epsm_count,
+ *    their DNA forms, epsm_search_batch) waits for the device or allocates
+ *    with a device-synchronising call: workspace growth is stream ordered
+ *    (hipFreeAsync / hipMallocAsync on the stream), and batch descriptors
+ *    reach the device by a stream-ordered copy from pinned staging memory.
+ *    Calls that synchronise say so.
+ *  - Graph capture: every search call may be captured.  While its stream is
+ *    being captured a call allocates nothing; it returns EPSM_EUNSUPPORTED if
+ *    the stream's workspace is too small or the stream has no fault word yet,
+ *    so call epsm_reserve on the stream before capturing.
  *  - Errors are returned as epsm_status; a thread-local message is available
  *    from epsm_last_error().  Synchronous returns report argument and launch
  *    errors only.
@@ -161,11 +169,12 @@ uint32_t epsm_fingerprint(uint32_t lo, uint32_t hi, uint32_t k, int collide);
  * out_capacity) positions, ascending (a prefix of the full answer);
  * *d_n_hits (device, uint64) receives the full count.  d_out may be NULL if
  * out_capacity == 0.  n == 0 or m > n gives count 0.  Uses a library-owned
- * workspace tied to the stream (grown on demand; growing allocates device
- * memory, so reserve with epsm_reserve before capturing a graph).  Long
- * texts with a small out_capacity are searched in two phases (see
- * EPSM_WRITE_AUTO), whose workspace is about n/8 bytes; others in a single
- * pass.
+ * workspace tied to the stream (grown on demand, in stream order; see
+ * epsm_reserve for graph capture).  Long texts with a small out_capacity are
+ * searched in two phases (see EPSM_WRITE_AUTO), whose workspace is about n/8
+ * bytes; others in a single pass, whose tiles wait (with a bound) on their
+ * predecessors' counts: if such a wait ever gave up, the stream's fault word
+ * is set and epsm_stream_check reports it.
  */
 epsm_status epsm_search(epsm_plan_t plan, const uint8_t *d_text, uint64_t n,
                         int64_t *d_out, uint64_t out_capacity,
@@ -242,11 +251,23 @@ typedef struct {
  * always complete).  With EPSM_BATCH_COUNT_ONLY only counts, offsets and
  * total are produced.  Output is identical to calling epsm_search per pair.
  * Device plans must live on the current device.  The host arrays are read
- * before the call returns.  Plans may be host-only (EPSM_PLAN_HOST_ONLY): the
- * batch then carries their tables to the device itself, which avoids one
- * device allocation and copy per plan.
+ * before the call returns: the work descriptors built from them are copied
+ * into pinned staging memory owned by the library and reach the stream's
+ * workspace by a stream-ordered copy, so the call does not wait for the
+ * device.  A staging block is reused once its copy has completed; a block
+ * copied under graph capture is read by every replay and is kept until
+ * epsm_release.  Plans may be host-only (EPSM_PLAN_HOST_ONLY): the batch then
+ * carries their tables to the device itself, which avoids one device
+ * allocation and copy per plan.  Plans must outlive the copy (and, under
+ * capture, the graph).
  */
 epsm_status epsm_search_batch(const epsm_batch *batch, void *stream);
+
+/* Bytes of stream workspace that epsm_search_batch needs for this batch
+ * (the descriptors plus the per-(pair, tile) counts and offsets), for
+ * epsm_reserve before a graph capture.  Validates the batch as
+ * epsm_search_batch does, without its output pointers. */
+epsm_status epsm_batch_workspace(const epsm_batch *batch, uint64_t *bytes);
 
 /* ---- tuning ------------------------------------------------------------- */
 
@@ -349,8 +370,13 @@ typedef struct {
     uint32_t max_batch_queries;  /* queries per micro-batch (0 = 64) */
     uint64_t max_batch_entries;  /* (pattern, text tile) entries per micro-batch (0 = 2^25) */
     uint64_t hbm_budget;         /* device bytes for micro-batch work and outputs (0 = 16 GiB) */
-    uint32_t flags;              /* reserved, must be 0 */
+    uint32_t flags;              /* EPSM_SERVER_* (0 for normal operation) */
 } epsm_server_config;
+
+/* Test hook: every write stage fails its output allocation as if the device
+ * were out of memory; its queries complete with EPSM_ENOMEM and the slot's
+ * device memory is released. */
+#define EPSM_SERVER_FAIL_OUTPUT_ALLOC 0x1u
 
 typedef struct {
     uint64_t query_id;
@@ -398,18 +424,37 @@ void epsm_server_destroy(epsm_server_t s);
 
 /* ---- workspace and diagnostics -------------------------------------------- */
 
-/* Make sure the workspace tied to `stream` can serve texts of up to max_n
- * bytes and batches of up to max_units tiles without allocating again. */
-epsm_status epsm_reserve(void *stream, uint64_t max_n, uint64_t max_units);
+/* Make sure the workspace tied to `stream` serves, without allocating
+ * again, searches of texts of up to max_n bytes (packed DNA: max_n symbols)
+ * with any tile and write strategy, and one-shot batches whose
+ * epsm_batch_workspace is at most batch_bytes; also creates the stream's
+ * fault word and, when batch_bytes > 0, makes sure a free pinned staging
+ * block of batch_bytes exists (a batch call captured into a graph takes one
+ * such block for the life of the graph: reserve once per captured batch
+ * call).  Device allocation is stream ordered.  Call it before capturing the
+ * stream into a graph (EPSM_EUNSUPPORTED if the stream is being captured). */
+epsm_status epsm_reserve(void *stream, uint64_t max_n, uint64_t batch_bytes);
 
-/* Free every cached workspace (synchronises the device). */
+/* Free every cached workspace, fault word and staging block (synchronises
+ * the device first).  Graphs that captured library calls must not be
+ * replayed afterwards. */
 void epsm_release(void);
 
 /* Synchronise `stream` and report EPSM_EDEVICE if a kernel launched on it
- * ever gave up one of its bounded inter-workgroup waits (its output is then
- * not trustworthy).  Such a wait is not expected to time out; this is a
- * diagnostic for tests.  Returns EPSM_OK otherwise. */
+ * gave up one of its bounded inter-workgroup waits since the last check (its
+ * output is then not trustworthy; the report clears the stream's fault
+ * word).  Such a wait is not expected to time out; the Python
+ * helpers that synchronise (search, count and their DNA and batch forms)
+ * call this and raise.  Returns EPSM_OK otherwise. */
 epsm_status epsm_stream_check(void *stream);
+
+/* Test hook (process-wide; 0 disables): while enabled, single-pass positions
+ * searches make their first tile also wait on a status word that no tile
+ * publishes, with a bound of a few polls, so the wait gives up and the
+ * stream's fault word is set while every kernel exits normally.  The output
+ * is unaffected (the wait is an extra one).  Lets tests check that give-ups
+ * surface. */
+void epsm_debug_force_giveup(int enable);
 
 /* Thread-local description of the last error on this thread ("" if none). */
 const char *epsm_last_error(void);

@@ -26,7 +26,7 @@ __all__ = ["EpsmError", "Plan", "search", "count", "search_into", "count_into", 
            "stream_check", "lib", "library_path", "Batch", "BatchPlan", "search_batch",
            "set_tile_config", "set_batch_config", "tile_configs", "set_tune_table",
            "set_default_hash_bits", "pack_dna", "search_dna", "count_dna", "search_dna_into",
-           "count_dna_into"]
+           "count_dna_into", "debug_force_giveup"]
 
 
 def lib():
@@ -57,6 +57,15 @@ def _stream_handle(stream) -> int | None:
     if isinstance(stream, int):
         return stream or None
     return stream.cuda_stream or None
+
+
+def _torch_stream(stream):
+    """The torch stream a helper runs on: the caller's, else the current one."""
+    if stream is None:
+        return torch.cuda.current_stream()
+    if isinstance(stream, int):
+        return torch.cuda.ExternalStream(stream) if stream else torch.cuda.default_stream()
+    return stream
 
 
 class Plan:
@@ -135,25 +144,39 @@ def count_into(plan: Plan, text: torch.Tensor, n_hits: torch.Tensor, stream=None
            "epsm_count")
 
 
+def _sync_and_check(s) -> None:
+    """Wait for stream s and raise if a kernel on it gave up a bounded wait."""
+    _check(lib().epsm_stream_check(_stream_handle(s)), "epsm_stream_check")
+
+
 def count(text: torch.Tensor, pattern, flags: int = 0, stream=None) -> int:
-    """Number of occurrences (synchronises the stream)."""
+    """Number of occurrences (runs on `stream` and synchronises it)."""
     plan = _as_plan(pattern, flags)
-    hits = torch.zeros(1, dtype=torch.int64, device=text.device)
-    count_into(plan, text, hits, stream)
-    return int(hits.item())
+    s = _torch_stream(stream)
+    with torch.cuda.stream(s):
+        hits = torch.zeros(1, dtype=torch.int64, device=text.device)
+        count_into(plan, text, hits, s)
+        _sync_and_check(s)
+        return int(hits.item())
 
 
 def search(text: torch.Tensor, pattern, flags: int = 0, stream=None) -> torch.Tensor:
-    """All occurrence positions as an int64 tensor (counts, allocates, then searches)."""
+    """All occurrence positions as an int64 tensor (counts, allocates, then
+    searches, all on `stream`; synchronises it and raises if a bounded wait of
+    the search gave up)."""
     plan = _as_plan(pattern, flags)
-    hits = torch.zeros(1, dtype=torch.int64, device=text.device)
-    count_into(plan, text, hits, stream)
-    n = int(hits.item())
-    out = torch.empty(n, dtype=torch.int64, device=text.device)
-    search_into(plan, text, out, hits, stream)
-    if int(hits.item()) != n:
-        raise RuntimeError("count changed between passes")
-    return out
+    s = _torch_stream(stream)
+    with torch.cuda.stream(s):
+        hits = torch.zeros(1, dtype=torch.int64, device=text.device)
+        count_into(plan, text, hits, s)
+        _sync_and_check(s)
+        n = int(hits.item())
+        out = torch.empty(n, dtype=torch.int64, device=text.device)
+        search_into(plan, text, out, hits, s)
+        _sync_and_check(s)
+        if int(hits.item()) != n:
+            raise RuntimeError("count changed between passes")
+        return out
 
 
 def pack_dna(codes: torch.Tensor, stream=None) -> torch.Tensor:
@@ -197,20 +220,29 @@ def _as_dna_plan(pattern_or_plan) -> Plan:
 def count_dna(packed: torch.Tensor, n: int, pattern, stream=None) -> int:
     """Occurrences of a code pattern (bytes of 0..3, or a PLAN_DNA Plan) in n packed symbols."""
     plan = _as_dna_plan(pattern)
-    hits = torch.zeros(1, dtype=torch.int64, device=packed.device)
-    count_dna_into(plan, packed, n, hits, stream)
-    return int(hits.item())
+    s = _torch_stream(stream)
+    with torch.cuda.stream(s):
+        hits = torch.zeros(1, dtype=torch.int64, device=packed.device)
+        count_dna_into(plan, packed, n, hits, s)
+        _sync_and_check(s)
+        return int(hits.item())
 
 
 def search_dna(packed: torch.Tensor, n: int, pattern, stream=None) -> torch.Tensor:
-    """All occurrence positions (symbol indices) as an int64 tensor."""
+    """All occurrence positions (symbol indices) as an int64 tensor (on `stream`)."""
     plan = _as_dna_plan(pattern)
-    hits = torch.zeros(1, dtype=torch.int64, device=packed.device)
-    count_dna_into(plan, packed, n, hits, stream)
-    k = int(hits.item())
-    out = torch.empty(k, dtype=torch.int64, device=packed.device)
-    search_dna_into(plan, packed, n, out, hits, stream)
-    return out
+    s = _torch_stream(stream)
+    with torch.cuda.stream(s):
+        hits = torch.zeros(1, dtype=torch.int64, device=packed.device)
+        count_dna_into(plan, packed, n, hits, s)
+        _sync_and_check(s)
+        k = int(hits.item())
+        out = torch.empty(k, dtype=torch.int64, device=packed.device)
+        search_dna_into(plan, packed, n, out, hits, s)
+        _sync_and_check(s)
+        if int(hits.item()) != k:
+            raise RuntimeError("count changed between passes")
+        return out
 
 
 def set_tile_config(waves: int, pieces: int) -> None:
@@ -223,8 +255,16 @@ def stream_check(stream=None) -> None:
     _check(lib().epsm_stream_check(_stream_handle(stream)), "epsm_stream_check")
 
 
-def reserve(max_n: int, max_units: int = 0, stream=None) -> None:
-    _check(lib().epsm_reserve(_stream_handle(stream), max_n, max_units), "epsm_reserve")
+def reserve(max_n: int, batch_bytes: int = 0, stream=None) -> None:
+    """epsm_reserve: workspace for texts up to max_n and one-shot batches whose
+    workspace (Batch.workspace_bytes) is up to batch_bytes; call it before
+    capturing the stream into a graph."""
+    _check(lib().epsm_reserve(_stream_handle(stream), max_n, batch_bytes), "epsm_reserve")
+
+
+def debug_force_giveup(enable: bool) -> None:
+    """Test hook epsm_debug_force_giveup (process-wide)."""
+    lib().epsm_debug_force_giveup(1 if enable else 0)
 
 
 # ---------------------------------------------------------------------------
@@ -277,6 +317,13 @@ class Batch:
         _check(lib().epsm_search_batch(ctypes.byref(self.struct), _stream_handle(stream)),
                "epsm_search_batch")
 
+    def workspace_bytes(self) -> int:
+        """epsm_batch_workspace: stream workspace a one-shot run of this batch needs."""
+        b = ctypes.c_uint64()
+        _check(lib().epsm_batch_workspace(ctypes.byref(self.struct), ctypes.byref(b)),
+               "epsm_batch_workspace")
+        return b.value
+
 
 class BatchPlan:
     """A prepared batch (epsm_batch_prepare); launch() replays a captured graph."""
@@ -316,15 +363,19 @@ def search_batch(texts, pairs, stream=None, groups: bool = True):
     its own in the count pass (EPSM_BATCH_NO_GROUPS).
     """
     pairs = [(ti, _as_plan(p)) for ti, p in pairs]
-    b0 = Batch(texts, pairs, count_only=True, groups=groups)
-    b0.run(stream)
-    total = int(b0.total.item())
-    dev = texts[0].device if texts else torch.device("cuda")
-    out = torch.empty(max(total, 1), dtype=torch.int64, device=dev)
-    b1 = Batch(texts, pairs, out=out[:total] if total else None, groups=groups)
-    b1.run(stream)
-    n = len(pairs)
-    return out[:total], b1.counts[:n], b1.offsets[:n]
+    s = _torch_stream(stream)
+    with torch.cuda.stream(s):
+        b0 = Batch(texts, pairs, count_only=True, groups=groups)
+        b0.run(s)
+        s.synchronize()
+        total = int(b0.total.item())
+        dev = texts[0].device if texts else torch.device("cuda")
+        out = torch.empty(max(total, 1), dtype=torch.int64, device=dev)
+        b1 = Batch(texts, pairs, out=out[:total] if total else None, groups=groups)
+        b1.run(s)
+        s.synchronize()
+        n = len(pairs)
+        return out[:total], b1.counts[:n], b1.offsets[:n]
 
 
 def tile_configs() -> list[tuple[int, int]]:

@@ -38,6 +38,7 @@ CLASS_WORDS = 1
 CLASS_FINGERPRINT = 2
 CLASS_DNA = 3
 N_CLASSES = 4
+SERVER_FAIL_OUTPUT_ALLOC = 0x1
 BATCH_COUNT_ONLY = 0x1
 BATCH_NO_GROUPS = 0x2
 MAX_M = 4096
@@ -157,6 +158,8 @@ SIGNATURES = {
     "epsm_reserve": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint64]),
     "epsm_release": (None, []),
     "epsm_stream_check": (ctypes.c_int, [ctypes.c_void_p]),
+    "epsm_debug_force_giveup": (None, [ctypes.c_int]),
+    "epsm_batch_workspace": (ctypes.c_int, [ctypes.POINTER(Batch), ctypes.POINTER(ctypes.c_uint64)]),
     "epsm_server_create": (ctypes.c_int, [ctypes.POINTER(ServerConfig), ctypes.POINTER(ctypes.c_void_p)]),
     "epsm_server_add_text": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64,
                                             ctypes.POINTER(ctypes.c_uint32)]),

@@ -5,9 +5,11 @@
 // a per-stream device workspace for the look-back status words, and kernel
 // launches.  Nothing here touches text bytes: all matching runs on the GPU.
 #include <algorithm>
+#include <atomic>
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <memory>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -44,6 +46,7 @@ std::mutex g_tune_mutex;
 TileConfig g_tile = {8, 16};
 std::vector<epsm_tune_entry> g_tune;
 uint32_t g_default_hash_bits = kDefaultHashBits;
+std::atomic<bool> g_debug_giveup{false};  // epsm_debug_force_giveup
 constexpr uint32_t kMaxTuneEntries = 256;
 
 uint32_t kernel_class(const DevPlan &d) {
@@ -90,8 +93,10 @@ SearchWorkspace search_workspace(uint64_t tiles, TileConfig tile, uint32_t write
     SearchWorkspace w;
     size_t at = 0;
     if (write == kWriteLookBack) {
+        // one status word per tile, plus one that no tile publishes (the
+        // target of the forced wait of epsm_debug_force_giveup)
         w.status = at;
-        at += tiles * sizeof(uint64_t);
+        at += (tiles + 1) * sizeof(uint64_t);
         w.zeroed = at;
     } else if (write == kWriteTwoPhase) {
         w.tcnt = at;
@@ -112,6 +117,10 @@ SearchWorkspace search_workspace(uint64_t tiles, TileConfig tile, uint32_t write
 
 
 // ---- workspace: one device buffer per (device, stream), grown on demand ----
+// Growth is stream ordered (hipFreeAsync of the old buffer, hipMallocAsync of
+// the new one, both on the stream), so it never waits for the device.  While
+// the stream is being captured into a graph nothing may be allocated: a call
+// that needs more than the stream holds fails, and the caller reserves first.
 struct Workspace {
     uint8_t *ptr = nullptr;
     size_t bytes = 0;
@@ -120,6 +129,11 @@ struct Workspace {
 std::mutex g_ws_mutex;
 std::map<std::pair<int, hipStream_t>, Workspace> g_ws;
 
+bool capturing(hipStream_t stream) {
+    hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
+    return hipStreamIsCapturing(stream, &st) == hipSuccess && st != hipStreamCaptureStatusNone;
+}
+
 epsm_status workspace_for(hipStream_t stream, size_t bytes, uint8_t **out) {
     int dev = 0;
     hipError_t e = hipGetDevice(&dev);
@@ -127,18 +141,22 @@ epsm_status workspace_for(hipStream_t stream, size_t bytes, uint8_t **out) {
     std::lock_guard<std::mutex> lock(g_ws_mutex);
     Workspace &ws = g_ws[{dev, stream}];
     if (ws.bytes < bytes) {
+        if (capturing(stream))
+            return fail(EPSM_EUNSUPPORTED, "the stream is being captured and its workspace holds " +
+                                               std::to_string(ws.bytes) + " bytes, this call needs " +
+                                               std::to_string(bytes) + ": call epsm_reserve before capturing");
         if (ws.ptr) {
-            e = hipFree(ws.ptr);  // implicitly synchronises: no kernel still uses it
+            e = hipFreeAsync(ws.ptr, stream);  // after the stream's earlier work
             ws.ptr = nullptr;
             ws.bytes = 0;
-            if (e != hipSuccess) return hip_fail(e, "hipFree(workspace)");
+            if (e != hipSuccess) return hip_fail(e, "hipFreeAsync(workspace)");
         }
         size_t want = std::max<size_t>(bytes, 1 << 16);
         want = (want + 4095) & ~size_t(4095);
-        e = hipMalloc(&ws.ptr, want);
+        e = hipMallocAsync((void **)&ws.ptr, want, stream);
         if (e != hipSuccess) {
             ws.ptr = nullptr;
-            return hip_fail(e, "hipMalloc(workspace)");
+            return hip_fail(e, "hipMallocAsync(workspace)");
         }
         ws.bytes = want;
         ws.device = dev;
@@ -148,25 +166,107 @@ epsm_status workspace_for(hipStream_t stream, size_t bytes, uint8_t **out) {
 }
 
 // One device word per (device, stream) that kernels set when a bounded wait
-// gives up; read back by epsm_stream_check.
+// gives up; read back by epsm_stream_check.  Created (and cleared by a kernel
+// on the stream, in stream order) by epsm_reserve or by the first search on
+// the stream; never while the stream is being captured.
 std::map<std::pair<int, hipStream_t>, uint32_t *> g_fault;
 
-uint32_t *fault_word(hipStream_t stream) {
+epsm_status fault_word(hipStream_t stream, bool create, uint32_t **out) {
+    *out = nullptr;
     int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess) return nullptr;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
     std::lock_guard<std::mutex> lock(g_ws_mutex);
-    uint32_t *&f = g_fault[{dev, stream}];
-    if (!f) {
-        if (hipMalloc(&f, 256) != hipSuccess) {
-            f = nullptr;
-            return nullptr;
-        }
-        if (hipMemset(f, 0, 256) != hipSuccess) {
-            (void)hipFree(f);
-            f = nullptr;
-        }
+    auto it = g_fault.find({dev, stream});
+    if (it != g_fault.end()) {
+        *out = it->second;
+        return EPSM_OK;
     }
-    return f;
+    if (!create) return EPSM_OK;
+    if (capturing(stream))
+        return fail(EPSM_EUNSUPPORTED, "the stream is being captured and has no fault word yet: "
+                                       "call epsm_reserve on it before capturing");
+    uint32_t *f = nullptr;
+    e = hipMallocAsync((void **)&f, 256, stream);
+    if (e != hipSuccess) return hip_fail(e, "hipMallocAsync(fault word)");
+    e = launch_zero_u64((uint64_t *)f, 256 / 8, stream);
+    if (e != hipSuccess) {
+        (void)hipFreeAsync(f, stream);
+        return hip_fail(e, "launch(zero fault word)");
+    }
+    g_fault[{dev, stream}] = f;
+    *out = f;
+    return EPSM_OK;
+}
+
+// ---- pinned staging of batch descriptors -----------------------------------
+// A one-shot batch builds its descriptors on the host; they reach the device
+// by one stream-ordered copy from pinned host memory, so the call returns
+// without waiting for the device.  A block is reused once the event recorded
+// after its copy has completed; a block copied under graph capture is read by
+// every replay of the graph, so it is kept until epsm_release.
+struct StagingBlock {
+    uint8_t *host = nullptr;
+    size_t bytes = 0;
+    hipEvent_t done = nullptr;  // recorded after the copy (not under capture)
+    bool in_use = false;        // a copy may still read it (check `done`)
+    bool filling = false;       // being filled by a caller: not available
+    bool captured = false;      // read by a graph: never reused
+    int device = -1;
+};
+std::mutex g_staging_mutex;
+std::vector<StagingBlock *> g_staging;
+
+// A free block of at least `bytes` (the smallest), else a new one.  Under
+// graph capture nothing may be allocated or queried, so only blocks already
+// known to be free qualify (epsm_reserve sets one aside).
+epsm_status staging_acquire(size_t bytes, int dev, bool capture, StagingBlock **out) {
+    std::lock_guard<std::mutex> lock(g_staging_mutex);
+    StagingBlock *best = nullptr;
+    for (StagingBlock *b : g_staging) {
+        if (b->captured || b->filling || b->device != dev) continue;
+        if (b->in_use && !capture && hipEventQuery(b->done) != hipErrorNotReady) b->in_use = false;
+        if (b->in_use || b->bytes < bytes) continue;
+        if (!best || b->bytes < best->bytes) best = b;
+    }
+    if (!best) {
+        if (capture)
+            return fail(EPSM_EUNSUPPORTED, "the stream is being captured and no free staging block of " +
+                                               std::to_string(bytes) + " bytes exists: call epsm_reserve "
+                                               "with batch_bytes >= epsm_batch_workspace before capturing");
+        std::unique_ptr<StagingBlock> b(new (std::nothrow) StagingBlock());
+        if (!b) return fail(EPSM_ENOMEM, "staging block");
+        size_t want = 1 << 16;
+        while (want < bytes) want *= 2;
+        hipError_t e = hipHostMalloc((void **)&b->host, want, hipHostMallocDefault);
+        if (e != hipSuccess) return hip_fail(e, "hipHostMalloc(batch staging)");
+        e = hipEventCreateWithFlags(&b->done, hipEventDisableTiming);
+        if (e != hipSuccess) {
+            (void)hipHostFree(b->host);
+            return hip_fail(e, "hipEventCreate(batch staging)");
+        }
+        b->bytes = want;
+        b->device = dev;
+        best = b.release();
+        g_staging.push_back(best);
+    }
+    best->in_use = true;
+    best->filling = true;  // until staging_commit
+    *out = best;
+    return EPSM_OK;
+}
+
+// The copy out of blk is queued (queued = false: it was not): record its
+// event, or keep the block for good when a graph captured the copy.
+epsm_status staging_commit(StagingBlock *blk, hipStream_t s, bool queued) {
+    hipError_t e = hipSuccess;
+    const bool cap = queued && capturing(s);
+    if (queued && !cap) e = hipEventRecord(blk->done, s);
+    std::lock_guard<std::mutex> lock(g_staging_mutex);
+    blk->filling = false;
+    if (!queued) blk->in_use = false;
+    if (cap || e != hipSuccess) blk->captured = true;  // no event to wait on: never reuse
+    return e == hipSuccess ? EPSM_OK : hip_fail(e, "hipEventRecord(batch staging)");
 }
 
 uint32_t load_le32(const uint8_t *p, uint64_t m, uint64_t at) {
@@ -316,8 +416,11 @@ epsm_status run_search(epsm_plan_t plan, const uint8_t *d_text, uint64_t n, int6
     a.toff = (uint64_t *)(ws + L.toff);
     a.wcnt = (uint32_t *)(ws + L.wcnt);
     a.slots = (uint32_t *)(ws + L.slots);
-    a.fault = fault_word(stream);
-    if (!a.fault) return fail(EPSM_ENOMEM, "fault word allocation");
+    if (a.write == kWriteLookBack) {
+        st = fault_word(stream, true, &a.fault);
+        if (st != EPSM_OK) return st;
+        a.debug_giveup = g_debug_giveup.load() ? 1u : 0u;
+    }
     hipError_t e = hipSuccess;
     if (L.zeroed) {
         e = launch_zero_u64((uint64_t *)ws, L.zeroed / 8, stream);
@@ -483,31 +586,43 @@ epsm_status build_batch(const epsm_batch *b, int waves, HostBatch &hb, bool chec
     return EPSM_OK;
 }
 
-epsm_status upload_batch(HostBatch &hb, const BatchLayout &L, uint8_t *dev, hipStream_t s) {
-    const BatchPtrs P = batch_ptrs(dev, L);
+epsm_status upload_batch(HostBatch &hb, const BatchLayout &L, uint8_t *dev, hipStream_t s, bool sync) {
     for (size_t k = 0; k < hb.pairs.size(); ++k) {  // point host-only plans at the blob copy
         if (hb.blob_table[k] != kNoBlob)
             hb.pairs[k].plan.table = (const uint16_t *)(dev + L.blob + hb.blob_table[k]);
         if (hb.blob_pattern[k] != kNoBlob)
             hb.pairs[k].plan.pattern = dev + L.blob + hb.blob_pattern[k];
     }
-    hipError_t e = hipSuccess;
-    auto put = [&](void *dst, const void *src, size_t bytes) {
-        if (e == hipSuccess && bytes) e = hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, s);
+    const size_t bytes = L.ptc;  // the descriptors end where the count arrays begin
+    if (bytes == 0) return EPSM_OK;
+    int devid = 0;
+    hipError_t e = hipGetDevice(&devid);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    StagingBlock *blk = nullptr;
+    epsm_status st = staging_acquire(bytes, devid, capturing(s), &blk);
+    if (st != EPSM_OK) return st;
+    uint8_t *h = blk->host;
+    auto put = [&](size_t at, const void *src, size_t n) {
+        if (n) std::memcpy(h + at, src, n);
     };
-    put(dev + L.blob, hb.blob.data(), hb.blob.size());
-    put(P.texts, hb.texts.data(), hb.texts.size() * sizeof(BatchTextDesc));
-    put(P.pairs, hb.pairs.data(), hb.pairs.size() * sizeof(BatchPairDesc));
-    put(P.order, hb.order.data(), hb.order.size() * sizeof(uint32_t));
-    put(P.solo, hb.solo.data(), hb.solo.size() * sizeof(uint32_t));
-    put(P.groups, hb.groups.data(), hb.groups.size() * sizeof(BatchGroupDesc));
-    put(P.gpairs, hb.group_pairs.data(), hb.group_pairs.size() * sizeof(uint32_t));
-    put(P.gtables, hb.group_tables.data(), hb.group_tables.size() * sizeof(uint32_t));
-    put(P.units, hb.units.data(), hb.units.size() * sizeof(BatchUnit));
-    // pageable sources: the copies are staged before hipMemcpyAsync returns,
-    // but finish them here so the host vectors can be released safely
-    if (e == hipSuccess) e = hipStreamSynchronize(s);
-    return e == hipSuccess ? EPSM_OK : hip_fail(e, "batch descriptor upload");
+    put(L.blob, hb.blob.data(), hb.blob.size());
+    put(L.texts, hb.texts.data(), hb.texts.size() * sizeof(BatchTextDesc));
+    put(L.pairs, hb.pairs.data(), hb.pairs.size() * sizeof(BatchPairDesc));
+    put(L.order, hb.order.data(), hb.order.size() * sizeof(uint32_t));
+    put(L.solo, hb.solo.data(), hb.solo.size() * sizeof(uint32_t));
+    put(L.groups, hb.groups.data(), hb.groups.size() * sizeof(BatchGroupDesc));
+    put(L.gpairs, hb.group_pairs.data(), hb.group_pairs.size() * sizeof(uint32_t));
+    put(L.gtables, hb.group_tables.data(), hb.group_tables.size() * sizeof(uint32_t));
+    put(L.units, hb.units.data(), hb.units.size() * sizeof(BatchUnit));
+    e = hipMemcpyAsync(dev, h, bytes, hipMemcpyHostToDevice, s);
+    st = staging_commit(blk, s, e == hipSuccess);
+    if (e != hipSuccess) return hip_fail(e, "batch descriptor upload");
+    if (st != EPSM_OK) return st;
+    if (sync) {
+        e = hipStreamSynchronize(s);
+        if (e != hipSuccess) return hip_fail(e, "batch descriptor upload");
+    }
+    return EPSM_OK;
 }
 
 // The kernel sequence of one batch (stream ordered, no host round trip):
@@ -833,7 +948,7 @@ epsm_status epsm_search_batch(const epsm_batch *batch, void *stream) {
     uint8_t *ws = nullptr;
     st = workspace_for((hipStream_t)stream, L.total, &ws);
     if (st != EPSM_OK) return st;
-    st = upload_batch(hb, L, ws, (hipStream_t)stream);
+    st = upload_batch(hb, L, ws, (hipStream_t)stream, false);
     if (st != EPSM_OK) return st;
     const epsm_batch_outputs o{batch->d_out, batch->out_capacity, batch->d_counts, batch->d_offsets,
                                batch->d_total, !(batch->flags & EPSM_BATCH_COUNT_ONLY)};
@@ -859,7 +974,7 @@ epsm_status epsm_batch_prepare(const epsm_batch *batch, epsm_batch_plan_t *out) 
         epsm_batch_destroy(bp);
         return hip_fail(e, "batch plan device memory");
     }
-    st = upload_batch(bp->hb, L, bp->mem, nullptr);
+    st = upload_batch(bp->hb, L, bp->mem, nullptr, true);
     if (st != EPSM_OK) {
         epsm_batch_destroy(bp);
         return st;
@@ -983,43 +1098,93 @@ epsm_status epsm_set_default_hash_bits(uint32_t k) {
     return EPSM_OK;
 }
 
-epsm_status epsm_reserve(void *stream, uint64_t max_n, uint64_t max_units) {
+epsm_status epsm_reserve(void *stream, uint64_t max_n, uint64_t batch_bytes) {
     g_last_error.clear();
+    hipStream_t s = (hipStream_t)stream;
+    if (capturing(s)) return fail(EPSM_EUNSUPPORTED, "epsm_reserve on a stream that is being captured");
     // the largest workspace any built tile and write strategy needs for max_n
     TileConfig cfg[16];
     const int nc = std::min(built_tile_configs(cfg, 16), 16);
-    size_t need = 0;
+    size_t need = batch_bytes;
     for (int i = 0; i < nc; ++i) {
-        const uint64_t tiles = max_n / (uint64_t)cfg[i].bytes() + 2 + max_units;
+        const uint64_t tiles = max_n / (uint64_t)cfg[i].bytes() + 2;
         need = std::max(need, search_workspace(tiles, cfg[i], kWriteLookBack).total);
         need = std::max(need, search_workspace(tiles, cfg[i], kWriteTwoPhase).total);
     }
+    // packed DNA texts of max_n symbols through the wide-lane kernel
+    const uint64_t wtiles = max_n / dna_wide_tile_symbols() + 2;
+    need = std::max<size_t>(need, wtiles * (4 + 8 + dna_wide_waves() * (4 + 4 * dna_wide_slot())) + 1024);
+    // strided long-pattern filter: counts, offsets and scan block sums per tile
+    const uint64_t stiles = max_n / (kStrideMin * kStrideBlocksPerTile) + 2;
+    need = std::max<size_t>(need, stiles * 12 + (stiles / kScanBlock + 2) * 8 + 1024);
     uint8_t *ws = nullptr;
-    return workspace_for((hipStream_t)stream, need, &ws);
+    epsm_status st = workspace_for(s, need, &ws);
+    if (st != EPSM_OK) return st;
+    uint32_t *f = nullptr;
+    st = fault_word(s, true, &f);
+    if (st != EPSM_OK || batch_bytes == 0) return st;
+    // one free staging block for a batch call captured later on any stream
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    StagingBlock *blk = nullptr;
+    st = staging_acquire(batch_bytes, dev, false, &blk);
+    if (st != EPSM_OK) return st;
+    std::lock_guard<std::mutex> lock(g_staging_mutex);
+    blk->filling = false;
+    blk->in_use = false;
+    return EPSM_OK;
+}
+
+epsm_status epsm_batch_workspace(const epsm_batch *batch, uint64_t *bytes) {
+    g_last_error.clear();
+    if (!bytes) return fail(EPSM_EINVAL, "bytes is NULL");
+    HostBatch hb;
+    epsm_status st = build_batch(batch, g_batch_waves, hb, false);
+    if (st != EPSM_OK) return st;
+    *bytes = BatchLayout(hb).total;
+    return EPSM_OK;
 }
 
 void epsm_release(void) {
-    std::lock_guard<std::mutex> lock(g_ws_mutex);
-    for (auto &kv : g_ws)
-        if (kv.second.ptr) (void)hipFree(kv.second.ptr);
-    g_ws.clear();
-    for (auto &kv : g_fault)
-        if (kv.second) (void)hipFree(kv.second);
-    g_fault.clear();
+    (void)hipDeviceSynchronize();
+    {
+        std::lock_guard<std::mutex> lock(g_ws_mutex);
+        for (auto &kv : g_ws)
+            if (kv.second.ptr) (void)hipFree(kv.second.ptr);
+        g_ws.clear();
+        for (auto &kv : g_fault)
+            if (kv.second) (void)hipFree(kv.second);
+        g_fault.clear();
+    }
+    std::lock_guard<std::mutex> lock(g_staging_mutex);
+    for (StagingBlock *b : g_staging) {
+        (void)hipEventDestroy(b->done);
+        (void)hipHostFree(b->host);
+        delete b;
+    }
+    g_staging.clear();
 }
+
+void epsm_debug_force_giveup(int enable) { g_debug_giveup.store(enable != 0); }
 
 epsm_status epsm_stream_check(void *stream) {
     g_last_error.clear();
     hipStream_t s = (hipStream_t)stream;
     hipError_t e = hipStreamSynchronize(s);
     if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
-    uint32_t *f = fault_word(s);
-    if (!f) return fail(EPSM_ENOMEM, "fault word allocation");
+    uint32_t *f = nullptr;
+    epsm_status st = fault_word(s, false, &f);
+    if (st != EPSM_OK) return st;
+    if (!f) return EPSM_OK;  // no waiting kernel ever ran on this stream
     uint32_t v = 0;
     e = hipMemcpy(&v, f, sizeof(v), hipMemcpyDeviceToHost);
     if (e != hipSuccess) return hip_fail(e, "hipMemcpy(fault word)");
-    if (v) return fail(EPSM_EDEVICE, "a kernel on this stream gave up a bounded wait");
-    return EPSM_OK;
+    if (!v) return EPSM_OK;
+    const uint32_t zero = 0;  // report each give-up once
+    e = hipMemcpy(f, &zero, sizeof(zero), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpy(fault word)");
+    return fail(EPSM_EDEVICE, "a kernel on this stream gave up a bounded wait: its output is not trustworthy");
 }
 
 const char *epsm_last_error(void) { return g_last_error.c_str(); }

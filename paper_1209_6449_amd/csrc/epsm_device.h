@@ -345,12 +345,13 @@ __device__ __forceinline__ uint64_t status_load(uint64_t *p) {
 constexpr int kLookLoads = 1;
 constexpr int kLookWindow = kLookLoads * kWave;
 
-__device__ __forceinline__ uint64_t poll_status(uint64_t *status, int64_t idx, uint32_t *fault) {
+__device__ __forceinline__ uint64_t poll_status(uint64_t *status, int64_t idx, uint32_t *fault,
+                                                uint32_t limit = kSpinLimit) {
     if (idx < 0) return kFlagInclusive;  // before tile 0: an inclusive zero
     uint64_t st = status_load(&status[idx]);
     uint32_t polls = 0;
     while ((st >> 62) == 0) {
-        if (++polls == kSpinLimit) {
+        if (++polls >= limit) {
             __hip_atomic_store(fault, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             return kFlagInclusive;
         }

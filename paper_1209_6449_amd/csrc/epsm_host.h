@@ -99,8 +99,10 @@ BatchPtrs batch_ptrs(uint8_t *base, const BatchLayout &L);
 // text into multi-pattern groups for the count pass.
 epsm_status build_batch(const epsm_batch *b, int waves, HostBatch &hb, bool check_outputs,
                         bool group = true);
-// Copy descriptors (and host-only plan data) to `dev`; synchronises `s`.
-epsm_status upload_batch(HostBatch &hb, const BatchLayout &L, uint8_t *dev, hipStream_t s);
+// Copy descriptors (and host-only plan data) to `dev` in stream order, from a
+// pinned staging block of the library (the host vectors may be released when
+// it returns); sync: also wait for the copy.
+epsm_status upload_batch(HostBatch &hb, const BatchLayout &L, uint8_t *dev, hipStream_t s, bool sync);
 epsm_status run_batch_count(const BatchPtrs &P, const HostBatch &hb, const epsm_batch_outputs &o,
                             hipStream_t s);
 epsm_status run_batch_write(const BatchPtrs &P, const HostBatch &hb, const epsm_batch_outputs &o,

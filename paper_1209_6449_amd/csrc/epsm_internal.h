@@ -19,6 +19,8 @@ constexpr uint64_t kValueMask = (1ull << 62) - 1;
 // cycles plus a memory round trip: several seconds in total).  Every wait is
 // expected to end long before; the bound only guarantees the kernel drains.
 constexpr uint32_t kSpinLimit = 1u << 22;
+// Poll bound of the forced wait of epsm_debug_force_giveup (a test hook).
+constexpr uint32_t kDebugSpinLimit = 64;
 
 // Fingerprint hash of an aligned 8-byte text block (lo = bytes 0..3, hi =
 // bytes 4..7, little endian), reduced to `bits` bits.  A two-multiply
@@ -71,6 +73,9 @@ struct ScanArgs {
     uint32_t shift;          // coordinates per text byte, log2: 0 bytes, 2 packed DNA
     uint32_t write;          // kWriteNone, kWriteLookBack or kWriteTwoPhase
     uint32_t expand_tiles;   // two-phase: tiles per expand workgroup, 1..kExpandTiles
+    uint32_t debug_giveup;   // single pass, test hook: tile 0 also waits (bounded) on
+                             // status[num_tiles], which no tile publishes
+    uint32_t pad_;
     DevPlan plan;
 };
 

@@ -217,7 +217,7 @@ void epsm_server_s::start_batch(Slot &s, std::unique_lock<std::mutex> &lk) {
             s.d_meta = (uint64_t *)(s.d_work + ((s.layout->total + 255) & ~size_t(255)));
             e = s.h_meta.reserve(2 * (size_t)b.n_pairs + 1);
         }
-        if (e == hipSuccess) st = upload_batch(s.hb, *s.layout, s.d_work, s.stream);
+        if (e == hipSuccess) st = upload_batch(s.hb, *s.layout, s.d_work, s.stream, false);
         else st = hip_fail(e, "serve: work buffer");
     }
     if (st == EPSM_OK) {
@@ -248,7 +248,9 @@ void epsm_server_s::counted(Slot &s) {
     start_write(s);
 }
 
-// Admit the output against the budget and launch the write stage.
+// Admit the output against the budget and launch the write stage.  On an
+// error the micro-batch fails and fail_batch releases whatever device memory
+// the slot still holds.
 void epsm_server_s::start_write(Slot &s) {
     const uint64_t need = s.total * sizeof(int64_t);
     if (need && reserved + need > cfg.hbm_budget && writing_slots()) return;  // wait for memory
@@ -256,7 +258,9 @@ void epsm_server_s::start_write(Slot &s) {
     s.out_bytes = need;
     hipError_t e = hipSuccess;
     if (s.total) {
-        e = hipMallocAsync((void **)&s.d_out, need, s.stream);
+        if (cfg.flags & EPSM_SERVER_FAIL_OUTPUT_ALLOC) e = hipErrorOutOfMemory;  // test hook
+        else e = hipMallocAsync((void **)&s.d_out, need, s.stream);
+        if (e != hipSuccess) s.d_out = nullptr;
         if (e == hipSuccess) e = s.h_pos.reserve(s.total);
         if (e == hipSuccess) {
             const BatchPtrs P = batch_ptrs(s.d_work, *s.layout);
@@ -268,13 +272,17 @@ void epsm_server_s::start_write(Slot &s) {
         if (e == hipSuccess)
             e = hipMemcpyAsync(s.h_pos.ptr, s.d_out, need, hipMemcpyDeviceToHost, s.stream);
     }
-    if (e == hipSuccess && s.d_out) e = hipFreeAsync(s.d_out, s.stream);
-    s.d_out = nullptr;
-    if (e == hipSuccess) e = hipFreeAsync(s.d_work, s.stream);
-    s.d_work = nullptr;
+    if (e == hipSuccess && s.d_out) {
+        e = hipFreeAsync(s.d_out, s.stream);
+        if (e == hipSuccess) s.d_out = nullptr;
+    }
+    if (e == hipSuccess) {
+        e = hipFreeAsync(s.d_work, s.stream);
+        if (e == hipSuccess) s.d_work = nullptr;
+    }
     if (e == hipSuccess) e = hipEventRecord(s.event, s.stream);
     if (e != hipSuccess) {
-        fail_batch(s, EPSM_EDEVICE);
+        fail_batch(s, e == hipErrorOutOfMemory ? EPSM_ENOMEM : EPSM_EDEVICE);
         return;
     }
     s.state = SlotState::Writing;
@@ -366,7 +374,7 @@ epsm_status epsm_server_create(const epsm_server_config *cfg, epsm_server_t *out
     epsm_server_s *s = new (std::nothrow) epsm_server_s();
     if (!s) return fail(EPSM_ENOMEM, "server allocation");
     if (cfg) s->cfg = *cfg;
-    if (s->cfg.flags) {
+    if (s->cfg.flags & ~EPSM_SERVER_FAIL_OUTPUT_ALLOC) {
         delete s;
         return fail(EPSM_EINVAL, "unknown server flags");
     }

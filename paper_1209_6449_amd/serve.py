@@ -39,8 +39,8 @@ class Server:
     """epsm_server: resident texts + continuous batching over `slots` streams."""
 
     def __init__(self, slots: int = 4, max_batch_queries: int = 64, max_batch_entries: int = 0,
-                 hbm_budget: int = 0):
-        cfg = _lib.ServerConfig(slots, max_batch_queries, max_batch_entries, hbm_budget, 0)
+                 hbm_budget: int = 0, flags: int = 0):
+        cfg = _lib.ServerConfig(slots, max_batch_queries, max_batch_entries, hbm_budget, flags)
         self._h = ctypes.c_void_p()
         _check(lib().epsm_server_create(ctypes.byref(cfg), ctypes.byref(self._h)), "epsm_server_create")
         self._texts = []
