@@ -5,8 +5,8 @@ import this package.  It shares no code with the GPU library and never
 imports it.
 
 Contents
-  * search / count / count_mt / search_range: ctypes wrappers over the plain C
-    brute force in epsm_oracle.c (the problem statement of the paper's
+  * search / count / count_mt / search_range / search_range_mt: ctypes wrappers
+    over the plain C brute force in epsm_oracle.c (the problem statement of the paper's
     Introduction and Section 2: every s in [0, n-m] with t[s..s+m-1] = p,
     overlaps included, ascending, 0-based).
   * occurrences_py: the same definition as a pure-Python double loop, for
@@ -54,6 +54,8 @@ def load(path: str = _LIB_PATH):
     lib.oracle_count.restype = u64
     lib.oracle_count_mt.argtypes = [u8p, u64, u8p, u64, ctypes.c_int]
     lib.oracle_count_mt.restype = u64
+    lib.oracle_range_mt.argtypes = [u8p, u64, u8p, u64, u64, u64, ctypes.c_void_p, ctypes.c_int]
+    lib.oracle_range_mt.restype = u64
     return lib
 
 
@@ -112,6 +114,17 @@ class Oracle:
                                           out.ctypes.data, cap))
         return out[:min(cap, total)], total
 
+    def search_range_mt(self, text, pattern, s_begin: int, s_end: int, threads: int) -> np.ndarray:
+        """Every occurrence starting in [s_begin, s_end), ascending, by `threads` threads."""
+        t, p = _as_u8(text), _as_u8(pattern)
+        hi = min(s_end, t.size - p.size + 1)
+        out = np.empty(max(hi - s_begin, 1), dtype=np.int64)
+        r = int(self.lib.oracle_range_mt(_ptr(t), t.size, _ptr(p), p.size, s_begin, s_end,
+                                         out.ctypes.data, threads))
+        if r == (1 << 64) - 1:
+            raise RuntimeError("oracle_range_mt could not start its threads")
+        return out[:r]
+
     def count_mt(self, text, pattern, threads: int) -> int:
         t, p = _as_u8(text), _as_u8(pattern)
         r = int(self.lib.oracle_count_mt(_ptr(t), t.size, _ptr(p), p.size, threads))
@@ -126,6 +139,7 @@ search = _default.search
 positions = _default.positions
 search_range = _default.search_range
 count_mt = _default.count_mt
+search_range_mt = _default.search_range_mt
 
 
 # --------------------------------------------------------------------------

@@ -133,3 +133,85 @@ uint64_t oracle_count_mt(const uint8_t *t, uint64_t n, const uint8_t *p, uint64_
     free(started);
     return failed ? (uint64_t)-1 : total;
 }
+
+/* ---- multi-threaded positions: contiguous start ranges, one per thread -- */
+
+struct range_job {
+    const uint8_t *t;
+    uint64_t n;
+    const uint8_t *p;
+    uint64_t m;
+    uint64_t s_begin, s_end;
+    int64_t *out;       /* room for s_end - s_begin positions */
+    uint64_t result;
+};
+
+static void *range_worker(void *arg)
+{
+    struct range_job *job = (struct range_job *)arg;
+    job->result = oracle_range(job->t, job->n, job->p, job->m, job->s_begin, job->s_end,
+                               job->out, job->s_end - job->s_begin);
+    return NULL;
+}
+
+/*
+ * The occurrences whose start lies in [s_begin, s_end), all of them, in
+ * ascending order, found by `threads` POSIX threads over contiguous start
+ * ranges.  out must hold s_end - s_begin entries (every start could match):
+ * thread i writes the occurrences of its range at out + (its first start -
+ * s_begin), then the ranges' results are moved down, in range order, to be
+ * contiguous.  Returns the number of occurrences, or (uint64_t)-1 if a thread
+ * cannot be created.
+ */
+uint64_t oracle_range_mt(const uint8_t *t, uint64_t n, const uint8_t *p, uint64_t m,
+                         uint64_t s_begin, uint64_t s_end, int64_t *out, int threads)
+{
+    if (m == 0 || m > n)
+        return 0;
+    if (s_end > n - m + 1)
+        s_end = n - m + 1;
+    if (s_begin >= s_end)
+        return 0;
+    if (threads < 1)
+        threads = 1;
+    uint64_t starts = s_end - s_begin;
+    struct range_job *jobs = calloc((size_t)threads, sizeof(*jobs));
+    pthread_t *tids = calloc((size_t)threads, sizeof(*tids));
+    char *started = calloc((size_t)threads, 1);
+    if (!jobs || !tids || !started) {
+        free(jobs);
+        free(tids);
+        free(started);
+        return (uint64_t)-1;
+    }
+    uint64_t failed = 0;
+    for (int i = 0; i < threads; i++) {
+        jobs[i].t = t;
+        jobs[i].n = n;
+        jobs[i].p = p;
+        jobs[i].m = m;
+        jobs[i].s_begin = s_begin + starts * (uint64_t)i / (uint64_t)threads;
+        jobs[i].s_end = s_begin + starts * (uint64_t)(i + 1) / (uint64_t)threads;
+        jobs[i].out = out + (jobs[i].s_begin - s_begin);
+        if (pthread_create(&tids[i], NULL, range_worker, &jobs[i]) == 0)
+            started[i] = 1;
+        else
+            failed = 1;
+    }
+    uint64_t total = 0;
+    for (int i = 0; i < threads; i++) {
+        if (!started[i])
+            continue;
+        pthread_join(tids[i], NULL);
+        /* Range i's results start at or after where the previous ranges end,
+         * so moving them down one element at a time never overwrites an
+         * element not yet moved. */
+        for (uint64_t k = 0; k < jobs[i].result; k++)
+            out[total + k] = jobs[i].out[k];
+        total += jobs[i].result;
+    }
+    free(jobs);
+    free(tids);
+    free(started);
+    return failed ? (uint64_t)-1 : total;
+}

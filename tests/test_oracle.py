@@ -190,3 +190,37 @@ def test_count_mt_matches_single_thread():
     for threads in (1, 2, 3, 8, 64):
         for p in (b"\x00", b"\x01\x02", b"\x00\x00\x00\x00"):
             assert oracle.count_mt(t, p, threads) == oracle.count(t, p)
+
+
+@pytest.mark.parametrize("sigma", [1, 2, 4, 64])
+def test_range_mt_against_find(sigma):
+    """Threaded positions over contiguous start ranges equal iterated bytes.find."""
+    rng = np.random.default_rng(100 + sigma)
+    for trial in range(12):
+        n = int(rng.integers(0, 60_000))
+        t = rng.integers(0, sigma, n).astype(np.uint8).tobytes()
+        m = int(rng.integers(1, 12))
+        if n >= m and trial % 2 == 0:
+            o = int(rng.integers(0, n - m + 1))
+            p = t[o:o + m]
+        else:
+            p = rng.integers(0, sigma, m).astype(np.uint8).tobytes()
+        full = find_all(t, p)
+        for threads in (1, 2, 5, 16, 33):
+            a = int(rng.integers(0, n + 2))
+            b = int(rng.integers(a, n + 10))
+            got = oracle.search_range_mt(t, p, a, b, threads)
+            assert got.dtype == np.int64
+            assert got.tolist() == [s for s in full if a <= s < b]
+        assert oracle.search_range_mt(t, p, 0, n, 7).tolist() == full
+
+
+def test_range_mt_unary_closed_form():
+    """a^n with a^m: every start hits, so every thread range is full."""
+    n = 1 << 20
+    t = b"a" * n
+    for m in (1, 3, 16):
+        got = oracle.search_range_mt(t, b"a" * m, 0, n, 9)
+        assert got.size == n - m + 1
+        assert np.array_equal(got, np.arange(n - m + 1, dtype=np.int64))
+        assert int(got.sum()) == (n - m) * (n - m + 1) // 2

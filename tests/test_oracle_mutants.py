@@ -8,6 +8,7 @@ at least one.
 """
 import itertools
 import os
+import random
 
 import pytest
 
@@ -36,6 +37,14 @@ MUTANTS = {
     # non-overlapping occurrences only
     "no-overlap": ("            count++;\n        }\n    }\n    return count;",
                    "            count++;\n            s += m - 1;\n        }\n    }\n    return count;"),
+    # threaded positions: ranges' results not moved together (gaps left between them)
+    "mt-no-compaction": ("out[total + k] = jobs[i].out[k];", "out[k] = jobs[i].out[k];"),
+    # threaded positions: each range after the first skips its first start
+    "mt-split-gap": ("jobs[i].s_begin = s_begin + starts * (uint64_t)i / (uint64_t)threads;",
+                     "jobs[i].s_begin = s_begin + starts * (uint64_t)i / (uint64_t)threads + (i > 0);"),
+    # threaded positions: drops the last valid start
+    "mt-last-start": ("if (s_end > n - m + 1)\n        s_end = n - m + 1;",
+                      "if (s_end > n - m)\n        s_end = n - m;"),
 }
 
 
@@ -63,6 +72,16 @@ def pin_battery(o: oracle.Oracle) -> list[str]:
         failed.append("p-equals-t")
     if o.count(b"abcabc", b"abd") != 0:
         failed.append("absent")
+    rng = random.Random(3)
+    for n in (1, 2, 5, 97, 4099):
+        t = bytes(rng.randrange(2) for _ in range(n))
+        for p in (b"\x01", b"\x00\x01", b"\x01\x01\x00"):
+            for threads in (1, 3, 7):
+                for a, b in ((0, n), (1, n - 1), (n // 3, n + 5)):
+                    exp = [s for s in find_all(t, p) if a <= s < b]
+                    if o.search_range_mt(t, p, a, b, threads).tolist() != exp:
+                        failed.append("range-mt")
+                        break
     pats = [bytes(p) for mm in range(1, 4) for p in itertools.product(b"\x00\x01", repeat=mm)]
     for n in range(0, 8):
         for tt in itertools.product(b"\x00\x01", repeat=n):
