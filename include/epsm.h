@@ -184,6 +184,31 @@ epsm_status epsm_search(epsm_plan_t plan, const uint8_t *d_text, uint64_t n,
 epsm_status epsm_count(epsm_plan_t plan, const uint8_t *d_text, uint64_t n,
                        uint64_t *d_n_hits, void *stream);
 
+/*
+ * epsm_search_noalloc: epsm_search for callers that cannot allocate device
+ * memory (code under graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  Same arguments, output, ordering and truncation as
+ * epsm_search (out_capacity == 0 gives the count only); it never allocates,
+ * frees or waits: its scratch (tile counts, look-back status words,
+ * two-phase slots, the fault word of its bounded waits) is one static device
+ * array of EPSM_NOALLOC_SCRATCH_BYTES, one copy per device, which every GPU
+ * the library runs on holds from the library's load until the process ends.
+ * A search whose scratch would not fit takes the single pass (8 bytes per
+ * tile: texts up to about 127 GiB at the default 128 KiB tile) instead of the
+ * two-phase write (about n/8 bytes); a longer text returns EPSM_EUNSUPPORTED
+ * before anything is launched.  Packed DNA plans are rejected (EPSM_EINVAL).
+ * Every call on a device shares that device's array and leaves its contents
+ * behind (what must start at zero is cleared by each call, in stream
+ * order): calls that overlap in time on one device (on different streams or
+ * from different threads) race and give wrong output, so serialise them (one
+ * stream does).  A give-up of one of its bounded waits is reported by the
+ * next epsm_stream_check on any stream of the device.
+ */
+#define EPSM_NOALLOC_SCRATCH_BYTES (8u << 20)
+epsm_status epsm_search_noalloc(epsm_plan_t plan, const uint8_t *d_text, uint64_t n,
+                                int64_t *d_out, uint64_t out_capacity, uint64_t *d_n_hits,
+                                void *stream);
+
 /* ---- packed DNA texts ------------------------------------------------------ */
 
 /*
@@ -443,7 +468,8 @@ void epsm_release(void);
 /* Synchronise `stream` and report EPSM_EDEVICE if a kernel launched on it
  * gave up one of its bounded inter-workgroup waits since the last check (its
  * output is then not trustworthy; the report clears the stream's fault
- * word).  Such a wait is not expected to time out; the Python
+ * word), or if an epsm_search_noalloc kernel on the current device did (that
+ * word is shared by the device's no-allocation calls).  Such a wait is not expected to time out; the Python
  * helpers that synchronise (search, count and their DNA and batch forms)
  * call this and raise.  Returns EPSM_OK otherwise. */
 epsm_status epsm_stream_check(void *stream);

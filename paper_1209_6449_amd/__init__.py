@@ -17,8 +17,8 @@ import torch
 
 from . import _lib
 from ._lib import (BATCH_COUNT_ONLY, CLASS_BYTES, CLASS_FINGERPRINT, CLASS_WORDS,  # noqa: F401
-                   CLASS_DNA, MAX_M, N_CLASSES, PLAN_COLLIDE, PLAN_DNA, PLAN_FORCE_DIRECT,
-                   PLAN_FORCE_FINGERPRINT, PLAN_NO_STRIDE, PLAN_PREFIX4, VARIANT_DNA, VARIANT_STRIDE,
+                   CLASS_DNA, MAX_M, NOALLOC_SCRATCH_BYTES, N_CLASSES, PLAN_COLLIDE, PLAN_DNA,
+                   PLAN_FORCE_DIRECT, PLAN_FORCE_FINGERPRINT, PLAN_NO_STRIDE, PLAN_PREFIX4, VARIANT_DNA, VARIANT_STRIDE,
                    PLAN_HASH_BITS, PLAN_HOST_ONLY, VARIANT_DIRECT, VARIANT_FINGERPRINT,
                    WRITE_AUTO, WRITE_SINGLE_PASS, WRITE_TWO_PHASE)
 
@@ -26,7 +26,7 @@ __all__ = ["EpsmError", "Plan", "search", "count", "search_into", "count_into", 
            "stream_check", "lib", "library_path", "Batch", "BatchPlan", "search_batch",
            "set_tile_config", "set_batch_config", "tile_configs", "set_tune_table",
            "set_default_hash_bits", "pack_dna", "search_dna", "count_dna", "search_dna_into",
-           "count_dna_into", "debug_force_giveup"]
+           "count_dna_into", "debug_force_giveup", "search_noalloc_into"]
 
 
 def lib():
@@ -135,6 +135,18 @@ def search_into(plan: Plan, text: torch.Tensor, out: torch.Tensor | None, n_hits
     _check(lib().epsm_search(plan.handle, text.data_ptr() if text.numel() else None,
                              text.numel(), out_ptr, cap, n_hits.data_ptr(),
                              _stream_handle(stream)), "epsm_search")
+
+
+def search_noalloc_into(plan: Plan, text: torch.Tensor, out: torch.Tensor | None, n_hits: torch.Tensor,
+                        stream=None) -> None:
+    """epsm_search_noalloc into caller tensors (the library's static scratch
+    instead of a stream workspace; calls on one device must not overlap)."""
+    _check_text(text)
+    cap = 0 if out is None else out.numel()
+    out_ptr = None if out is None or cap == 0 else out.data_ptr()
+    _check(lib().epsm_search_noalloc(plan.handle, text.data_ptr() if text.numel() else None,
+                                     text.numel(), out_ptr, cap, n_hits.data_ptr(),
+                                     _stream_handle(stream)), "epsm_search_noalloc")
 
 
 def count_into(plan: Plan, text: torch.Tensor, n_hits: torch.Tensor, stream=None) -> None:

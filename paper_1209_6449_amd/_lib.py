@@ -42,6 +42,7 @@ SERVER_FAIL_OUTPUT_ALLOC = 0x1
 BATCH_COUNT_ONLY = 0x1
 BATCH_NO_GROUPS = 0x2
 MAX_M = 4096
+NOALLOC_SCRATCH_BYTES = 8 << 20
 
 
 class PlanInfo(ctypes.Structure):
@@ -136,6 +137,9 @@ SIGNATURES = {
                                    ctypes.c_void_p]),
     "epsm_count": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64,
                                   ctypes.c_void_p, ctypes.c_void_p]),
+    "epsm_search_noalloc": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64,
+                                           ctypes.c_void_p, ctypes.c_uint64, ctypes.c_void_p,
+                                           ctypes.c_void_p]),
     "epsm_search_batch": (ctypes.c_int, [ctypes.POINTER(Batch), ctypes.c_void_p]),
     "epsm_pack_dna": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_void_p, ctypes.c_void_p]),
     "epsm_search_dna": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64,

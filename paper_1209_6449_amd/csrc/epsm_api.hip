@@ -269,6 +269,55 @@ epsm_status staging_commit(StagingBlock *blk, hipStream_t s, bool queued) {
     return e == hipSuccess ? EPSM_OK : hip_fail(e, "hipEventRecord(batch staging)");
 }
 
+// ---- static scratch of epsm_search_noalloc ----------------------------------
+// One array per device, in this code object's global memory, held from the
+// library's load until the process ends.  Host code never uses the array's
+// name as an address: hipGetSymbolAddress gives each device's copy once, with
+// that device current, and the kernels take that pointer as their workspace.
+// Bytes [0, 256) hold the fault word of its bounded waits, the rest is the
+// search workspace.  Every call on a device shares its copy.
+constexpr size_t kStaticFaultBytes = 256;
+static __device__ __align__(256) uint8_t scratch[EPSM_NOALLOC_SCRATCH_BYTES];
+static_assert(EPSM_NOALLOC_SCRATCH_BYTES > kStaticFaultBytes, "scratch too small");
+
+constexpr int kMaxStaticDevices = 64;
+std::mutex g_static_mutex;
+uint8_t *g_static_ptr[kMaxStaticDevices] = {};  // device address of `scratch`, per device
+
+// The current device's copy of `scratch` (looked up on the first call on the
+// device); create = false only reports one already looked up (else NULL).
+epsm_status static_scratch(bool create, uint8_t **out) {
+    *out = nullptr;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    if (dev < 0 || dev >= kMaxStaticDevices)
+        return fail(EPSM_EUNSUPPORTED, "device index beyond the static scratch table");
+    std::lock_guard<std::mutex> lock(g_static_mutex);
+    if (!g_static_ptr[dev] && create) {
+        void *ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+        g_static_ptr[dev] = (uint8_t *)ptr;
+    }
+    *out = g_static_ptr[dev];
+    return EPSM_OK;
+}
+
+// A caller-fixed workspace (the static scratch) used instead of the stream's:
+// a search whose layout does not fit fails instead of growing it.
+struct FixedScratch {
+    uint8_t *ws = nullptr;      // workspace
+    size_t bytes = 0;           // its size
+    uint32_t *fault = nullptr;  // fault word of bounded waits
+};
+
+epsm_status scratch_too_small(size_t need, size_t have) {
+    return fail(EPSM_EUNSUPPORTED, "this search needs " + std::to_string(need) +
+                                       " bytes of scratch; the static scratch holds " +
+                                       std::to_string(have) + " (use epsm_search)");
+}
+
 uint32_t load_le32(const uint8_t *p, uint64_t m, uint64_t at) {
     uint32_t v = 0;
     for (int b = 0; b < 4; ++b)
@@ -291,7 +340,8 @@ epsm_status check_plan(epsm_plan_t plan) {
 // scan of the counts, then (positions) the write pass; the total is the
 // scan's last entry.  Workspace: [counts u32][offsets u64][scan block sums].
 epsm_status run_stride(epsm_plan_t plan, const uint8_t *d_text, uint64_t n, int64_t *d_out,
-                       uint64_t cap, uint64_t *d_n_hits, hipStream_t stream, bool write) {
+                       uint64_t cap, uint64_t *d_n_hits, hipStream_t stream, bool write,
+                       const FixedScratch *fx) {
     const DevPlan &d = plan->dev;
     StrideArgs a{};
     const uintptr_t addr = (uintptr_t)d_text;
@@ -314,8 +364,14 @@ epsm_status run_stride(epsm_plan_t plan, const uint8_t *d_text, uint64_t n, int6
     const size_t off_bytes = ((tiles + 1) * sizeof(uint64_t) + 255) & ~size_t(255);
     const size_t bsum_bytes = ((tiles + kScanBlock - 1) / kScanBlock + 1) * sizeof(uint64_t);
     uint8_t *ws = nullptr;
-    epsm_status st = workspace_for(stream, cnt_bytes + off_bytes + bsum_bytes, &ws);
-    if (st != EPSM_OK) return st;
+    const size_t need = cnt_bytes + off_bytes + bsum_bytes;
+    if (fx) {
+        if (need > fx->bytes) return scratch_too_small(need, fx->bytes);
+        ws = fx->ws;
+    } else {
+        epsm_status st = workspace_for(stream, need, &ws);
+        if (st != EPSM_OK) return st;
+    }
     a.tile_count = (uint32_t *)ws;
     uint64_t *offsets = (uint64_t *)(ws + cnt_bytes);
     a.tile_offset = offsets;
@@ -334,7 +390,7 @@ epsm_status run_stride(epsm_plan_t plan, const uint8_t *d_text, uint64_t n, int6
 
 epsm_status run_search(epsm_plan_t plan, const uint8_t *d_text, uint64_t n, int64_t *d_out,
                        uint64_t cap, uint64_t *d_n_hits, hipStream_t stream, bool write,
-                       bool dna = false) {
+                       bool dna = false, const FixedScratch *fx = nullptr) {
     epsm_status st = check_plan(plan);
     if (st != EPSM_OK) return st;
     if (dna != (plan->dev.variant == EPSM_VARIANT_DNA))
@@ -349,7 +405,7 @@ epsm_status run_search(epsm_plan_t plan, const uint8_t *d_text, uint64_t n, int6
         return e == hipSuccess ? EPSM_OK : hip_fail(e, "launch(set)");
     }
     if (plan->dev.variant == EPSM_VARIANT_STRIDE)
-        return run_stride(plan, d_text, n, d_out, cap, d_n_hits, stream, write);
+        return run_stride(plan, d_text, n, d_out, cap, d_n_hits, stream, write, fx);
     // coordinates are bytes, or 2-bit symbols (four per byte) for packed DNA
     ScanArgs a{};
     const uint32_t sh = dna ? 2u : 0u;
@@ -365,6 +421,7 @@ epsm_status run_search(epsm_plan_t plan, const uint8_t *d_text, uint64_t n, int6
     a.plan = plan->dev;
     const uint64_t wsym = dna_wide_tile_symbols();
     const uint64_t wtiles = (a.last + 1 + wsym - 1) / wsym;
+    if (dna && fx) return fail(EPSM_EINVAL, "packed DNA searches use the stream workspace");
     if (dna && (!write || cap <= wtiles * kDnaWideMaxPerTile)) {
         // packed: the wide-lane kernel (block filter for m >= 8, direct
         // compare below); positions by a count pass (tile and wave counts,
@@ -407,17 +464,31 @@ epsm_status run_search(epsm_plan_t plan, const uint8_t *d_text, uint64_t n, int6
     else
         a.write = ch.strategy == EPSM_WRITE_TWO_PHASE ? kWriteTwoPhase : kWriteLookBack;
 
-    const SearchWorkspace L = search_workspace(tiles, tile, a.write);
+    SearchWorkspace L = search_workspace(tiles, tile, a.write);
     uint8_t *ws = nullptr;
-    st = workspace_for(stream, L.total, &ws);
-    if (st != EPSM_OK) return st;
+    if (fx) {
+        // a fixed scratch: a two-phase layout (about n/8 bytes) that does not
+        // fit falls back to the single pass (8 bytes per tile)
+        if (L.total > fx->bytes && a.write == kWriteTwoPhase) {
+            a.write = kWriteLookBack;
+            L = search_workspace(tiles, tile, a.write);
+        }
+        if (L.total > fx->bytes) return scratch_too_small(L.total, fx->bytes);
+        ws = fx->ws;
+    } else {
+        st = workspace_for(stream, L.total, &ws);
+        if (st != EPSM_OK) return st;
+    }
     a.tcnt = (uint32_t *)(ws + L.tcnt);
     a.status = (uint64_t *)(ws + L.status);
     a.toff = (uint64_t *)(ws + L.toff);
     a.wcnt = (uint32_t *)(ws + L.wcnt);
     a.slots = (uint32_t *)(ws + L.slots);
     if (a.write == kWriteLookBack) {
-        st = fault_word(stream, true, &a.fault);
+        if (fx)
+            a.fault = fx->fault;
+        else
+            st = fault_word(stream, true, &a.fault);
         if (st != EPSM_OK) return st;
         a.debug_giveup = g_debug_giveup.load() ? 1u : 0u;
     }
@@ -918,6 +989,20 @@ epsm_status epsm_count(epsm_plan_t plan, const uint8_t *d_text, uint64_t n, uint
     return run_search(plan, d_text, n, nullptr, 0, d_n_hits, (hipStream_t)stream, false);
 }
 
+epsm_status epsm_search_noalloc(epsm_plan_t plan, const uint8_t *d_text, uint64_t n, int64_t *d_out,
+                                uint64_t out_capacity, uint64_t *d_n_hits, void *stream) {
+    g_last_error.clear();
+    uint8_t *base = nullptr;
+    epsm_status st = static_scratch(true, &base);
+    if (st != EPSM_OK) return st;
+    FixedScratch fx;
+    fx.fault = (uint32_t *)base;
+    fx.ws = base + kStaticFaultBytes;
+    fx.bytes = EPSM_NOALLOC_SCRATCH_BYTES - kStaticFaultBytes;
+    return run_search(plan, d_text, n, d_out, out_capacity, d_n_hits, (hipStream_t)stream, true,
+                      false, &fx);
+}
+
 epsm_status epsm_search_dna(epsm_plan_t plan, const uint8_t *d_packed, uint64_t n, int64_t *d_out,
                             uint64_t out_capacity, uint64_t *d_n_hits, void *stream) {
     g_last_error.clear();
@@ -1173,18 +1258,30 @@ epsm_status epsm_stream_check(void *stream) {
     hipStream_t s = (hipStream_t)stream;
     hipError_t e = hipStreamSynchronize(s);
     if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
-    uint32_t *f = nullptr;
-    epsm_status st = fault_word(s, false, &f);
+    // the stream's own fault word, then the device's static one (waits of
+    // epsm_search_noalloc calls on any stream of this device)
+    uint32_t *words[2] = {nullptr, nullptr};
+    epsm_status st = fault_word(s, false, &words[0]);
     if (st != EPSM_OK) return st;
-    if (!f) return EPSM_OK;  // no waiting kernel ever ran on this stream
-    uint32_t v = 0;
-    e = hipMemcpy(&v, f, sizeof(v), hipMemcpyDeviceToHost);
-    if (e != hipSuccess) return hip_fail(e, "hipMemcpy(fault word)");
-    if (!v) return EPSM_OK;
-    const uint32_t zero = 0;  // report each give-up once
-    e = hipMemcpy(f, &zero, sizeof(zero), hipMemcpyHostToDevice);
-    if (e != hipSuccess) return hip_fail(e, "hipMemcpy(fault word)");
-    return fail(EPSM_EDEVICE, "a kernel on this stream gave up a bounded wait: its output is not trustworthy");
+    uint8_t *base = nullptr;
+    st = static_scratch(false, &base);
+    if (st != EPSM_OK) return st;
+    words[1] = (uint32_t *)base;
+    for (uint32_t *f : words) {
+        if (!f) continue;  // no waiting kernel ever used this word
+        uint32_t v = 0;
+        e = hipMemcpy(&v, f, sizeof(v), hipMemcpyDeviceToHost);
+        if (e != hipSuccess) return hip_fail(e, "hipMemcpy(fault word)");
+        if (!v) continue;
+        const uint32_t zero = 0;  // report each give-up once
+        e = hipMemcpy(f, &zero, sizeof(zero), hipMemcpyHostToDevice);
+        if (e != hipSuccess) return hip_fail(e, "hipMemcpy(fault word)");
+        return fail(EPSM_EDEVICE, f == words[0]
+                                      ? "a kernel on this stream gave up a bounded wait: its output is not trustworthy"
+                                      : "an epsm_search_noalloc kernel on this device gave up a bounded wait: "
+                                        "its output is not trustworthy");
+    }
+    return EPSM_OK;
 }
 
 const char *epsm_last_error(void) { return g_last_error.c_str(); }
