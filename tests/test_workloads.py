@@ -67,3 +67,16 @@ def test_configs_are_deterministic():
     q1 = W.config5_queries(W.config5_texts(8, 1 << 12, 1 << 14), 20, 100.0)
     q2 = W.config5_queries(W.config5_texts(8, 1 << 12, 1 << 14), 20, 100.0)
     assert [(q.arrival, q.text, q.patterns) for q in q1] == [(q.arrival, q.text, q.patterns) for q in q2]
+
+
+def test_small_ranges_equal_tensor_generator():
+    """The numpy path for short ranges gives the same bytes as the tensor path."""
+    specs = [W.TextSpec(n=1 << 20, kind="uniform", key=W.text_key(4, 3), sigma=64),
+             W.TextSpec(n=1 << 20, kind="zipf96", key=W.text_key(3, 0)),
+             W.TextSpec(n=1 << 20, kind="uniform", key=W.text_key(1, 0), sigma=4, alphabet=b"ACGT"),
+             W.TextSpec(n=1 << 20, kind="periodic", fill=0x61)]
+    for spec in specs:
+        for start, length in ((0, 1), (3, 17), (1001, 32), (5, 4096), ((1 << 20) - 33, 33), (77, 0)):
+            small = W.gen_numpy(spec, start, length)
+            ref = W.gen_bytes(spec, start, length, device="cpu").numpy()
+            assert small.dtype == np.uint8 and np.array_equal(small, ref), (spec.kind, start, length)

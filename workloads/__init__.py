@@ -182,7 +182,42 @@ def gen_bytes(spec: TextSpec, start: int = 0, length: int | None = None,
     return out
 
 
+_NP_TABLE_CACHE: dict = {}
+
+
+def _splitmix64_np(counter: np.ndarray, key: int) -> np.ndarray:
+    """splitmix64 over a uint64 array (numpy's uint64 arithmetic wraps mod 2^64)."""
+    with np.errstate(over="ignore"):
+        z = (counter + np.uint64(1)) * np.uint64(0x9E3779B97F4A7C15) + np.uint64(key & _MASK64)
+        z = (z ^ (z >> np.uint64(30))) * np.uint64(0xBF58476D1CE4E5B9)
+        z = (z ^ (z >> np.uint64(27))) * np.uint64(0x94D049BB133111EB)
+        return z ^ (z >> np.uint64(31))
+
+
+def _gen_small(spec: TextSpec, start: int, length: int) -> np.ndarray:
+    """Bytes [start, start+length) computed with numpy (the same bytes as gen_bytes)."""
+    if spec.kind == "periodic":
+        return np.full(length, spec.fill, dtype=np.uint8)
+    k = (spec.kind, spec.sigma, spec.alphabet)
+    if k not in _NP_TABLE_CACHE:
+        _NP_TABLE_CACHE[k] = spec.table()
+    table = _NP_TABLE_CACHE[k]
+    w0, w1 = start // 4, (start + length + 3) // 4
+    if w1 - w0 <= 16:
+        raw = b"".join(splitmix64_int(c, spec.key).to_bytes(8, "little") for c in range(w0, w1))
+        z = np.frombuffer(raw, dtype="<u8")
+    else:
+        z = _splitmix64_np(np.arange(w0, w1, dtype=np.uint64), spec.key).astype("<u8")
+    samples = z.view("<u2")  # sample j of a word is its bits 16j..16j+15
+    lo = start - 4 * w0
+    return table[samples[lo:lo + length]]
+
+
 def gen_numpy(spec: TextSpec, start: int = 0, length: int | None = None) -> np.ndarray:
+    if length is None:
+        length = spec.n - start
+    if 0 <= start and 0 <= length <= 65536 and start + length <= spec.n:
+        return _gen_small(spec, start, length)
     return gen_bytes(spec, start, length, device="cpu").numpy()
 
 
