@@ -88,6 +88,16 @@ typedef struct epsm_plan_s *epsm_plan_t;
  * there compares the first min(m, 8) bytes as one 64-bit word, Section 3.2's
  * packed compare at twice the width).  Output is the same. */
 #define EPSM_PLAN_PREFIX4 0x40u
+/* Direct variant with m > 16: compare the first 16 bytes from a register run
+ * of two 16-byte blocks per lane and check the rest of each surviving
+ * candidate from memory (the default run for a direct m > 16 is three
+ * blocks, holding 32 pattern bytes).  Output is the same. */
+#define EPSM_PLAN_SHORT_RUN 0x80u
+/* Alphabet-size hint: the effective number of distinct byte values of the
+ * texts the plan will search (1..256; see epsm_estimate_alphabet), in bits
+ * 16..24 of flags; 0, the default, means unknown.  Only the variant table
+ * (epsm_set_variant_table) reads it; output never depends on it. */
+#define EPSM_PLAN_SIGMA(s) (((uint32_t)(s) & 0x1FFu) << 16)
 
 /* Variants */
 #define EPSM_VARIANT_DIRECT 1u
@@ -95,8 +105,9 @@ typedef struct epsm_plan_s *epsm_plan_t;
 #define EPSM_VARIANT_DNA 3u
 /* Long patterns (m >= 263): the fingerprint filter with a stride, as EPSMc
  * (Section 3.4) is defined: only the aligned 8-byte blocks at multiples of S
- * are read (S the largest power of two <= min(m - 7, 2048)), so the text
- * lines in between are not fetched.  Every occurrence contains exactly one
+ * are read (S the largest power of two <= min(m - 7, 2048); a variant-table
+ * row may ask for it from m = 39, S >= 32), so the text lines in between are
+ * not fetched.  Every occurrence contains exactly one
  * such block, at pattern offset j in [0, S); the plan's table lists the
  * offsets per hash value, and every candidate is checked exactly.  Chosen by
  * default unless a FORCE or COLLIDE flag or EPSM_PLAN_NO_STRIDE is given;
@@ -151,7 +162,11 @@ typedef struct {
     uint32_t stride;         /* EPSM_VARIANT_STRIDE: bytes between inspected blocks, else 0 */
     uint32_t prefix_bytes;   /* EPSM_VARIANT_DIRECT: bytes of the prefix compare
                                 (min(m, 8); 4 for m > 4 with EPSM_PLAN_PREFIX4
-                                or m > 16), else 0 */
+                                or m > 16 on a three-block run), else 0 */
+    uint32_t run_blocks;     /* 16-byte blocks of a lane's register run (2 or 3;
+                                1 for DNA plans) */
+    uint32_t table_row;      /* 1 + the index of the variant-table row that chose
+                                the variant, or 0 (built-in choice or forced) */
 } epsm_plan_info;
 
 /* Copy the plan's description to *info (host memory). */
@@ -348,6 +363,48 @@ epsm_status epsm_set_tune_table(const epsm_tune_entry *entries, uint32_t count);
  * EPSM_PLAN_HASH_BITS; 8 <= k <= 14, 0 restores the default 11.
  * Process-wide; output never depends on k. */
 epsm_status epsm_set_default_hash_bits(uint32_t k);
+
+/*
+ * Variant table: which variant (and run, prefix width, fingerprint width) a
+ * plan made later uses, by pattern length and alphabet hint.  The paper
+ * fixes the choice by m alone (Section 3: EPSMa/b below 16 bytes, EPSMc
+ * above); which filter is fastest on this device also depends on how often
+ * its candidates survive, i.e. on the alphabet, so the autotuner measures
+ * the variants per (m, sigma) bucket and installs its choices here.  A plan
+ * made without EPSM_PLAN_FORCE_* / EPSM_PLAN_COLLIDE / EPSM_PLAN_DNA takes
+ * the first row, in array order, with m_min <= m <= m_max and sigma_min <=
+ * sigma <= sigma_max, where sigma is its EPSM_PLAN_SIGMA hint (0 when it has
+ * none); with no matching row, the built-in choice (direct below 16, the
+ * fingerprint filter from 16, strided from 263).  The row's flags (any of
+ * EPSM_PLAN_SHORT_RUN, EPSM_PLAN_PREFIX4, EPSM_PLAN_HASH_BITS(k)) are added
+ * to the plan's own; a k of the plan's own wins.  Output never depends on
+ * the table.
+ */
+typedef struct {
+    uint32_t m_min, m_max;          /* pattern lengths, inclusive */
+    uint32_t sigma_min, sigma_max;  /* alphabet hints, inclusive, 0..256 */
+    uint32_t variant;               /* EPSM_VARIANT_DIRECT, _FINGERPRINT (m_min >= 15)
+                                       or _STRIDE (m_min >= 39: the strided filter
+                                       with S the largest power of two <= min(m - 7,
+                                       2048), S >= 32) */
+    uint32_t flags;                 /* EPSM_PLAN_SHORT_RUN | EPSM_PLAN_PREFIX4 |
+                                       EPSM_PLAN_HASH_BITS(k), or 0 */
+} epsm_variant_entry;
+
+/* Install the variant table (copied; at most 256 rows; count == 0 clears it).
+ * EPSM_EINVAL for a bad row (empty range, sigma above 256, unknown variant or
+ * flags, a fingerprint row below m = 15, a strided row below m = 39, k
+ * outside 8..14); the old table is kept on error.  Process-wide; affects
+ * plans made later. */
+epsm_status epsm_set_variant_table(const epsm_variant_entry *entries, uint32_t count);
+
+/* Effective alphabet size of a text, from its first min(n, 65536) bytes:
+ * round(L^2 / sum_c count_c^2), the inverse of the probability that two
+ * sampled bytes are equal (sigma for a uniform text over sigma symbols),
+ * clamped to 1..256; 0 for n == 0.  Runs one kernel on `stream` and
+ * synchronises the stream (the value is returned to the host).  For
+ * EPSM_PLAN_SIGMA. */
+epsm_status epsm_estimate_alphabet(const uint8_t *d_text, uint64_t n, uint32_t *sigma, void *stream);
 
 /*
  * Prepared batches, for callers that run the same batch structure many times

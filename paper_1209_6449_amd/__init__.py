@@ -18,7 +18,8 @@ import torch
 from . import _lib
 from ._lib import (BATCH_COUNT_ONLY, CLASS_BYTES, CLASS_FINGERPRINT, CLASS_WORDS,  # noqa: F401
                    CLASS_DNA, MAX_M, NOALLOC_SCRATCH_BYTES, N_CLASSES, PLAN_COLLIDE, PLAN_DNA,
-                   PLAN_FORCE_DIRECT, PLAN_FORCE_FINGERPRINT, PLAN_NO_STRIDE, PLAN_PREFIX4, VARIANT_DNA, VARIANT_STRIDE,
+                   PLAN_FORCE_DIRECT, PLAN_FORCE_FINGERPRINT, PLAN_NO_STRIDE, PLAN_PREFIX4,
+                   PLAN_SHORT_RUN, PLAN_SIGMA, VARIANT_DNA, VARIANT_STRIDE,
                    PLAN_HASH_BITS, PLAN_HOST_ONLY, VARIANT_DIRECT, VARIANT_FINGERPRINT,
                    WRITE_AUTO, WRITE_SINGLE_PASS, WRITE_TWO_PHASE)
 
@@ -26,7 +27,8 @@ __all__ = ["EpsmError", "Plan", "search", "count", "search_into", "count_into", 
            "stream_check", "lib", "library_path", "Batch", "BatchPlan", "search_batch",
            "set_tile_config", "set_batch_config", "tile_configs", "set_tune_table",
            "set_default_hash_bits", "pack_dna", "search_dna", "count_dna", "search_dna_into",
-           "count_dna_into", "debug_force_giveup", "search_noalloc_into"]
+           "count_dna_into", "debug_force_giveup", "search_noalloc_into", "release",
+           "set_variant_table", "estimate_alphabet"]
 
 
 def lib():
@@ -98,7 +100,7 @@ class Plan:
             "m": inf.m, "variant": inf.variant, "flags": inf.flags, "hash_bits": inf.hash_bits,
             "prefix_words": inf.prefix_words, "words": list(inf.words), "masks": list(inf.masks),
             "table": table, "device": inf.device, "kernel_class": inf.kernel_class, "stride": inf.stride,
-            "prefix_bytes": inf.prefix_bytes,
+            "prefix_bytes": inf.prefix_bytes, "run_blocks": inf.run_blocks, "table_row": inf.table_row,
         }
 
     def close(self) -> None:
@@ -274,6 +276,13 @@ def reserve(max_n: int, batch_bytes: int = 0, stream=None) -> None:
     _check(lib().epsm_reserve(_stream_handle(stream), max_n, batch_bytes), "epsm_reserve")
 
 
+def release() -> None:
+    """epsm_release: free every cached workspace, fault word and staging block
+    (synchronises the device; graphs that captured library calls must not be
+    replayed afterwards)."""
+    lib().epsm_release()
+
+
 def debug_force_giveup(enable: bool) -> None:
     """Test hook epsm_debug_force_giveup (process-wide)."""
     lib().epsm_debug_force_giveup(1 if enable else 0)
@@ -411,6 +420,24 @@ def set_tune_table(entries) -> None:
 def set_default_hash_bits(k: int) -> None:
     """Fingerprint width for plans made later without PLAN_HASH_BITS (0: 11)."""
     _check(lib().epsm_set_default_hash_bits(k), "epsm_set_default_hash_bits")
+
+
+def set_variant_table(entries) -> None:
+    """Install the variant table (epsm_set_variant_table): an iterable of
+    (m_min, m_max, sigma_min, sigma_max, variant, flags); first match wins."""
+    rows = [tuple(int(x) for x in e) for e in entries]
+    arr = (_lib.VariantEntry * max(len(rows), 1))(*[_lib.VariantEntry(*r) for r in rows])
+    _check(lib().epsm_set_variant_table(arr, len(rows)), "epsm_set_variant_table")
+
+
+def estimate_alphabet(text: torch.Tensor, stream=None) -> int:
+    """epsm_estimate_alphabet: effective alphabet size of the text's first
+    64 KiB (synchronises the stream); for PLAN_SIGMA."""
+    _check_text(text)
+    v = ctypes.c_uint32()
+    _check(lib().epsm_estimate_alphabet(text.data_ptr() if text.numel() else None, text.numel(),
+                                        ctypes.byref(v), _stream_handle(stream)), "epsm_estimate_alphabet")
+    return v.value
 
 
 def set_batch_config(waves: int) -> None:

@@ -20,6 +20,12 @@ PLAN_COLLIDE = 0x8
 PLAN_DNA = 0x10
 PLAN_NO_STRIDE = 0x20
 PLAN_PREFIX4 = 0x40
+PLAN_SHORT_RUN = 0x80
+
+
+def PLAN_SIGMA(s: int) -> int:
+    return (s & 0x1FF) << 16
+
 
 
 def PLAN_HASH_BITS(k: int) -> int:
@@ -59,6 +65,8 @@ class PlanInfo(ctypes.Structure):
         ("kernel_class", ctypes.c_uint32),
         ("stride", ctypes.c_uint32),
         ("prefix_bytes", ctypes.c_uint32),
+        ("run_blocks", ctypes.c_uint32),
+        ("table_row", ctypes.c_uint32),
     ]
 
 
@@ -66,6 +74,11 @@ class TuneEntry(ctypes.Structure):
     _fields_ = [("kernel_class", ctypes.c_uint32), ("count_only", ctypes.c_uint32),
                 ("n_max", ctypes.c_uint64), ("waves", ctypes.c_uint32), ("pieces", ctypes.c_uint32),
                 ("strategy", ctypes.c_uint32)]
+
+
+class VariantEntry(ctypes.Structure):
+    _fields_ = [("m_min", ctypes.c_uint32), ("m_max", ctypes.c_uint32), ("sigma_min", ctypes.c_uint32),
+                ("sigma_max", ctypes.c_uint32), ("variant", ctypes.c_uint32), ("flags", ctypes.c_uint32)]
 
 
 class TextRef(ctypes.Structure):
@@ -153,6 +166,9 @@ SIGNATURES = {
                                             ctypes.POINTER(ctypes.c_uint32), ctypes.c_uint32]),
     "epsm_set_tune_table": (ctypes.c_int, [ctypes.POINTER(TuneEntry), ctypes.c_uint32]),
     "epsm_set_default_hash_bits": (ctypes.c_int, [ctypes.c_uint32]),
+    "epsm_set_variant_table": (ctypes.c_int, [ctypes.POINTER(VariantEntry), ctypes.c_uint32]),
+    "epsm_estimate_alphabet": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64,
+                                              ctypes.POINTER(ctypes.c_uint32), ctypes.c_void_p]),
     "epsm_batch_prepare": (ctypes.c_int, [ctypes.POINTER(Batch), ctypes.POINTER(ctypes.c_void_p)]),
     "epsm_batch_launch": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
     "epsm_batch_destroy": (None, [ctypes.c_void_p]),

@@ -1,11 +1,14 @@
 """Autotuner for the scan kernels: picks, per kernel class, mode and text
 length, the fastest built workgroup tile (and, for positions, write
 strategy) whose output is bit-identical to the default's; then the
-fingerprint width k (Section 3.4 uses k = 11) and the batch tile the same way.
+fingerprint width k (Section 3.4 uses k = 11), per (pattern length,
+alphabet) bucket the variant (direct on a two- or three-block register run,
+or the fingerprint filter and its k), and the batch tile the same way.
 
 The result is a JSON cache keyed by the device (architecture and CU count)
 and the library version; apply() installs it through the C ABI
-(epsm_set_tune_table, epsm_set_default_hash_bits, epsm_set_batch_config).
+(epsm_set_tune_table, epsm_set_default_hash_bits, epsm_set_variant_table,
+epsm_set_batch_config).
 Output never depends on the choice: every timed variant is compared with the
 default's output before it may win.
 
@@ -13,7 +16,8 @@ default's output before it may win.
     import paper_1209_6449_amd.autotune as at; at.apply(at.load("tune.json"))
 
 Inputs are seeded and synthetic: uniform random texts over 4 and 64 byte codes
-with patterns cut from them (so every pattern occurs), at several lengths.
+(2, 4, 20 and 64 for the variants) with patterns cut from them (so every
+pattern occurs) and random ones, at several lengths.
 """
 from __future__ import annotations
 
@@ -26,12 +30,13 @@ import time
 
 import torch
 
-from . import (CLASS_BYTES, CLASS_FINGERPRINT, CLASS_WORDS, PLAN_HASH_BITS, PLAN_HOST_ONLY,
+from . import (CLASS_BYTES, CLASS_FINGERPRINT, CLASS_WORDS, PLAN_FORCE_DIRECT, PLAN_FORCE_FINGERPRINT,
+               PLAN_HASH_BITS, PLAN_HOST_ONLY, PLAN_SHORT_RUN, VARIANT_DIRECT, VARIANT_FINGERPRINT,
                WRITE_AUTO, WRITE_SINGLE_PASS, WRITE_TWO_PHASE, Batch, BatchPlan, Plan, count_into, lib,
                search_into, set_batch_config, set_default_hash_bits, set_tile_config,
-               set_tune_table, stream_check, tile_configs)
+               set_tune_table, set_variant_table, stream_check, tile_configs)
 
-CACHE_VERSION = 1
+CACHE_VERSION = 2
 HERE = os.path.dirname(os.path.abspath(__file__))
 PACKAGED_DIR = os.path.join(HERE, "tuned")
 
@@ -40,6 +45,12 @@ CLASS_MS = {CLASS_BYTES: (1, 2, 3), CLASS_WORDS: (4, 8, 15), CLASS_FINGERPRINT: 
 CLASS_NAMES = {CLASS_BYTES: "bytes", CLASS_WORDS: "words", CLASS_FINGERPRINT: "fingerprint"}
 STRATEGY_NAMES = {WRITE_AUTO: "auto", WRITE_SINGLE_PASS: "single", WRITE_TWO_PHASE: "two-phase"}
 SIGMAS = (4, 64)
+# Variant stage: alphabets timed, and the hint range each one stands for
+VARIANT_SIGMAS = ((2, 1, 2), (4, 3, 9), (20, 10, 40), (64, 41, 256))
+# pattern lengths timed, and the m range each one stands for
+VARIANT_MS = ((15, 15, 15), (16, 16, 17), (20, 18, 22), (24, 23, 28), (32, 29, 40), (48, 41, 56),
+              (64, 57, 262))
+VARIANT_KS = (10, 11, 12, 13)
 DEFAULT_SIZES = (1 << 20, 1 << 24, 1 << 28, 1 << 30)
 HASH_BITS = tuple(range(8, 15))
 BATCH_WAVES = (4, 8, 16)
@@ -207,6 +218,79 @@ def tune_hash_bits(rows, n: int = 1 << 28, reps: int = 5, log=print) -> tuple[in
     return best, per
 
 
+def _variant_candidates(m: int, k_default: int):
+    """(name, plan flags used for timing, variant-table (variant, flags)) per
+    candidate variant of length m; the first is the built-in choice."""
+    fp = [(f"fingerprint/k{k}", PLAN_FORCE_FINGERPRINT | PLAN_HASH_BITS(k),
+           (VARIANT_FINGERPRINT, PLAN_HASH_BITS(k))) for k in VARIANT_KS]
+    fp.sort(key=lambda c: c[0] != f"fingerprint/k{k_default}")  # the default k first
+    direct = [("direct", PLAN_FORCE_DIRECT, (VARIANT_DIRECT, 0))]
+    if m > 16:
+        direct.append(("direct/short-run", PLAN_FORCE_DIRECT | PLAN_SHORT_RUN,
+                       (VARIANT_DIRECT, PLAN_SHORT_RUN)))
+    return direct + fp if m < 16 else fp + direct
+
+
+def tune_variants(rows, k_default: int, n: int = 1 << 28, reps: int = 5, log=print) -> tuple[list, dict]:
+    """Per (m, alphabet) bucket: the fastest variant (direct on a two- or
+    three-block run, or the fingerprint filter with k in VARIANT_KS), timed
+    in both modes on a cut and a random pattern with the tuned tiles; every
+    candidate must give the built-in variant's output.  Returns the variant
+    table rows (m_min, m_max, sigma_min, sigma_max, variant, flags) where the
+    winner is not the built-in choice, and the timings."""
+    set_tune_table(rows)
+    set_variant_table([])
+    out_rows, timings = [], {}
+    rel = {}  # (m, candidate) -> [time / best time per alphabet]
+    for sigma, s_lo, s_hi in VARIANT_SIGMAS:
+        text = _text(n, sigma, seed=9100 + sigma)
+        for m, m_lo, m_hi in VARIANT_MS:
+            g = torch.Generator().manual_seed(31 * m + sigma)
+            pats = [_cut(text, m, seed=13 * m + sigma),
+                    bytes(torch.randint(0, sigma, (m,), generator=g, dtype=torch.uint8).tolist())]
+            base = [_Case(text, p) for p in pats]
+            refs = {co: [c.output(co) for c in base] for co in (False, True)}
+            cands = _variant_candidates(m, k_default)
+            per = {}
+            for name, flags, _ in cands:
+                cases = [_Case(text, p, flags) for p in pats]
+                total = 0.0
+                for co in (False, True):
+                    _check_identical(cases, co, refs[co], f"m={m} sigma={sigma} {name}")
+                    total += sum(_time_ms(lambda c=c: c.run(co), reps) for c in cases)
+                per[name] = round(total, 4)
+            # the fastest, unless it beats the built-in choice by less than 3%
+            best = min(per, key=per.get)
+            if per[best] * 1.03 >= per[cands[0][0]]:
+                best = cands[0][0]
+            key = f"m{m}/sigma{sigma}"
+            timings[key] = per
+            lo = min(per.values())
+            for name in per:
+                rel.setdefault((m, name), []).append(per[name] / lo)
+            log(f"[autotune] variant {key}: best {best} ({per[best]:.3f} ms; "
+                + ", ".join(f"{k} {v:.3f}" for k, v in per.items()) + ")")
+            if best != cands[0][0]:
+                variant, vflags = next(c[2] for c in cands if c[0] == best)
+                out_rows.append((m_lo, m_hi, s_lo, s_hi, variant, vflags))
+            del base, cases
+        del text
+        torch.cuda.empty_cache()
+    # no alphabet hint: the candidate with the least summed slowdown over
+    # the alphabets, if it beats the built-in choice's by 3% of a rate
+    for m, m_lo, m_hi in VARIANT_MS:
+        cands = _variant_candidates(m, k_default)
+        score = {name: sum(rel[(m, name)]) for name, _, _ in cands}
+        best = min(score, key=score.get)
+        if best != cands[0][0] and score[best] * 1.03 < score[cands[0][0]]:
+            variant, vflags = next(c[2] for c in cands if c[0] == best)
+            out_rows.append((m_lo, m_hi, 0, 0, variant, vflags))
+            log(f"[autotune] variant m{m}/no hint: {best}")
+    set_tune_table([])
+    stream_check()
+    return out_rows, timings
+
+
 def tune_batch(n_texts: int = 400, max_len: int = 1 << 22, reps: int = 3, log=print) -> tuple[int, dict]:
     """Batch tile (KiB per text tile): least device time of a prepared batch
     (its captured graph replayed) over seeded texts of log-uniform length with
@@ -254,6 +338,7 @@ def tune(sizes=DEFAULT_SIZES, reps: int = 5, batch: bool = True, log=print) -> d
     t0 = time.time()
     rows, tile_t = tune_tiles(sizes, reps, log)
     k, k_t = tune_hash_bits(rows, n=min(max(sizes), 1 << 28), reps=reps, log=log)
+    vrows, v_t = tune_variants(rows, k, n=min(max(sizes), 1 << 28), reps=reps, log=log)
     bw, b_t = tune_batch(log=log) if batch else (BATCH_WAVES[1], {})
     return {
         "version": CACHE_VERSION,
@@ -262,8 +347,9 @@ def tune(sizes=DEFAULT_SIZES, reps: int = 5, batch: bool = True, log=print) -> d
         "tiles_built": [list(t) for t in tile_configs()],
         "table": [list(r) for r in rows],
         "hash_bits": k,
+        "variants": [list(r) for r in vrows],
         "batch_waves": bw,
-        "timings_ms": {"tiles": tile_t, "hash_bits": k_t, "batch_waves": b_t},
+        "timings_ms": {"tiles": tile_t, "hash_bits": k_t, "variants": v_t, "batch_waves": b_t},
         "sizes": list(sizes),
         "seconds": round(time.time() - t0, 1),
     }
@@ -298,15 +384,17 @@ def matches(cache: dict, key: dict | None = None) -> bool:
 
 
 def apply(cache: dict) -> None:
-    """Install a cache's tile table, fingerprint width and batch tile."""
+    """Install a cache's tile table, fingerprint width, variant table and batch tile."""
     set_tune_table([tuple(r) for r in cache.get("table", [])])
     set_default_hash_bits(int(cache.get("hash_bits", 0)))
+    set_variant_table([tuple(r) for r in cache.get("variants", [])])
     set_batch_config(int(cache.get("batch_waves", BATCH_WAVES[1])))
 
 
 def reset() -> None:
     """Back to the built-in defaults."""
     set_tune_table([])
+    set_variant_table([])
     set_default_hash_bits(0)
     set_batch_config(BATCH_WAVES[1])
     set_tile_config(*tile_configs()[0])

@@ -36,7 +36,10 @@ epsm_status hip_fail(hipError_t e, const char *what) {
 constexpr uint32_t kKnownPlanFlags = EPSM_PLAN_HOST_ONLY | EPSM_PLAN_FORCE_DIRECT |
                                      EPSM_PLAN_FORCE_FINGERPRINT | EPSM_PLAN_COLLIDE |
                                      EPSM_PLAN_HASH_BITS(0xF) | EPSM_PLAN_DNA |
-                                     EPSM_PLAN_NO_STRIDE | EPSM_PLAN_PREFIX4;
+                                     EPSM_PLAN_NO_STRIDE | EPSM_PLAN_PREFIX4 |
+                                     EPSM_PLAN_SHORT_RUN | EPSM_PLAN_SIGMA(0x1FF);
+// flags a variant-table row may add to a plan's own
+constexpr uint32_t kVariantRowFlags = EPSM_PLAN_SHORT_RUN | EPSM_PLAN_PREFIX4 | EPSM_PLAN_HASH_BITS(0xF);
 constexpr uint32_t kDefaultHashBits = 11;  // k = 11 in Section 3.4
 
 // Default tile: 8 waves x 16 KiB per wave = 128 KiB per workgroup tile.
@@ -48,6 +51,8 @@ std::vector<epsm_tune_entry> g_tune;
 uint32_t g_default_hash_bits = kDefaultHashBits;
 std::atomic<bool> g_debug_giveup{false};  // epsm_debug_force_giveup
 constexpr uint32_t kMaxTuneEntries = 256;
+std::vector<epsm_variant_entry> g_variants;  // epsm_set_variant_table (under g_tune_mutex)
+constexpr uint32_t kMaxVariantEntries = 256;
 
 uint32_t kernel_class(const DevPlan &d) {
     if (d.variant == EPSM_VARIANT_DNA) return EPSM_CLASS_DNA;
@@ -777,14 +782,32 @@ epsm_status epsm_plan(const uint8_t *pattern, uint64_t m, uint32_t flags, epsm_p
     if (flags & ~kKnownPlanFlags) return fail(EPSM_EINVAL, "unknown plan flags");
     if ((flags & EPSM_PLAN_FORCE_DIRECT) && (flags & EPSM_PLAN_FORCE_FINGERPRINT))
         return fail(EPSM_EINVAL, "FORCE_DIRECT and FORCE_FINGERPRINT are exclusive");
+    const uint32_t sigma = (flags >> 16) & 0x1FFu;  // alphabet hint, 0 = unknown
+    if (sigma > 256) return fail(EPSM_EINVAL, "EPSM_PLAN_SIGMA takes 1..256 (0: unknown)");
+    const bool dna = (flags & EPSM_PLAN_DNA) != 0;
+    const bool forced = flags & (EPSM_PLAN_FORCE_DIRECT | EPSM_PLAN_FORCE_FINGERPRINT | EPSM_PLAN_COLLIDE);
+    // the variant table's row for (m, sigma), if any
+    uint32_t row_variant = 0, row_flags = 0, table_row = 0;
     uint32_t k = (flags >> 8) & 0xF;
-    if (k == 0) {
+    {
         std::lock_guard<std::mutex> lock(g_tune_mutex);
-        k = g_default_hash_bits;
+        if (!dna && !forced) {
+            for (size_t i = 0; i < g_variants.size(); ++i) {
+                const epsm_variant_entry &e = g_variants[i];
+                if (m >= e.m_min && m <= e.m_max && sigma >= e.sigma_min && sigma <= e.sigma_max) {
+                    row_variant = e.variant;
+                    row_flags = e.flags;
+                    table_row = (uint32_t)i + 1;
+                    break;
+                }
+            }
+        }
+        if (k == 0) k = (row_flags >> 8) & 0xF;
+        if (k == 0) k = g_default_hash_bits;
     }
     if (k < 8 || k > 14) return fail(EPSM_EINVAL, "hash bits must be in [8, 14]");
+    const uint32_t eff = flags | (row_flags & (EPSM_PLAN_SHORT_RUN | EPSM_PLAN_PREFIX4));
 
-    const bool dna = (flags & EPSM_PLAN_DNA) != 0;
     if (dna) {
         if (flags & (EPSM_PLAN_FORCE_DIRECT | EPSM_PLAN_FORCE_FINGERPRINT | EPSM_PLAN_COLLIDE |
                      EPSM_PLAN_HASH_BITS(0xF)))
@@ -793,6 +816,8 @@ epsm_status epsm_plan(const uint8_t *pattern, uint64_t m, uint32_t flags, epsm_p
             if (pattern[i] > 3) return fail(EPSM_EINVAL, "DNA pattern codes must be 0..3");
     }
     bool fingerprint = !dna && m >= 16;
+    if (row_variant == EPSM_VARIANT_DIRECT) fingerprint = false;
+    if (row_variant == EPSM_VARIANT_FINGERPRINT || row_variant == EPSM_VARIANT_STRIDE) fingerprint = true;
     if (flags & EPSM_PLAN_FORCE_DIRECT) fingerprint = false;
     if (flags & EPSM_PLAN_FORCE_FINGERPRINT) {
         if (m < 15) return fail(EPSM_EINVAL, "the fingerprint variant needs m >= 15");
@@ -803,6 +828,7 @@ epsm_status epsm_plan(const uint8_t *pattern, uint64_t m, uint32_t flags, epsm_p
     if (!p) return fail(EPSM_ENOMEM, "plan allocation");
     p->pattern.assign(pattern, pattern + m);
     p->flags = flags;
+    p->table_row = table_row;
     DevPlan &d = p->dev;
     d.m = m;
     for (int j = 0; j < 8; ++j) {
@@ -818,7 +844,7 @@ epsm_status epsm_plan(const uint8_t *pattern, uint64_t m, uint32_t flags, epsm_p
     // filter needs bytes 0..23 of the run, verifies 16 bytes from registers
     // and the rest with the tail check, which keeps it at two blocks and
     // fewer VGPRs
-    d.nl = (!fingerprint && m > 16) ? 3 : 2;
+    d.nl = (!fingerprint && m > 16 && !(eff & EPSM_PLAN_SHORT_RUN)) ? 3 : 2;
     const uint32_t nwmax = 4 * d.nl - 4;
     const uint64_t words = (m + 3) / 4;
     d.nw = (uint32_t)std::min<uint64_t>(words, nwmax);
@@ -826,7 +852,7 @@ epsm_status epsm_plan(const uint8_t *pattern, uint64_t m, uint32_t flags, epsm_p
     // the first min(m, 8) bytes (a register run of two blocks holds every
     // window it needs), so m <= 8 needs no verify at all
     d.pk = (uint32_t)std::min<uint64_t>(m, 4);
-    if (!fingerprint && d.nl == 2 && m >= 5 && !(flags & EPSM_PLAN_PREFIX4))
+    if (!fingerprint && d.nl == 2 && m >= 5 && !(eff & EPSM_PLAN_PREFIX4))
         d.pk = (uint32_t)std::min<uint64_t>(m, 8);
     d.collide = (flags & EPSM_PLAN_COLLIDE) ? 1 : 0;
     d.hash_bits = fingerprint ? k : 0;
@@ -886,11 +912,14 @@ epsm_status epsm_plan(const uint8_t *pattern, uint64_t m, uint32_t flags, epsm_p
     }
     // Long patterns: EPSMc with stride S (Section 3.4 inspects one block per
     // stride), S the largest power of two <= min(m - 7, kStrideMax), at least
-    // kStrideMin; the table lists, per hash value, the offsets j in [0, S)
-    // of the pattern blocks p[j..j+7] with that hash, in ascending j.
-    const bool forced = flags & (EPSM_PLAN_FORCE_DIRECT | EPSM_PLAN_FORCE_FINGERPRINT | EPSM_PLAN_COLLIDE);
-    if (fingerprint && !forced && !(flags & EPSM_PLAN_NO_STRIDE) && m >= kStrideMin + 7) {
-        uint32_t S = kStrideMin;
+    // kStrideMin (kStrideMinRow when a variant-table row asks for the strided
+    // filter); the table lists, per hash value, the offsets j in [0, S) of
+    // the pattern blocks p[j..j+7] with that hash, in ascending j.  A table
+    // row of the per-block fingerprint filter keeps the stride off.
+    const uint32_t s_min = row_variant == EPSM_VARIANT_STRIDE ? kStrideMinRow : kStrideMin;
+    if (fingerprint && !forced && !(flags & EPSM_PLAN_NO_STRIDE) && row_variant != EPSM_VARIANT_FINGERPRINT &&
+        m >= s_min + 7) {
+        uint32_t S = s_min;
         while (S * 2 <= kStrideMax && S * 2 + 7 <= m) S *= 2;
         const uint32_t buckets = 1u << kStrideHashBits;
         std::vector<uint32_t> hv(S);
@@ -974,6 +1003,8 @@ epsm_status epsm_plan_get_info(epsm_plan_t plan, epsm_plan_info *info) {
     info->kernel_class = kernel_class(d);
     info->stride = d.stride;
     info->prefix_bytes = d.variant == EPSM_VARIANT_DIRECT ? d.pk : 0;
+    info->run_blocks = d.nl;
+    info->table_row = plan->table_row;
     return EPSM_OK;
 }
 
@@ -1174,6 +1205,52 @@ epsm_status epsm_set_tune_table(const epsm_tune_entry *entries, uint32_t count) 
     return EPSM_OK;
 }
 
+epsm_status epsm_set_variant_table(const epsm_variant_entry *entries, uint32_t count) {
+    g_last_error.clear();
+    if (count > kMaxVariantEntries) return fail(EPSM_EINVAL, "at most 256 variant rows");
+    if (count && !entries) return fail(EPSM_EINVAL, "entries is NULL");
+    std::vector<epsm_variant_entry> rows(entries, entries + count);
+    for (uint32_t i = 0; i < count; ++i) {
+        const epsm_variant_entry &e = rows[i];
+        const std::string at = "variant row " + std::to_string(i) + ": ";
+        if (e.m_min == 0 || e.m_min > e.m_max) return fail(EPSM_EINVAL, at + "empty or zero m range");
+        if (e.sigma_min > e.sigma_max || e.sigma_max > 256) return fail(EPSM_EINVAL, at + "bad sigma range");
+        if (e.variant != EPSM_VARIANT_DIRECT && e.variant != EPSM_VARIANT_FINGERPRINT &&
+            e.variant != EPSM_VARIANT_STRIDE)
+            return fail(EPSM_EINVAL, at + "variant must be direct, fingerprint or strided");
+        if (e.variant == EPSM_VARIANT_FINGERPRINT && e.m_min < 15)
+            return fail(EPSM_EINVAL, at + "the fingerprint filter needs m >= 15");
+        if (e.variant == EPSM_VARIANT_STRIDE && e.m_min < kStrideMinRow + 7)
+            return fail(EPSM_EINVAL, at + "the strided filter needs m >= " + std::to_string(kStrideMinRow + 7));
+        if (e.flags & ~kVariantRowFlags) return fail(EPSM_EINVAL, at + "unknown flags");
+        const uint32_t k = (e.flags >> 8) & 0xF;
+        if (k && (k < 8 || k > 14)) return fail(EPSM_EINVAL, at + "hash bits must be in [8, 14]");
+    }
+    std::lock_guard<std::mutex> lock(g_tune_mutex);
+    g_variants.swap(rows);
+    return EPSM_OK;
+}
+
+epsm_status epsm_estimate_alphabet(const uint8_t *d_text, uint64_t n, uint32_t *sigma, void *stream) {
+    g_last_error.clear();
+    if (!sigma) return fail(EPSM_EINVAL, "sigma is NULL");
+    if (n > 0 && !d_text) return fail(EPSM_EINVAL, "d_text is NULL");
+    *sigma = 0;
+    if (n == 0) return EPSM_OK;
+    hipStream_t s = (hipStream_t)stream;
+    uint8_t *ws = nullptr;
+    epsm_status st = workspace_for(s, 256, &ws);
+    if (st != EPSM_OK) return st;
+    hipError_t e = launch_alphabet(d_text, (uint32_t)std::min<uint64_t>(n, kAlphabetSample), (uint32_t *)ws, s);
+    if (e != hipSuccess) return hip_fail(e, "launch(alphabet)");
+    uint32_t v = 0;
+    e = hipMemcpyAsync(&v, ws, sizeof(v), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(alphabet)");
+    *sigma = v;
+    return EPSM_OK;
+}
+
 epsm_status epsm_set_default_hash_bits(uint32_t k) {
     g_last_error.clear();
     if (k == 0) k = kDefaultHashBits;
@@ -1200,7 +1277,7 @@ epsm_status epsm_reserve(void *stream, uint64_t max_n, uint64_t batch_bytes) {
     const uint64_t wtiles = max_n / dna_wide_tile_symbols() + 2;
     need = std::max<size_t>(need, wtiles * (4 + 8 + dna_wide_waves() * (4 + 4 * dna_wide_slot())) + 1024);
     // strided long-pattern filter: counts, offsets and scan block sums per tile
-    const uint64_t stiles = max_n / (kStrideMin * kStrideBlocksPerTile) + 2;
+    const uint64_t stiles = max_n / (kStrideMinRow * kStrideBlocksPerTile) + 2;
     need = std::max<size_t>(need, stiles * 12 + (stiles / kScanBlock + 2) * 8 + 1024);
     uint8_t *ws = nullptr;
     epsm_status st = workspace_for(s, need, &ws);
@@ -1297,6 +1374,6 @@ const char *epsm_status_string(epsm_status s) {
     return "EPSM_UNKNOWN";
 }
 
-int epsm_version(void) { return 100; }
+int epsm_version(void) { return 110; }
 
 }  // extern "C"

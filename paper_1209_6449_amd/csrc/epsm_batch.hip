@@ -1,9 +1,9 @@
 // Batched search: many (text, pattern) pairs in one stream-ordered submission.
 //
 // Work is cut into units, one unit = one tile of one text.  The unit's
-// workgroup loads the tile once (each lane 16 bytes plus a 32-byte halo) and
-// runs every pattern aimed at that text over it, so a text read from HBM
-// serves all of its patterns.  Output is pair-major: pair k's positions,
+// workgroup loads the tile once (each lane its 16 bytes, the 32-byte halo
+// from its neighbours) and runs every pattern aimed at that text over it, so
+// a text read from HBM serves all of its patterns.  Output is pair-major: pair k's positions,
 // ascending, fill d_out[offsets[k] .. offsets[k] + counts[k]).  That order is
 // produced in three steps: a count pass writes the hits of every
 // (pair, tile) entry, a device exclusive scan turns the entries (in pair
@@ -102,16 +102,13 @@ __global__ __launch_bounds__(WAVES * kWave) void batch_kernel(BatchArgs a) {
     const uint32_t lane_off = (uint32_t)wave * kWavePiece + (uint32_t)lane * kPiece;
     const uint64_t s0 = tile_start + lane_off;
 
-    uint32_t w[kBatchNL * 4 + 1];
-#pragma unroll
-    for (int l = 0; l < kBatchNL; ++l) {
-        const u32x4 v = load16(rsrc, lane_off + l * kPiece);
-        w[4 * l + 0] = v.x;
-        w[4 * l + 1] = v.y;
-        w[4 * l + 2] = v.z;
-        w[4 * l + 3] = v.w;
-    }
-    w[kBatchNL * 4] = 0;
+    // each lane loads its own 16 bytes; the 32 after them come from the next
+    // two lanes (lanes 62 and 63: the next piece's first bytes, one
+    // wave-uniform load), so the tile crosses the cache hierarchy once
+    uint32_t wl[1][kBatchNL * 4 + 1];
+    load_chunk<1, kBatchNL>(wl, rsrc, lane_off);
+    fill_halo<kBatchNL>(wl[0]);
+    uint32_t (&w)[kBatchNL * 4 + 1] = wl[0];
 
     // the count pass filters the solo pairs one by one and the groups
     // together; the write pass redoes, pair by pair, only entries with hits.

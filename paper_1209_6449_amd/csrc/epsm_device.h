@@ -45,30 +45,52 @@ __device__ __forceinline__ uint64_t pattern64(const DevPlan &p, int j) {
 
 // Narrow a wave mask of candidates at lane byte k with pattern words
 // J0..nw-1, two words per compare: one 64-bit v_cmp whose result is the wave
-// mask itself, so a pair costs one scalar AND.  Skips the rest as soon as no
-// lane of the wave has a candidate left.  nw is the template constant NW, or
-// the plan's runtime value when NW == 0.  Every register index is a
-// compile-time constant (a runtime one would move the run to scratch).
-template <int NWMAX, int NW, int J0, int N>
+// mask itself, so a pair costs one scalar AND.  Every pattern word but the
+// last is whole, so only the last one is masked.  nw is the template
+// constant NW, or the plan's runtime value when NW == 0 (then the high word
+// of every pair is masked, since it may be the last).  SKIP: no compare for
+// a start that no lane holds a candidate for (a scalar test and branch per
+// start; without it the compares run unconditionally, which costs vector
+// instructions only where candidates are rare).  LEAN: the form with fewer
+// live registers (differences OR-ed into one test).  Every register index
+// is a compile-time constant (a runtime one would move the run to scratch).
+template <int NWMAX, int NW, int J0, bool SKIP, bool LEAN, int N>
 __device__ __forceinline__ uint64_t verify_words(const uint32_t (&w)[N], int k, uint64_t b,
                                                  const DevPlan &p) {
     const int nw = NW > 0 ? NW : (int)p.nw;
 #pragma unroll
     for (int j = J0; j < NWMAX; j += 2) {
-        if (j < nw && b != 0) {
+        if (j < nw && (!SKIP || b != 0)) {
             if (j + 1 < nw) {
-                // XOR-ed halves, not the raw words: two adjacent words of the
-                // run joined into one 64-bit value become one 64-bit access
-                // to the run, which then no longer fits in registers
-                const uint32_t d0 = (window(w, k + 4 * j) ^ p.pw[j]) & p.pmask[j];
-                const uint32_t d1 = (window(w, k + 4 * j + 4) ^ p.pw[j + 1]) & p.pmask[j + 1];
-                b &= ballot((((uint64_t)d1 << 32) | d0) == 0);
+                const bool whole = NW > 0 && j + 2 < NW;  // the high word is not the last
+                const uint32_t lo = window(w, k + 4 * j), hi = window(w, k + 4 * j + 4);
+                if (LEAN) {
+                    const uint32_t d0 = lo ^ p.pw[j];
+                    const uint32_t d1 = whole ? (hi ^ p.pw[j + 1]) : ((hi ^ p.pw[j + 1]) & p.pmask[j + 1]);
+                    b &= ballot((((uint64_t)d1 << 32) | d0) == 0);
+                } else if (whole && (k & 3) == 0) {
+                    // two adjacent words of the run as they are: joined into
+                    // one 64-bit value they would become one 64-bit access to
+                    // the run, which then no longer fits in registers
+                    b &= ballot(lo == p.pw[j] && hi == p.pw[j + 1]);
+                } else {
+                    const uint32_t h = whole ? hi : (hi & p.pmask[j + 1]);
+                    b &= ballot((((uint64_t)h << 32) | lo) == pattern64(p, j));
+                }
             } else {
                 b &= ballot((window(w, k + 4 * j) & p.pmask[j]) == p.pw[j]);
             }
         }
     }
     return b;
+}
+
+// Occurrences marked in 16 wave masks (wave-uniform: scalar popcounts).
+__device__ __forceinline__ uint32_t masks_count(const uint64_t (&b)[16]) {
+    uint32_t c = 0;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) c += (uint32_t)__builtin_popcountll(b[k]);
+    return c;
 }
 
 // Per-lane 16-bit mask from the 16 wave masks: bit k of lane L is bit L of b[k].
@@ -80,12 +102,6 @@ __device__ __forceinline__ uint32_t lanes_from_masks(const uint64_t (&b)[16]) {
     return lm;
 }
 
-// Direct variant: 16-bit hit mask of one lane piece (positions 0..15).
-// All 16 prefix compares come first and their wave masks are OR-ed once;
-// only a wave with some candidate narrows them with the remaining pattern
-// words and transposes them into per-lane masks.  Keeping the common path
-// free of per-position branches matters: the scalar unit issues one
-// instruction per SIMD every four cycles and was the bottleneck.
 // m = 1: per-lane byte equality without wave masks.  For x = word ^ c*0x01010101
 // a byte is zero iff the byte matches; ((x & 0x7F..) + 0x7F..) sets the high
 // bit of every byte whose low seven bits are not all zero, without carries
@@ -104,19 +120,20 @@ __device__ __forceinline__ uint32_t byte_mask(const uint32_t *w, uint32_t c) {
     return mk;
 }
 
-template <int NL, int PK, int NW>
-__device__ __forceinline__ uint32_t direct_mask(const uint32_t (&w)[NL * 4 + 1], const DevPlan &p) {
-    if constexpr (PK == 1) return byte_mask(w, p.pw[0]);
+// Wave masks of the direct variant (PK >= 2): bit L of b[k] is set iff
+// lane L's start k matches the prefix and the remaining register words.
+// Returns false, with b undefined, when no lane has a hit.
+template <int NL, int PK, int NW, bool SKIP, bool LEAN>
+__device__ __forceinline__ bool direct_wave_masks(const uint32_t (&w)[NL * 4 + 1], const DevPlan &p,
+                                                  uint64_t (&b)[16]) {
+    static_assert(PK >= 2, "m = 1 uses byte_mask");
     constexpr int NWMAX = 4 * NL - 4;
-    uint64_t b[16];
     uint64_t any = 0;
 #pragma unroll
     for (int k = 0; k < 16; ++k) {
         const int q = k >> 2, r = k & 3;
         bool c;
-        if constexpr (PK == 1) {
-            c = ((w[q] >> (8 * r)) & 0xFFu) == p.pw[0];
-        } else if constexpr (PK == 2) {
+        if constexpr (PK == 2) {
             c = (window(w, k) & 0xFFFFu) == p.pw[0];
         } else if constexpr (PK == 8) {
             c = window64(w, k) == pattern64(p, 0);  // m >= 8: no mask
@@ -134,18 +151,34 @@ __device__ __forceinline__ uint32_t direct_mask(const uint32_t (&w)[NL * 4 + 1],
         b[k] = ballot(c);
         any |= b[k];
     }
-    if (any == 0) return 0u;
+    if (any == 0) return false;
     constexpr int J0 = PK >= 7 ? 2 : 1;  // words the prefix compare covers
     if constexpr (PK >= 4 && (NW == 0 || NW > J0)) {
         any = 0;
 #pragma unroll
         for (int k = 0; k < 16; ++k) {
-            if (b[k]) b[k] = verify_words<NWMAX, NW, J0>(w, k, b[k], p);
+            b[k] = verify_words<NWMAX, NW, J0, SKIP, LEAN>(w, k, b[k], p);
             any |= b[k];
         }
-        if (any == 0) return 0u;
+        if (any == 0) return false;
     }
-    return lanes_from_masks(b);
+    return true;
+}
+
+// Direct variant: 16-bit hit mask of one lane piece (positions 0..15).
+// All 16 prefix compares come first and their wave masks are OR-ed once;
+// only a wave with some candidate narrows them with the remaining pattern
+// words and transposes them into per-lane masks.  Keeping the common path
+// free of per-position branches matters: the scalar unit issues one
+// instruction per SIMD every four cycles and was the bottleneck.
+template <int NL, int PK, int NW, bool SKIP = true, bool LEAN = true>
+__device__ __forceinline__ uint32_t direct_mask(const uint32_t (&w)[NL * 4 + 1], const DevPlan &p) {
+    if constexpr (PK == 1) {
+        return byte_mask(w, p.pw[0]);
+    } else {
+        uint64_t b[16];
+        return direct_wave_masks<NL, PK, NW, SKIP, LEAN>(w, p, b) ? lanes_from_masks(b) : 0u;
+    }
 }
 
 // Fingerprint variant: the lane hashes the blocks at its byte 0, 8 and 16
@@ -153,9 +186,11 @@ __device__ __forceinline__ uint32_t direct_mask(const uint32_t (&w)[NL * 4 + 1],
 // marks offset j, so the candidates relative to the lane start are
 // block0: bit 8 -> start 0; block8: bits 1..8 -> starts 1..8;
 // block16: bits 1..7 -> starts 9..15 (bit 8 = start 16 belongs to the next lane).
-template <int NL>
-__device__ __forceinline__ uint32_t fingerprint_mask(const uint32_t (&w)[NL * 4 + 1],
-                                                     const DevPlan &p, const uint16_t *tab) {
+// The candidates are verified as wave masks; returns false when no lane has
+// a hit.
+template <int NL, bool SKIP, bool LEAN>
+__device__ __forceinline__ bool fingerprint_wave_masks(const uint32_t (&w)[NL * 4 + 1], const DevPlan &p,
+                                                       const uint16_t *tab, uint64_t (&b)[16]) {
     constexpr int NWMAX = 4 * NL - 4;
     uint32_t v0 = 0, v1 = 0, v2 = 0;
     if (!p.collide) {
@@ -165,19 +200,23 @@ __device__ __forceinline__ uint32_t fingerprint_mask(const uint32_t (&w)[NL * 4 
     }
     const uint32_t cm = ((uint32_t)tab[v0] >> 8) | (uint32_t)tab[v1] |
                         (((uint32_t)tab[v2] << 8) & 0xFFFFu);
-    if (!wave_any(cm != 0)) return 0u;
-    uint64_t b[16];
+    if (!wave_any(cm != 0)) return false;
     uint64_t any = 0;
 #pragma unroll
     for (int k = 0; k < 16; ++k) {
-        uint64_t bk = ballot((cm >> k) & 1u);
         // a fingerprint plan has m >= 15, so a two-load run (NL = 2) holds
-        // exactly its first four words
-        if (bk) bk = verify_words<NWMAX, NL == 2 ? 4 : 0, 0>(w, k, bk, p);
-        b[k] = bk;
-        any |= bk;
+        // exactly its first four words (only the fourth can be partial)
+        b[k] = verify_words<NWMAX, NL == 2 ? 4 : 0, 0, SKIP, LEAN>(w, k, ballot((cm >> k) & 1u), p);
+        any |= b[k];
     }
-    return any ? lanes_from_masks(b) : 0u;
+    return any != 0;
+}
+
+template <int NL, bool SKIP = true, bool LEAN = true>
+__device__ __forceinline__ uint32_t fingerprint_mask(const uint32_t (&w)[NL * 4 + 1],
+                                                     const DevPlan &p, const uint16_t *tab) {
+    uint64_t b[16];
+    return fingerprint_wave_masks<NL, SKIP, LEAN>(w, p, tab, b) ? lanes_from_masks(b) : 0u;
 }
 
 // Packed DNA (variant 3): coordinates are 2-bit symbols, 16 to a 32-bit
@@ -487,25 +526,50 @@ __device__ __forceinline__ void load_chunk_dna(uint32_t (&w)[U][5], __amdgpu_buf
 }
 
 // Hit masks of the U pieces of one chunk, parked in LDS (two 16-bit masks per
-// word); returns the lane's hit count.
-template <int U, int NL, int VAR, int PK, int NW, int PAIRS, int THREADS>
+// word); returns the lane's hit count.  CNT (count mode, patterns held in
+// registers, no tail check): the wave masks are counted as they are (scalar
+// popcounts, into wave_cnt) instead of being turned into per-lane masks.
+// The direct filter verifies without a branch per start (SKIP false; its
+// 8-byte prefix leaves few waves with candidates unless the text is dense)
+// except in the three-load kernels, which keep the lean form for their
+// registers; the fingerprint filter's candidates are sparse within a wave
+// even on binary text (8/256 of the blocks), so it verifies only the starts
+// that have some.
+template <int U, int NL, int VAR, int PK, int NW, bool CNT, int PAIRS, int THREADS>
 __device__ __forceinline__ uint32_t process_chunk(uint32_t (&w)[U][NL * 4 + 1], int c,
                                                   const ScanArgs &a, const uint16_t *tab,
                                                   uint64_t lane_start, bool edge, bool tail,
-                                                  uint32_t (*s_mask)[THREADS], int tid) {
+                                                  uint32_t (*s_mask)[THREADS], int tid,
+                                                  uint32_t &wave_cnt) {
+    constexpr bool kLean = NL > 2;
     uint32_t cnt = 0, lo = 0;
 #pragma unroll
     for (int u = 0; u < U; ++u) {
         if constexpr (VAR != 3) fill_halo<NL>(w[u]);
-        uint32_t mk;
-        if constexpr (VAR == 1) mk = direct_mask<NL, PK, NW>(w[u], a.plan);
-        else if constexpr (VAR == 2) mk = fingerprint_mask<NL>(w[u], a.plan, tab);
-        else if constexpr (PK == 16) mk = dna_block_mask(w[u], a.plan, tab);
-        else mk = dna_mask<false>(w[u], a.plan);
         const int piece = c * U + u;
         const uint64_t s0 = lane_start + (uint64_t)piece * kWavePiece;
-        // only the first tile holds starts below delta and only the last
-        // one holds starts past `last`
+        if constexpr (CNT) {
+            uint64_t b[16];
+            bool any;
+            if constexpr (VAR == 1) any = direct_wave_masks<NL, PK, NW, kLean, kLean>(w[u], a.plan, b);
+            else any = fingerprint_wave_masks<NL, true, kLean>(w[u], a.plan, tab, b);
+            if (any) {
+                if (edge) {
+                    // only the first tile holds starts below delta and only
+                    // the last one holds starts past `last`
+                    const uint32_t vm = valid_mask(s0, a.delta, a.last);
+#pragma unroll
+                    for (int k = 0; k < 16; ++k) b[k] &= ballot((vm >> k) & 1u);
+                }
+                wave_cnt += masks_count(b);
+            }
+            continue;
+        }
+        uint32_t mk;
+        if constexpr (VAR == 1) mk = direct_mask<NL, PK, NW, kLean, kLean>(w[u], a.plan);
+        else if constexpr (VAR == 2) mk = fingerprint_mask<NL, true, kLean>(w[u], a.plan, tab);
+        else if constexpr (PK == 16) mk = dna_block_mask(w[u], a.plan, tab);
+        else mk = dna_mask<false>(w[u], a.plan);
         if (edge) mk &= valid_mask(s0, a.delta, a.last);
         if (tail && wave_any(mk != 0)) {
             if constexpr (VAR == 3)

@@ -16,6 +16,7 @@ struct epsm_plan_s {
     std::vector<uint32_t> stride_blocks; // strided filter: pattern blocks (lo, hi) per offset
     epsm::DevPlan dev{};          // pointers filled for device plans
     uint32_t flags = 0;
+    uint32_t table_row = 0;       // 1 + the variant-table row that chose the variant, or 0
     int device = -1;
     uint8_t *d_pattern = nullptr;  // device block: pattern, then table
 };

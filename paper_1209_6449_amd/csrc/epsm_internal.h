@@ -98,7 +98,9 @@ constexpr int kStrideWaves = 8;
 constexpr int kStrideThreads = kStrideWaves * kWave;
 constexpr uint32_t kStrideBlocksPerLane = 4;
 constexpr uint64_t kStrideBlocksPerTile = (uint64_t)kStrideThreads * kStrideBlocksPerLane;
-constexpr uint32_t kStrideMin = 256, kStrideMax = 2048;  // S: powers of two, S <= m - 7
+// S: powers of two, S <= m - 7; at least kStrideMin unless a variant-table
+// row asks for the strided filter, then at least kStrideMinRow
+constexpr uint32_t kStrideMin = 256, kStrideMax = 2048, kStrideMinRow = 32;
 constexpr uint32_t kStrideHashBits = 12;
 // Packed DNA, m >= 16: buckets of the 8-symbol block filter (2^k u16 entries
 // in LDS, as the byte fingerprint table).
@@ -216,6 +218,9 @@ hipError_t launch_set_u64(uint64_t *p, uint64_t value, hipStream_t s);
 // 2-bit packing of n symbol codes (low two bits of each byte) into
 // ceil(n/4) bytes, symbol i at bits 2*(i%4) of byte i/4.
 hipError_t launch_pack_dna(const uint8_t *codes, uint64_t n, uint8_t *packed, hipStream_t s);
+// *out = the effective alphabet size of text[0, len) (one workgroup; len >= 1).
+constexpr uint32_t kAlphabetSample = 65536;  // bytes epsm_estimate_alphabet samples
+hipError_t launch_alphabet(const uint8_t *text, uint32_t len, uint32_t *out, hipStream_t s);
 // *out = sum of tcnt[0 .. tiles) (one workgroup).
 hipError_t launch_sum_tiles(const uint32_t *tcnt, uint32_t tiles, uint64_t *out, hipStream_t s);
 // Packed DNA, m >= 16, wide lanes (a.num_tiles tiles of

@@ -424,6 +424,34 @@ hipError_t launch_pack_dna(const uint8_t *codes, uint64_t n, uint8_t *packed, hi
     return hipGetLastError();
 }
 
+// Effective alphabet of text[0, len): one workgroup histograms the bytes in
+// LDS, then *out = round(len^2 / sum_c count_c^2), clamped to 1..256.
+__global__ __launch_bounds__(256) void alphabet_kernel(const uint8_t *text, uint32_t len, uint32_t *out) {
+    __shared__ uint32_t hist[256];
+    __shared__ uint64_t part[4];
+    const int tid = threadIdx.x;
+    hist[tid] = 0;
+    __syncthreads();
+    for (uint32_t i = tid; i < len; i += 256) atomicAdd(&hist[text[i]], 1u);
+    __syncthreads();
+    const uint64_t c = hist[tid];
+    uint64_t sq = c * c;
+    for (int off = 32; off > 0; off >>= 1) sq += __shfl_xor(sq, off);
+    if ((tid & 63) == 0) part[tid >> 6] = sq;
+    __syncthreads();
+    if (tid == 0) {
+        const uint64_t sum = part[0] + part[1] + part[2] + part[3];
+        const uint64_t l2 = (uint64_t)len * len;
+        uint64_t v = (l2 + sum / 2) / sum;
+        *out = (uint32_t)(v < 1 ? 1 : (v > 256 ? 256 : v));
+    }
+}
+
+hipError_t launch_alphabet(const uint8_t *text, uint32_t len, uint32_t *out, hipStream_t s) {
+    hipLaunchKernelGGL(alphabet_kernel, dim3(1), dim3(256), 0, s, text, len, out);
+    return hipGetLastError();
+}
+
 __global__ void set_u64_kernel(uint64_t *p, uint64_t value) {
     if (blockIdx.x == 0 && threadIdx.x == 0) *p = value;
 }
@@ -446,13 +474,13 @@ hipError_t launch_set_u64(uint64_t *p, uint64_t value, hipStream_t s) {
 // workgroups fit on a CU.
 static const TileConfig kBuiltTiles[] = {{8, 16}, {8, 8}, {4, 16}, {4, 32}, {16, 8}, {16, 16}};
 
-static ScanFn pick_fn(TileConfig cfg, const DevPlan &p) {
-    if (cfg.waves == 8 && cfg.pieces == 16) return scan_fn_8x16(p);
-    if (cfg.waves == 8 && cfg.pieces == 8) return scan_fn_8x8(p);
-    if (cfg.waves == 4 && cfg.pieces == 16) return scan_fn_4x16(p);
-    if (cfg.waves == 4 && cfg.pieces == 32) return scan_fn_4x32(p);
-    if (cfg.waves == 16 && cfg.pieces == 8) return scan_fn_16x8(p);
-    if (cfg.waves == 16 && cfg.pieces == 16) return scan_fn_16x16(p);
+static ScanFn pick_fn(TileConfig cfg, const DevPlan &p, bool count_only = false) {
+    if (cfg.waves == 8 && cfg.pieces == 16) return scan_fn_8x16(p, count_only);
+    if (cfg.waves == 8 && cfg.pieces == 8) return scan_fn_8x8(p, count_only);
+    if (cfg.waves == 4 && cfg.pieces == 16) return scan_fn_4x16(p, count_only);
+    if (cfg.waves == 4 && cfg.pieces == 32) return scan_fn_4x32(p, count_only);
+    if (cfg.waves == 16 && cfg.pieces == 8) return scan_fn_16x8(p, count_only);
+    if (cfg.waves == 16 && cfg.pieces == 16) return scan_fn_16x16(p, count_only);
     return nullptr;
 }
 
@@ -501,7 +529,7 @@ hipError_t launch_expand(ScanArgs a, TileConfig cfg, hipStream_t s) {
 }
 
 hipError_t launch_scan(const ScanArgs &a, TileConfig cfg, int grid, hipStream_t s) {
-    ScanFn fn = pick_fn(cfg, a.plan);
+    ScanFn fn = pick_fn(cfg, a.plan, a.write == kWriteNone);
     if (!fn) return hipErrorInvalidValue;
     hipLaunchKernelGGL(fn, dim3(grid), dim3(cfg.waves * kWave), table_bytes(a.plan), s, a);
     return hipGetLastError();

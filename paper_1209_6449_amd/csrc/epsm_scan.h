@@ -117,7 +117,9 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t tile_rsrc(const ScanArgs &a, u
 // loads need.  The three-load direct kernel keeps its registers.  Tiles
 // whose LDS admits fewer waves (4x32, 16x8, 16x16) do not reach the target;
 // their register use is left as it is.
-template <int WAVES, int U, int C, int NL, int VAR, int PK, int NW>
+// CNT: the count-mode kernel of a plan held in registers (no tail check),
+// which counts the filter's wave masks without per-lane masks.
+template <int WAVES, int U, int C, int NL, int VAR, int PK, int NW, bool CNT>
 __global__ __launch_bounds__(WAVES * kWave)
 __attribute__((amdgpu_waves_per_eu(NL > 2 ? 4 : 6)))
 void scan_kernel(ScanArgs a) {
@@ -161,7 +163,7 @@ void scan_kernel(ScanArgs a) {
     // the loop body is two ping-pong rounds (four chunks), unrolled: with a
     // body of one round the register allocator kept 16 more bytes live in
     // the fingerprint and long-verify kernels and spilled them at 80 VGPRs
-    uint32_t cnt = 0;
+    uint32_t cnt = 0, wave_cnt = 0;  // per-lane hits; hits counted per wave (CNT)
     constexpr int kStep = C >= 4 ? 4 : 2;
     static_assert(C % kStep == 0, "whole loop bodies per tile");
 #pragma unroll 1
@@ -169,21 +171,21 @@ void scan_kernel(ScanArgs a) {
 #pragma unroll
         for (int c = c0; c < c0 + kStep; c += 2) {
             load(wb, lane_off + (uint32_t)(c + 1) * U * kWavePiece);
-            cnt += process_chunk<U, NL, VAR, PK, NW, kPieces / 2, kThreads>(
-                wa, c, a, s_table, lane_start, edge, tail, s_mask, tid);
+            cnt += process_chunk<U, NL, VAR, PK, NW, CNT, kPieces / 2, kThreads>(
+                wa, c, a, s_table, lane_start, edge, tail, s_mask, tid, wave_cnt);
             if (c + 2 < C) load(wa, lane_off + (uint32_t)(c + 2) * U * kWavePiece);
-            cnt += process_chunk<U, NL, VAR, PK, NW, kPieces / 2, kThreads>(
-                wb, c + 1, a, s_table, lane_start, edge, tail, s_mask, tid);
+            cnt += process_chunk<U, NL, VAR, PK, NW, CNT, kPieces / 2, kThreads>(
+                wb, c + 1, a, s_table, lane_start, edge, tail, s_mask, tid, wave_cnt);
         }
     }
-    const uint32_t wtot = wave_sum32(cnt);
+    const uint32_t wtot = CNT ? wave_cnt : wave_sum32(cnt);
     if (lane == 0) s_wcnt[wave] = wtot;
     __syncthreads();
     uint64_t tile_cnt = 0;
 #pragma unroll
     for (int i = 0; i < WAVES; ++i) tile_cnt += s_wcnt[i];
 
-    if (a.write == kWriteNone) {
+    if (CNT || a.write == kWriteNone) {
         // count only: a plain store per tile, summed by one more kernel
         if (tid == 0) a.tcnt[tile] = (uint32_t)tile_cnt;
         return;
@@ -342,41 +344,52 @@ typedef void (*ScanFn)(ScanArgs);
 
 // Chunks of 2 pieces (two or three dwordx4 loads per piece and lane, two
 // chunks in flight) keep the kernels within about 100 VGPRs.
-template <int WAVES, int PIECES>
-static ScanFn pick(const DevPlan &p) {
-    if (p.variant == 3)
-        return p.pk == 16 ? scan_kernel<WAVES, 2, PIECES / 2, 1, 3, 16, 0>
-                          : scan_kernel<WAVES, 2, PIECES / 2, 1, 3, 4, 0>;
-    if (p.variant == 2) return scan_kernel<WAVES, 2, PIECES / 2, 2, 2, 4, 0>;
-    if (p.nl == 3) return scan_kernel<WAVES, 2, PIECES / 2, 3, 1, 4, 0>;
+template <int WAVES, int PIECES, bool CNT>
+static ScanFn pick_direct(const DevPlan &p) {
+    constexpr int C = PIECES / 2;
     switch (p.pk) {
-        case 1: return scan_kernel<WAVES, 2, PIECES / 2, 2, 1, 1, 1>;
-        case 2: return scan_kernel<WAVES, 2, PIECES / 2, 2, 1, 2, 1>;
-        case 3: return scan_kernel<WAVES, 2, PIECES / 2, 2, 1, 3, 1>;
+        case 2: return scan_kernel<WAVES, 2, C, 2, 1, 2, 1, CNT>;
+        case 3: return scan_kernel<WAVES, 2, C, 2, 1, 3, 1, CNT>;
         case 5:
         case 6:
-        case 7: return scan_kernel<WAVES, 2, PIECES / 2, 2, 1, 7, 2>;
+        case 7: return scan_kernel<WAVES, 2, C, 2, 1, 7, 2, CNT>;
         case 8:
             switch (p.nw) {
-                case 2: return scan_kernel<WAVES, 2, PIECES / 2, 2, 1, 8, 2>;
-                case 3: return scan_kernel<WAVES, 2, PIECES / 2, 2, 1, 8, 3>;
-                default: return scan_kernel<WAVES, 2, PIECES / 2, 2, 1, 8, 4>;
+                case 2: return scan_kernel<WAVES, 2, C, 2, 1, 8, 2, CNT>;
+                case 3: return scan_kernel<WAVES, 2, C, 2, 1, 8, 3, CNT>;
+                default: return scan_kernel<WAVES, 2, C, 2, 1, 8, 4, CNT>;
             }
         default: break;
     }
     switch (p.nw) {
-        case 1: return scan_kernel<WAVES, 2, PIECES / 2, 2, 1, 4, 1>;
-        case 2: return scan_kernel<WAVES, 2, PIECES / 2, 2, 1, 4, 2>;
-        case 3: return scan_kernel<WAVES, 2, PIECES / 2, 2, 1, 4, 3>;
-        default: return scan_kernel<WAVES, 2, PIECES / 2, 2, 1, 4, 4>;
+        case 1: return scan_kernel<WAVES, 2, C, 2, 1, 4, 1, CNT>;
+        case 2: return scan_kernel<WAVES, 2, C, 2, 1, 4, 2, CNT>;
+        case 3: return scan_kernel<WAVES, 2, C, 2, 1, 4, 3, CNT>;
+        default: return scan_kernel<WAVES, 2, C, 2, 1, 4, 4, CNT>;
     }
+}
+
+// Kernel of a plan; count_only selects the counting kernels where the
+// pattern is held in registers (m <= 4 * nw: no tail check).
+template <int WAVES, int PIECES>
+static ScanFn pick(const DevPlan &p, bool count_only) {
+    constexpr int C = PIECES / 2;
+    if (p.variant == 3)
+        return p.pk == 16 ? scan_kernel<WAVES, 2, C, 1, 3, 16, 0, false>
+                          : scan_kernel<WAVES, 2, C, 1, 3, 4, 0, false>;
+    const bool cnt = count_only && p.nl == 2 && p.m <= 4ull * p.nw;
+    if (p.variant == 2)
+        return cnt ? scan_kernel<WAVES, 2, C, 2, 2, 4, 0, true> : scan_kernel<WAVES, 2, C, 2, 2, 4, 0, false>;
+    if (p.nl == 3) return scan_kernel<WAVES, 2, C, 3, 1, 4, 0, false>;
+    if (p.pk == 1) return scan_kernel<WAVES, 2, C, 2, 1, 1, 1, false>;
+    return cnt ? pick_direct<WAVES, PIECES, true>(p) : pick_direct<WAVES, PIECES, false>(p);
 }
 
 typedef void (*ExpandFn)(ScanArgs);
 
 // Scan kernel of a plan and expand kernel, per built tile configuration.
 #define EPSM_TILE_FNS(W, P)                              \
-    ScanFn scan_fn_##W##x##P(const DevPlan &p);          \
+    ScanFn scan_fn_##W##x##P(const DevPlan &p, bool count_only); \
     ExpandFn expand_fn_##W##x##P();
 EPSM_TILE_FNS(8, 16)
 EPSM_TILE_FNS(8, 8)
@@ -390,7 +403,9 @@ EPSM_TILE_FNS(16, 16)
 // and the expand kernel of one tile configuration.
 #define EPSM_TILE_TU(W, P)                                                     \
     namespace epsm {                                                           \
-    ScanFn scan_fn_##W##x##P(const DevPlan &p) { return pick<W, P>(p); }       \
+    ScanFn scan_fn_##W##x##P(const DevPlan &p, bool count_only) {              \
+        return pick<W, P>(p, count_only);                                      \
+    }                                                                          \
     ExpandFn expand_fn_##W##x##P() { return expand_kernel<W, P>; }             \
     }
 

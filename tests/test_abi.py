@@ -110,7 +110,8 @@ def test_force_flags():
     (b"", 0),                                                        # m == 0
     (b"abc", epsm.PLAN_FORCE_FINGERPRINT),                           # needs m >= 15
     (b"abc", epsm.PLAN_FORCE_DIRECT | epsm.PLAN_FORCE_FINGERPRINT),  # exclusive
-    (b"abc", 0x10000),                                               # unknown flag
+    (b"abc", 0x2000000),                                             # unknown flag
+    (b"abc", epsm.PLAN_SIGMA(300)),                                  # alphabet hint above 256
     (b"a" * 20, epsm.PLAN_HASH_BITS(5)),                             # k out of range
 ])
 def test_plan_rejects_bad_arguments(pattern, flags):
@@ -360,3 +361,76 @@ def test_long_pattern_variant_and_stride(m, flags, variant, stride):
     assert info["variant"] == variant and info["stride"] == stride
     if variant == epsm.VARIANT_STRIDE:
         assert info["kernel_class"] == epsm.CLASS_FINGERPRINT and info["table"] is not None
+
+
+def test_variant_table_chooses_the_plan_variant():
+    """Rows are matched by m and the alphabet hint, first match wins; a plan
+    without a hint matches only rows whose sigma range holds 0."""
+    V = epsm
+    try:
+        V.set_variant_table([
+            (17, 32, 1, 2, V.VARIANT_DIRECT, V.PLAN_SHORT_RUN),
+            (16, 16, 1, 4, V.VARIANT_DIRECT, 0),
+            (15, 15, 0, 256, V.VARIANT_FINGERPRINT, V.PLAN_HASH_BITS(13)),
+            (16, 600, 0, 256, V.VARIANT_FINGERPRINT, 0),
+        ])
+        short = host_plan(b"ab" * 10, V.PLAN_SIGMA(2))
+        assert (short["variant"], short["run_blocks"], short["prefix_bytes"], short["table_row"]) == \
+            (V.VARIANT_DIRECT, 2, 8, 1)
+        assert host_plan(b"ab" * 10, V.PLAN_SIGMA(2) | V.PLAN_PREFIX4)["prefix_bytes"] == 4
+        d16 = host_plan(b"x" * 16, V.PLAN_SIGMA(4))
+        assert (d16["variant"], d16["run_blocks"], d16["table_row"]) == (V.VARIANT_DIRECT, 2, 2)
+        f15 = host_plan(b"x" * 15)
+        assert (f15["variant"], f15["hash_bits"], f15["table_row"]) == (V.VARIANT_FINGERPRINT, 13, 3)
+        assert host_plan(b"x" * 15, V.PLAN_HASH_BITS(9))["hash_bits"] == 9  # the plan's own k wins
+        # no hint: the sigma 1..2 row does not match, the generic one does
+        g = host_plan(b"ab" * 10)
+        assert (g["variant"], g["table_row"]) == (V.VARIANT_FINGERPRINT, 4)
+        # a per-block fingerprint row keeps the stride off
+        long = host_plan(bytes(range(256)) * 2)
+        assert (long["variant"], long["stride"], long["table_row"]) == (V.VARIANT_FINGERPRINT, 0, 4)
+        # forced plans ignore the table
+        assert host_plan(b"ab" * 10, V.PLAN_SIGMA(2) | V.PLAN_FORCE_FINGERPRINT)["table_row"] == 0
+        # outside every row: the built-in choice
+        b = host_plan(b"x" * 40, V.PLAN_SIGMA(2))
+        assert (b["variant"], b["run_blocks"], b["table_row"]) == (V.VARIANT_FINGERPRINT, 2, 4)
+        assert host_plan(b"x" * 12, V.PLAN_SIGMA(2))["table_row"] == 0
+    finally:
+        V.set_variant_table([])
+    assert host_plan(b"ab" * 10, V.PLAN_SIGMA(2))["table_row"] == 0
+    assert host_plan(b"ab" * 10, V.PLAN_SIGMA(2))["variant"] == V.VARIANT_FINGERPRINT
+    assert host_plan(bytes(range(256)) * 2)["variant"] == V.VARIANT_STRIDE
+
+
+@pytest.mark.parametrize("row", [
+    (0, 10, 0, 256, 1, 0),               # m_min 0
+    (10, 9, 0, 256, 1, 0),               # empty m range
+    (16, 32, 5, 4, 1, 0),                # empty sigma range
+    (16, 32, 0, 300, 1, 0),              # sigma above 256
+    (16, 32, 0, 256, 3, 0),              # DNA is not a table variant
+    (14, 32, 0, 256, 2, 0),              # fingerprint below 15
+    (30, 400, 0, 256, 4, 0),             # strided below 39
+    (16, 32, 0, 256, 1, 0x1),            # a flag rows may not add
+    (16, 32, 0, 256, 2, 0x500),          # k = 5
+])
+def test_variant_table_rejects_bad_rows(row):
+    epsm.set_variant_table([(20, 20, 0, 256, epsm.VARIANT_DIRECT, 0)])
+    try:
+        with pytest.raises(epsm.EpsmError) as e:
+            epsm.set_variant_table([row])
+        assert e.value.status == _lib.EPSM_EINVAL and e.value.detail
+        assert host_plan(b"y" * 20)["table_row"] == 1  # the old table is kept
+    finally:
+        epsm.set_variant_table([])
+
+
+@pytest.mark.parametrize("m,S", [(39, 32), (71, 64), (72, 64), (135, 128), (262, 128), (263, 256), (600, 512)])
+def test_stride_rows_below_263(m, S):
+    epsm.set_variant_table([(39, 4096, 0, 256, epsm.VARIANT_STRIDE, 0)])
+    try:
+        info = host_plan((bytes(range(256)) * 3)[:m])
+        assert (info["variant"], info["stride"], info["table_row"]) == (epsm.VARIANT_STRIDE, S, 1)
+    finally:
+        epsm.set_variant_table([])
+    info = host_plan((bytes(range(256)) * 3)[:m])
+    assert info["variant"] == (epsm.VARIANT_STRIDE if m >= 263 else epsm.VARIANT_FINGERPRINT)

@@ -389,3 +389,37 @@ def test_strided_filter_periodic_text(epsm, m):
         assert torch.equal(out[:cap].cpu(), torch.arange(cap, dtype=torch.int64))
         assert bool((out[cap:] == -3).all())
     epsm.stream_check()
+
+
+@pytest.mark.parametrize("m", [39, 40, 71, 72, 135, 136, 200, 262])
+def test_small_stride_rows_match_oracle(epsm, m):
+    """A variant-table row asking for the strided filter below m = 263
+    (S = 32, 64, 128 between inspected blocks): planted copies at the ends,
+    near block boundaries and overlapping, sparse and binary texts,
+    unaligned starts; and a^n with a^m (closed form)."""
+    epsm.set_variant_table([(39, 262, 0, 256, epsm.VARIANT_STRIDE, 0)])
+    try:
+        rng = np.random.default_rng(1000 + m)
+        for sigma in (2, 4, 64):
+            pattern = rng.integers(0, sigma, m).astype(np.uint8).tobytes()
+            plan = epsm.Plan(pattern)
+            info = plan.info()
+            S = 1 << (m - 7).bit_length() - 1
+            assert (info["variant"], info["stride"]) == (epsm.VARIANT_STRIDE, min(S, 2048))
+            for n in (m, 3 * m + 17, 100_000 + m):
+                spots = [0, n - m, n // 2, n // 2 + 1, (n // 3) & ~31, ((n // 3) & ~31) - 1]
+                text = planted_text(rng, n, sigma, pattern, spots)
+                for offset in (0, 7):
+                    say(f"small stride m={m} S={info['stride']} sigma={sigma} n={n} offset={offset}")
+                    t = to_gpu(text, offset)
+                    got = epsm.search(t, plan).cpu().numpy()
+                    exp = oracle.positions(text, pattern)
+                    assert np.array_equal(got, exp), (m, sigma, n, offset, got[:5], exp[:5])
+                    assert epsm.count(t, plan) == exp.size
+        n = 50_000 + 3
+        t = torch.full((n,), ord("a"), dtype=torch.uint8, device="cuda")
+        got = epsm.search(t, epsm.Plan(b"a" * m))
+        assert torch.equal(got, torch.arange(n - m + 1, dtype=torch.int64, device="cuda"))
+        epsm.stream_check()
+    finally:
+        epsm.set_variant_table([])

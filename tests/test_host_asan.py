@@ -30,7 +30,7 @@ for m in list(range(1, 40)) + [64, 100, 262, 263, 300, 519, 1031, 2055, 4096]:
             epsm.Plan(p, epsm.PLAN_FORCE_FINGERPRINT | epsm.PLAN_COLLIDE | H).info()
         codes = rng.integers(0, 4, m).astype(np.uint8).tobytes()
         epsm.Plan(codes, epsm.PLAN_DNA | H).info()
-for bad, flags in ((b"", 0), (b"a" * 4097, 0), (b"\x05", epsm.PLAN_DNA), (b"ab", 0x100000)):
+for bad, flags in ((b"", 0), (b"a" * 4097, 0), (b"\x05", epsm.PLAN_DNA), (b"ab", 0x2000000)):
     try:
         epsm.Plan(bad, flags | H)
         raise SystemExit("expected an error")
