@@ -6,14 +6,17 @@
 Prints ONE JSON line.  Workloads (all synthetic, seeded, generated on the GPU
 by the workloads module; texts are resident in HBM before timing starts):
 
-  sweep1g  (default) 1 GiB texts uniform over sigma in {2,4,20,64,128} codes;
-           per sigma and m in {1,2,4,8,12,16,24,32} one pattern cut from the
-           text and one random; every pattern searched in positions mode and
-           in count mode.  One step = the whole sweep (160 searches, 160 GiB
-           of logical text).
-  zipf4g   4 GiB Zipf(1) English-like text, cut patterns m = 1..16, positions
-           and count modes; plus the periodic text a^n with a^m (dense
-           output, 8 bytes written per byte read at m = 1).
+  zipf4g   (default) 4 GiB Zipf(1) English-like text, cut patterns m = 1..16,
+           positions and count modes; plus the periodic text a^n with a^m
+           (dense output, 8 bytes written per byte read at m = 1).  One step =
+           the 64 searches (256 GiB of logical text).  The default run then
+           adds the batch and serving legs below as the "batch" and "serve"
+           objects of the same line (--scan-only leaves them out).
+  sweep1g  1 GiB texts uniform over sigma in {2,4,20,64,128} codes; per sigma
+           and m in {1,2,4,8,12,16,24,32} one pattern cut from the text and
+           one random; every pattern searched in positions mode and in count
+           mode.  One step = the whole sweep (160 searches, 160 GiB of
+           logical text).
   serve    256 resident texts (sigma 20, log-uniform lengths in [1, 256] MiB);
            Poisson query streams (text id + 1..256 patterns, m in [2, 32])
            served with continuous batching: saturation throughput from a
@@ -43,6 +46,9 @@ sys.path.insert(0, ROOT)
 
 METRIC = "text GB/s scanned & fraction of HBM peak, batched vs plain; p99 query latency"
 HBM_PEAK_GBS = 8000.0
+# vector ALU int32 peak: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
+VALU_INT32_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+ALU_OPS_PER_PAIR_BYTE = 2
 
 
 def log(msg: str) -> None:
@@ -54,7 +60,9 @@ def parse_args():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="sweep1g", choices=["sweep1g", "zipf4g", "batch", "serve", "dna", "long"])
+    ap.add_argument("--workload", default="zipf4g", choices=["sweep1g", "zipf4g", "batch", "serve", "dna", "long"])
+    ap.add_argument("--scan-only", action="store_true",
+                    help="zipf4g: leave out the batch and serving legs of the default run")
     ap.add_argument("--serve-queries", type=int, default=1000, help="queries per serving run")
     ap.add_argument("--batch-texts", type=int, default=10_000, help="texts in the batch workload")
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
@@ -197,7 +205,8 @@ def run_dna_workload(args, torch, W, epsm):
 def run_long_workload(args, torch, W, epsm):
     """Long patterns on a 4 GiB Zipf text: the strided filter (one 8-byte
     block per S bytes, S = 256..2048) against the per-block filter, with cut
-    patterns of m in {263, 300, 519, 1031, 2055, 4096}."""
+    patterns of m in {263, 300, 519, 1031, 2055, 4096}; and, with S = 32, 64,
+    128 (a variant-table row), m in {40, 72, 136}."""
     spec, _, _, _ = W.config3()
     n = spec.n
     log("generating the 4 GiB Zipf text on the GPU")
@@ -208,6 +217,15 @@ def run_long_workload(args, torch, W, epsm):
     for m in (263, 300, 519, 1031, 2055, 4096):
         p, _ = W.cut_pattern(spec, m, g)
         cases.append((p, epsm.Plan(p), epsm.Plan(p, epsm.PLAN_NO_STRIDE)))
+    # shorter patterns with the strided filter asked for by a variant-table
+    # row (S = 32, 64, 128): whether skipping inside cache lines saves bytes
+    g = W.rng(7, 2)
+    for m in (40, 72, 136):
+        p, _ = W.cut_pattern(spec, m, g)
+        epsm.set_variant_table([(39, 262, 0, 256, epsm.VARIANT_STRIDE, 0)])
+        ps = epsm.Plan(p)
+        epsm.set_variant_table([])
+        cases.append((p, ps, epsm.Plan(p, epsm.PLAN_NO_STRIDE)))
     hits = torch.zeros(1, dtype=torch.int64, device="cuda")
     counts = []
     for p, ps, pb in cases:
@@ -253,8 +271,9 @@ def run_long_workload(args, torch, W, epsm):
         if args.detail:
             log(f"long m={len(p):4d} S={stride:4d} hits={c:3d} strided: positions {pm:7.3f} ms count {cm:7.3f} ms "
                 f"({n / cm / 1e6:8.1f} GB/s of text) | per-block count {bm:7.3f} ms ({n / bm / 1e6:7.1f} GB/s)")
-    config = {"workload": "long: 4 GiB Zipf(1) 96-symbol text, cut patterns m in {263,300,519,1031,2055,4096}; "
-                          "strided filter; positions+count modes",
+    config = {"workload": "long: 4 GiB Zipf(1) 96-symbol text, cut patterns m in {263,300,519,1031,2055,4096} "
+                          "and, with S = 32/64/128 from a variant-table row, m in {40,72,136}; strided filter; "
+                          "positions+count modes",
               "text_bytes": n, "searches_per_step": 2 * len(cases)}
     return n * 2 * len(cases) * args.steps / elapsed, elapsed / args.steps, config, detail, pos_ms_total
 
@@ -339,10 +358,30 @@ def run_batch_workload(args, torch, W, epsm):
               "texts": len(bts), "pairs": len(pairs_host), "text_bytes": text_bytes,
               "logical_bytes": logical, "positions": total, "batch_units": info["units"],
               "batch_entries": info["entries"], "batch_tile_bytes": info["tile_bytes"]}
+    # roofline of the replay: ALU-bound (each text byte is compared with
+    # every pattern of its text).  Algorithmic work: ALU_OPS_PER_PAIR_BYTE
+    # int32 operations per (pattern, text position) pair (cut the window,
+    # compare it; the ballot is free), against the vector ALUs' int32 peak.
+    # The HBM bytes the replay must move (text read by the count and write
+    # passes, 8 bytes per position written) are reported beside it.
+    alg_ops = ALU_OPS_PER_PAIR_BYTE * logical
+    achieved = alg_ops / (batched_gpu_ms / 1e3) / 1e12
+    hbm_bytes = 2 * text_bytes + 8 * total
+    traffic = load_traffic("batch")
+    roofline = {"bound": "alu", "achieved": round(achieved, 2), "peak": VALU_INT32_PEAK_TOPS,
+                "unit": "Top/s", "frac": round(achieved / VALU_INT32_PEAK_TOPS, 4),
+                "traffic": traffic["bytes_per_launch"] if traffic else None,
+                "kernel": "batch replay (count pass, scan of the (pair, tile) counts, finalize, write pass), "
+                          "event-timed per replay",
+                "alg_ops_per_launch": alg_ops, "avg_launch_ms": round(batched_gpu_ms, 4),
+                "hbm": {"bytes_per_launch": hbm_bytes,
+                        "gbs": round(hbm_bytes / (batched_gpu_ms / 1e3) / 1e9, 1),
+                        "frac": round(hbm_bytes / (batched_gpu_ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4)}}
     extra = {"batched_ms": round(batched_s * 1e3, 3), "batched_gpu_ms": round(batched_gpu_ms, 3),
              "oneshot_ms": round(oneshot_s * 1e3, 3), "plain_ms": round(plain_s * 1e3, 3),
              "speedup_vs_plain": round(plain_s / batched_s, 2),
-             "plain_gbs": round(logical / plain_s / 1e9, 1), "identical_output": identical}
+             "plain_gbs": round(logical / plain_s / 1e9, 1), "identical_output": identical,
+             "roofline": roofline}
     return logical, batched_s, config, extra
 
 
@@ -395,46 +434,74 @@ def run_serve_workload(args, torch, W, epsm):
 
 
 def cpu_baseline(torch, texts, cases, seconds: float, threads: int):
-    """The oracle, as it stands, on a bounded sample of the same workload."""
+    """The oracle, as it stands, on a bounded sample of the same workload:
+    half of the budget on the count-mode searches (oracle_count_mt), half on
+    the positions-mode ones (oracle_range_mt over 64M-start ranges, every
+    position materialised on the host), in the workload's order; each
+    completed search's count must equal the GPU's."""
     import oracle
     if threads <= 0:
-        threads = os.cpu_count() or 1
-    done_bytes, elapsed, used = 0, 0.0, []
+        threads = min(16, os.cpu_count() or 1)
     host_cache = {}
-    for c in cases:
-        if c.mode != "count":
-            continue
-        if c.text_idx not in host_cache:
+
+    def host(ti):
+        if ti not in host_cache:
             host_cache.clear()
-            host_cache[c.text_idx] = texts[c.text_idx].cpu().numpy()
-        t = host_cache[c.text_idx]
-        t0 = time.perf_counter()
-        got = oracle.count_mt(t, c.pattern, threads)
-        dt = time.perf_counter() - t0
-        if got != c.count:
-            raise AssertionError(f"oracle count {got} != GPU count {c.count} for m={len(c.pattern)}")
-        done_bytes += t.size
-        elapsed += dt
-        used.append(len(c.pattern))
-        if elapsed >= seconds:
-            break
+            host_cache[ti] = texts[ti].cpu().numpy()
+        return host_cache[ti]
+
+    modes = {}
+    for mode in ("count", "positions"):
+        done_bytes, elapsed, used, positions = 0, 0.0, [], 0
+        for c in cases:
+            if c.mode != mode:
+                continue
+            t = host(c.text_idx)
+            m = len(c.pattern)
+            got = 0
+            t0 = time.perf_counter()
+            if mode == "count":
+                got = oracle.count_mt(t, c.pattern, threads)
+            else:
+                chunk = 1 << 26
+                for lo in range(0, t.size - m + 1, chunk):
+                    got += oracle.search_range_mt(t, c.pattern, lo, lo + chunk, threads).size
+            dt = time.perf_counter() - t0
+            if got != c.count:
+                raise AssertionError(f"oracle {mode} count {got} != GPU count {c.count} for m={m}")
+            done_bytes += t.size
+            elapsed += dt
+            positions += got
+            used.append(m)
+            if elapsed >= seconds / 2:
+                break
+        modes[mode] = {"gbs": round(done_bytes / elapsed / 1e9, 3), "searches": len(used), "ms": used,
+                       "text_gib": round(done_bytes / 2**30, 2), "seconds": round(elapsed, 2),
+                       "positions": positions}
     # one thread on the first count-mode search, for the per-core rate
     first = next(c for c in cases if c.mode == "count")
-    t = texts[first.text_idx].cpu().numpy()
+    t = host(first.text_idx)
     t0 = time.perf_counter()
     got = oracle.count_mt(t, first.pattern, 1)
     one_s = time.perf_counter() - t0
     if got != first.count:
         raise AssertionError(f"oracle count {got} != GPU count {first.count} (one thread)")
     host_cache.clear()
+    total_bytes = sum(v["text_gib"] for v in modes.values()) * 2**30
+    total_s = sum(v["seconds"] for v in modes.values())
     return {
-        "value": round(done_bytes / elapsed / 1e9, 3),
+        "value": round(total_bytes / total_s / 1e9, 3),
         "unit": "GB/s",
         "cores": threads,
         "kind": "oracle",
-        "sample": f"count mode (oracle_count_mt, {threads} threads) over the first {len(used)} "
-                  f"count-mode searches of the workload (m = {used}), {done_bytes / 2**30:.1f} GiB "
-                  f"of text in {elapsed:.1f} s; counts equal the GPU's",
+        "sample": (f"the oracle ({threads} threads over contiguous start ranges) on the workload's first "
+                   f"{modes['count']['searches']} count-mode searches (m = {modes['count']['ms']}, "
+                   f"{modes['count']['text_gib']} GiB, {modes['count']['gbs']} GB/s) and first "
+                   f"{modes['positions']['searches']} positions-mode searches (m = {modes['positions']['ms']}, "
+                   f"{modes['positions']['text_gib']} GiB, {modes['positions']['positions']} positions "
+                   f"materialised, {modes['positions']['gbs']} GB/s); counts equal the GPU's"),
+        "count_mode": modes["count"],
+        "positions_mode": modes["positions"],
         "single_thread_value": round(t.size / one_s / 1e9, 3),
         "single_thread_sample": f"the first count-mode search (m = {len(first.pattern)}), "
                                 f"{t.size / 2**30:.2f} GiB in {one_s:.2f} s",
@@ -443,6 +510,15 @@ def cpu_baseline(torch, texts, cases, seconds: float, threads: int):
 
 
 def cpu_model() -> str:
+    """The host CPU's model name (lscpu, else /proc/cpuinfo)."""
+    import subprocess
+    try:
+        r = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10)
+        for line in r.stdout.splitlines():
+            if line.strip().startswith("Model name:"):
+                return line.split(":", 1)[1].strip()
+    except (OSError, subprocess.SubprocessError):
+        pass
     try:
         with open("/proc/cpuinfo") as f:
             for line in f:
@@ -538,7 +614,7 @@ def main():
             "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
             "ms_per_step": round(step_s * 1e3, 3), "higher_is_better": True, "scaling": "weak",
             "vs_baseline": None, "dtype": "u8", "data": "synthetic", "config": dict(config, tuning=tuning),
-            "batch": extra, "roofline": None, "cpu_baseline": None,
+            "batch": extra, "roofline": extra["roofline"], "cpu_baseline": None,
         }
         print(json.dumps(result), flush=True)
         return
@@ -567,31 +643,26 @@ def main():
     log(f"{len(cases)} searches, largest output {max_hits} positions")
     out = torch.empty(max_hits, dtype=torch.int64, device="cuda")
     step_bytes = sum(texts[c.text_idx].numel() for c in cases)
+    step_alg_bytes = sum(texts[c.text_idx].numel() + (8 * c.count if c.mode == "positions" else 0)
+                         for c in cases)
     pos_alg_bytes = sum(texts[c.text_idx].numel() + 8 * c.count for c in cases if c.mode == "positions")
-
-    events = []
+    for c in cases:
+        c.events = []
 
     def step(record: bool):
         for c in cases:
             t = texts[c.text_idx]
+            if record:
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record()
             if c.mode == "positions":
-                if record:
-                    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-                    e0.record()
                 epsm.search_into(c.plan, t, out[:c.count], hits)
-                if record:
-                    e1.record()
-                    events.append((e0, e1))
             else:
-                if record and args.detail:
-                    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-                    e0.record()
                 epsm.count_into(c.plan, t, hits)
-                if record and args.detail:
-                    e1.record()
-                    cevents.append((e0, e1))
+            if record:
+                e1.record()
+                c.events.append((e0, e1))
 
-    cevents = []
     for _ in range(args.warmup):
         step(False)
     torch.cuda.synchronize()
@@ -604,7 +675,7 @@ def main():
     epsm.stream_check()
     elapsed = t1 - t0
 
-    # spot-check the last positions search against its count
+    # the last search of the step wrote its count: spot-check it
     if int(hits.item()) != cases[-1].count:
         raise AssertionError("count mismatch after timing")
     if args.positions_only:
@@ -612,23 +683,16 @@ def main():
                           "text_bytes_per_step": step_bytes}), flush=True)
         return
 
-    pos_ms = sum(e0.elapsed_time(e1) for e0, e1 in events)
-    if args.detail:
-        pos_cases = [c for c in cases if c.mode == "positions"]
-        for i, c in enumerate(pos_cases):
-            ms = sum(events[s * len(pos_cases) + i][0].elapsed_time(events[s * len(pos_cases) + i][1])
-                     for s in range(args.steps)) / args.steps
+    for c in cases:
+        c.ms = sum(e0.elapsed_time(e1) for e0, e1 in c.events) / len(c.events)
+        if args.detail:
             n = texts[c.text_idx].numel()
-            log(f"text{c.text_idx} m={len(c.pattern):2d} {c.origin:11s} hits={c.count:11d} {ms:8.3f} ms "
-                f"text {n / ms / 1e6:7.1f} GB/s alg {(n + 8 * c.count) / ms / 1e6:7.1f} GB/s")
-        cnt_cases = [c for c in cases if c.mode == "count"]
-        for i, c in enumerate(cnt_cases):
-            ms = sum(cevents[s * len(cnt_cases) + i][0].elapsed_time(cevents[s * len(cnt_cases) + i][1])
-                     for s in range(args.steps)) / args.steps
-            n = texts[c.text_idx].numel()
-            log(f"count text{c.text_idx} m={len(c.pattern):2d} {c.origin:11s} hits={c.count:11d} {ms:8.3f} ms "
-                f"text {n / ms / 1e6:7.1f} GB/s")
-    n_pos_launches = len(events)
+            log(f"{c.mode:9s} text{c.text_idx} m={len(c.pattern):2d} {c.origin:11s} hits={c.count:11d} "
+                f"{c.ms:8.3f} ms text {n / c.ms / 1e6:7.1f} GB/s "
+                f"alg {(n + (8 * c.count if c.mode == 'positions' else 0)) / c.ms / 1e6:7.1f} GB/s")
+    pos_cases = [c for c in cases if c.mode == "positions"]
+    pos_ms = sum(c.ms for c in pos_cases) * args.steps
+    n_pos_launches = len(pos_cases) * args.steps
     achieved = pos_alg_bytes * args.steps / (pos_ms / 1e3) / 1e9
     traffic = load_traffic(args.workload)
     roofline = {
@@ -643,7 +707,7 @@ def main():
                   "event-timed per search",
         "launches": n_pos_launches,
         "avg_launch_ms": round(pos_ms / n_pos_launches, 4),
-        "alg_bytes_per_launch": round(pos_alg_bytes / (n_pos_launches / args.steps)),
+        "alg_bytes_per_launch": round(pos_alg_bytes / len(pos_cases)),
     }
 
     result = {
@@ -660,14 +724,57 @@ def main():
         "dtype": "u8",
         "data": "synthetic",
         "config": dict(config, tuning=tuning),
+        "alg_gbs": round(step_alg_bytes * args.steps / elapsed / 1e9, 1),
         "roofline": roofline,
+        "scan": scan_summary(cases, texts, specs),
     }
     if args.cpu_seconds > 0:
         log("timing the CPU oracle baseline")
         result["cpu_baseline"] = cpu_baseline(torch, texts, cases, args.cpu_seconds, args.threads)
     else:
         result["cpu_baseline"] = None
+    if args.workload == "zipf4g" and not args.scan_only:
+        del texts, out, cases
+        gc.collect()
+        torch.cuda.empty_cache()
+        epsm.release()
+        logical, step_s, bconfig, extra = run_batch_workload(args, torch, W, epsm)
+        result["batch"] = dict(extra, gbs=round(logical / step_s / 1e9, 1), config=bconfig)
+        gc.collect()
+        torch.cuda.empty_cache()
+        epsm.release()
+        points, stats, sconfig = run_serve_workload(args, torch, W, epsm)
+        top = points[-1]
+        result["serve"] = {"points": points, "p50_ms": top["p50_ms"], "p99_ms": top["p99_ms"],
+                           "gbs": top["gbs"], "server_stats": stats, "config": sconfig}
     print(json.dumps(result), flush=True)
+
+
+def scan_summary(cases, texts, specs) -> dict:
+    """Per-search rates of the timed step, by text and mode (text GB/s, and
+    algorithmic GB/s = (n + 8 per written position) / time), with the count-
+    and positions-mode ranges of each text."""
+    out = {}
+    for ti, spec in enumerate(specs):
+        n = texts[ti].numel()
+        name = f"{spec.kind}" + (f"_sigma{spec.sigma}" if spec.kind == "uniform" else "")
+        rows = []
+        for c in cases:
+            if c.text_idx != ti:
+                continue
+            alg = n + (8 * c.count if c.mode == "positions" else 0)
+            rows.append({"m": len(c.pattern), "mode": c.mode, "origin": c.origin, "hits": c.count,
+                         "ms": round(c.ms, 4), "text_gbs": round(n / c.ms / 1e6, 1),
+                         "alg_gbs": round(alg / c.ms / 1e6, 1)})
+        summary = {"text_bytes": n, "searches": rows}
+        for mode in ("count", "positions"):
+            r = [x for x in rows if x["mode"] == mode]
+            if r:
+                summary[f"{mode}_alg_gbs_min"] = min(x["alg_gbs"] for x in r)
+                summary[f"{mode}_alg_gbs_max"] = max(x["alg_gbs"] for x in r)
+                summary[f"{mode}_frac_min"] = round(summary[f"{mode}_alg_gbs_min"] / HBM_PEAK_GBS, 3)
+        out[name] = summary
+    return out
 
 
 if __name__ == "__main__":
