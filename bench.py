@@ -402,9 +402,21 @@ def run_serve_workload(args, torch, W, epsm):
     def logical(qs):
         return sum(len(q.patterns) * specs[q.text].n for q in qs)
 
+    def split(outs, lat):
+        # latency = queueing (arrival -> its micro-batch formed) + service
+        # (micro-batch formed -> results in host memory)
+        service = np.array([o.done_time - o.start_time for o in outs])
+        wait = lat - service
+        big = np.argsort(service)[-max(1, len(outs) // 100):]  # the slowest 1% of services
+        return {"p99_wait_ms": round(float(np.percentile(wait, 99)) * 1e3, 2),
+                "p99_service_ms": round(float(np.percentile(service, 99)) * 1e3, 2),
+                "slowest_1pct_logical_gb": round(float(np.mean(
+                    [len(qs_cur[i].patterns) * specs[qs_cur[i].text].n for i in big])) / 1e9, 1)}
+
     base = W.config5_queries(specs, n_q, qps=1.0)
     burst = [W.Query(0.0, q.text, q.patterns) for q in base]
     log(f"saturation run: burst of {n_q} queries")
+    qs_cur = burst
     outs, lat, wall = serve.run_queries(srv, burst)
     sat_qps = n_q / wall
     points = [{"load": "burst", "qps": round(sat_qps, 1), "wall_s": round(wall, 3),
@@ -416,14 +428,16 @@ def run_serve_workload(args, torch, W, epsm):
         qps = frac * sat_qps
         qs = W.config5_queries(specs, n_q, qps=qps, seed_stream=10 + int(frac * 100))
         log(f"Poisson stream at {qps:.1f} QPS ({frac} x saturation)")
+        qs_cur = qs
         outs, lat, wall = serve.run_queries(srv, qs)
         if any(o.status for o in outs):
             raise AssertionError("a served query failed")
-        points.append({"load": frac, "qps": round(qps, 1), "wall_s": round(wall, 3),
-                       "gbs": round(logical(qs) / wall / 1e9, 1),
-                       "p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 2),
-                       "p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 2),
-                       "mean_batch_queries": round(float(np.mean([o.batch_queries for o in outs])), 2)})
+        points.append(dict({"load": frac, "qps": round(qps, 1), "wall_s": round(wall, 3),
+                            "gbs": round(logical(qs) / wall / 1e9, 1),
+                            "p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 2),
+                            "p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 2),
+                            "mean_batch_queries": round(float(np.mean([o.batch_queries for o in outs])), 2)},
+                           **split(outs, lat)))
     stats = srv.stats()
     srv.close()
     config = {"workload": f"serve: {len(specs)} resident texts sigma 20 log-uniform [1 MiB, 256 MiB], "

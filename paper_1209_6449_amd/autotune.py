@@ -288,7 +288,34 @@ def tune_variants(rows, k_default: int, n: int = 1 << 28, reps: int = 5, log=pri
             log(f"[autotune] variant m{m}/no hint: {best}")
     set_tune_table([])
     stream_check()
-    return out_rows, timings
+    return merge_variant_rows(out_rows), timings
+
+
+def merge_variant_rows(rows) -> list:
+    """The same choices in fewer rows: an m range whose alphabet rows (with
+    the no-hint one) all agree and cover 0..256 becomes one row, then
+    neighbouring m ranges with the same alphabet range and choice merge."""
+    by_m = {}
+    for r in rows:
+        by_m.setdefault((r[0], r[1]), []).append(r)
+    out = []
+    for (lo, hi), rs in sorted(by_m.items()):
+        choices = {(r[4], r[5]) for r in rs}
+        cover = sorted((r[2], r[3]) for r in rs)
+        full = cover[0][0] == 0 and all(b[0] == a[1] + 1 for a, b in zip(cover, cover[1:])) and \
+            cover[-1][1] == 256
+        if len(choices) == 1 and full:
+            out.append((lo, hi, 0, 256) + next(iter(choices)))
+        else:
+            out.extend(sorted(tuple(r) for r in rs))
+    merged = []
+    for r in out:
+        p = merged[-1] if merged else None
+        if p and p[1] + 1 == r[0] and p[2:] == r[2:]:
+            merged[-1] = (p[0], r[1]) + p[2:]
+        else:
+            merged.append(r)
+    return merged
 
 
 def tune_batch(n_texts: int = 400, max_len: int = 1 << 22, reps: int = 3, log=print) -> tuple[int, dict]:

@@ -439,18 +439,39 @@ static __device__ inline uint64_t look_back(uint64_t *status, uint32_t tile, uin
 // offsets; one piece adds at most 1024).
 constexpr uint32_t kStage = 1024;
 
+typedef int64_t i64x2 __attribute__((ext_vector_type(2)));
+
 // Write stage[0..fill) as positions wave_pos0 + stage[j] to out[obase + j]
-// (entries at or past cap are dropped).  Lanes write consecutive entries.
+// (entries at or past cap are dropped).  Lanes write consecutive pairs of
+// entries as one 16-byte store (a wave instruction covers 1 KiB); an entry
+// before the first 16-byte boundary of the range, and an odd last one, are
+// written alone.
 __device__ __forceinline__ void flush_stage(const uint32_t *stage, uint32_t fill, int64_t *out,
                                             uint64_t cap, uint64_t obase, int64_t wave_pos0,
                                             int lane) {
     // the stage was filled by other lanes of this wave: order the LDS accesses
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     __builtin_amdgcn_wave_barrier();
-    for (uint32_t j = lane; j < fill; j += kWave) {
-        const uint64_t idx = obase + j;
-        if (idx < cap) out[idx] = wave_pos0 + stage[j];
+    const uint64_t end = min((uint64_t)fill, cap > obase ? cap - obase : 0ull);  // entries written
+    if ((uintptr_t)out & 7u) {
+        // an output that is not 8-byte aligned: one entry per store
+        for (uint32_t j = lane; j < end; j += kWave) out[obase + j] = wave_pos0 + stage[j];
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        return;
     }
+    // entry `head` (0 or 1) is the first on a 16-byte boundary
+    const uint32_t head = (((uintptr_t)(out + obase)) & 15u) ? 1u : 0u;
+    if (head && end > 0 && lane == 0) out[obase] = wave_pos0 + stage[0];
+    const uint64_t pairs = end > head ? (end - head) / 2 : 0;
+    for (uint64_t q = lane; q < pairs; q += kWave) {
+        const uint32_t j = head + 2 * (uint32_t)q;
+        i64x2 v;
+        v.x = wave_pos0 + stage[j];
+        v.y = wave_pos0 + stage[j + 1];
+        *reinterpret_cast<i64x2 *>(out + obase + j) = v;
+    }
+    if (end > head && ((end - head) & 1) && lane == 0) out[obase + end - 1] = wave_pos0 + stage[end - 1];
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     __builtin_amdgcn_wave_barrier();
 }
@@ -534,7 +555,7 @@ __device__ __forceinline__ void load_chunk_dna(uint32_t (&w)[U][5], __amdgpu_buf
 // except in the three-load kernels, which keep the lean form for their
 // registers; the fingerprint filter's candidates are sparse within a wave
 // even on binary text (8/256 of the blocks), so it verifies only the starts
-// that have some.
+// that have some, in the lean form (measured faster there).
 template <int U, int NL, int VAR, int PK, int NW, bool CNT, int PAIRS, int THREADS>
 __device__ __forceinline__ uint32_t process_chunk(uint32_t (&w)[U][NL * 4 + 1], int c,
                                                   const ScanArgs &a, const uint16_t *tab,
@@ -552,7 +573,7 @@ __device__ __forceinline__ uint32_t process_chunk(uint32_t (&w)[U][NL * 4 + 1], 
             uint64_t b[16];
             bool any;
             if constexpr (VAR == 1) any = direct_wave_masks<NL, PK, NW, kLean, kLean>(w[u], a.plan, b);
-            else any = fingerprint_wave_masks<NL, true, kLean>(w[u], a.plan, tab, b);
+            else any = fingerprint_wave_masks<NL, true, true>(w[u], a.plan, tab, b);
             if (any) {
                 if (edge) {
                     // only the first tile holds starts below delta and only
@@ -567,7 +588,7 @@ __device__ __forceinline__ uint32_t process_chunk(uint32_t (&w)[U][NL * 4 + 1], 
         }
         uint32_t mk;
         if constexpr (VAR == 1) mk = direct_mask<NL, PK, NW, kLean, kLean>(w[u], a.plan);
-        else if constexpr (VAR == 2) mk = fingerprint_mask<NL, true, kLean>(w[u], a.plan, tab);
+        else if constexpr (VAR == 2) mk = fingerprint_mask<NL, true, true>(w[u], a.plan, tab);
         else if constexpr (PK == 16) mk = dna_block_mask(w[u], a.plan, tab);
         else mk = dna_mask<false>(w[u], a.plan);
         if (edge) mk &= valid_mask(s0, a.delta, a.last);

@@ -434,3 +434,15 @@ def test_stride_rows_below_263(m, S):
         epsm.set_variant_table([])
     info = host_plan((bytes(range(256)) * 3)[:m])
     assert info["variant"] == (epsm.VARIANT_STRIDE if m >= 263 else epsm.VARIANT_FINGERPRINT)
+
+
+def test_variant_rows_merge():
+    from paper_1209_6449_amd.autotune import merge_variant_rows
+    D, F, SR = epsm.VARIANT_DIRECT, epsm.VARIANT_FINGERPRINT, epsm.PLAN_SHORT_RUN
+    rows = [(16, 17, 1, 2, D, 0), (16, 17, 3, 9, D, 0), (16, 17, 10, 256, F, 0),
+            (18, 22, 1, 2, D, SR), (18, 22, 3, 9, D, SR), (18, 22, 10, 256, D, SR), (18, 22, 0, 0, D, SR),
+            (23, 28, 0, 0, D, SR), (23, 28, 1, 256, D, SR), (29, 40, 1, 256, D, SR)]
+    assert merge_variant_rows(rows) == [
+        (16, 17, 1, 2, D, 0), (16, 17, 3, 9, D, 0), (16, 17, 10, 256, F, 0),
+        (18, 28, 0, 256, D, SR), (29, 40, 1, 256, D, SR)]
+    assert merge_variant_rows([]) == []

@@ -423,3 +423,36 @@ def test_small_stride_rows_match_oracle(epsm, m):
         epsm.stream_check()
     finally:
         epsm.set_variant_table([])
+
+
+@pytest.mark.parametrize("shift", [0, 8, 4, 1])
+def test_output_pointer_alignment(epsm, shift):
+    """Positions written to an output that starts `shift` bytes past a
+    16-byte boundary (16-byte pair stores, the single entry before the first
+    boundary, and the unaligned fallback), dense single-pass and sparse
+    two-phase outputs, exact and truncated capacities."""
+    import ctypes
+    L = epsm.lib()
+    dense = torch.full((3 * TILE + 5,), ord("a"), dtype=torch.uint8, device="cuda")
+    rng = np.random.default_rng(7)
+    sparse_h = rng.integers(0, 64, 40 * TILE + 3).astype(np.uint8)
+    sparse = torch.from_numpy(sparse_h).cuda()
+    for t, pat in ((dense, b"aa"), (sparse, bytes(sparse_h[5000:5002]))):
+        host = t.cpu().numpy()
+        exp = oracle.positions(host, pat)
+        plan = epsm.Plan(pat)
+        for cap in (exp.size, exp.size - 1, 3, 1):
+            say(f"output alignment shift={shift} n={t.numel()} hits={exp.size} cap={cap}")
+            buf = torch.full((cap * 8 + 32,), 0xEE, dtype=torch.uint8, device="cuda")
+            base = (buf.data_ptr() + 15) // 16 * 16 + shift
+            hits = torch.zeros(1, dtype=torch.int64, device="cuda")
+            st = L.epsm_search(plan.handle, t.data_ptr(), t.numel(), ctypes.c_void_p(base), cap,
+                               hits.data_ptr(), None)
+            assert st == 0
+            epsm.stream_check()
+            assert int(hits.item()) == exp.size
+            raw = buf.cpu().numpy()
+            start = base - buf.data_ptr()
+            got = raw[start:start + 8 * cap].view(np.int64)
+            assert np.array_equal(got, exp[:cap]), (shift, cap)
+            assert (raw[:start] == 0xEE).all() and (raw[start + 8 * cap:] == 0xEE).all()
