@@ -75,6 +75,10 @@ def parse_args():
     ap.add_argument("--positions-only", action="store_true",
                     help="profiling aid: only the positions-mode searches, outputs sized to n "
                          "(no count pass), so every scan dispatch is a positions-mode one")
+    ap.add_argument("--count-only", action="store_true",
+                    help="profiling aid: only the count-mode searches of the workload")
+    ap.add_argument("--no-plain", action="store_true",
+                    help="profiling aid (batch): leave out the per-instance searches")
     return ap.parse_args()
 
 
@@ -322,6 +326,10 @@ def run_batch_workload(args, torch, W, epsm):
     batch.run()
     torch.cuda.synchronize()
     oneshot_s = time.perf_counter() - t0
+    if args.no_plain:
+        print(json.dumps({"batch_no_plain": True, "batched_gpu_ms": round(batched_gpu_ms, 3),
+                          "units": info["units"], "entries": info["entries"]}), flush=True)
+        sys.exit(0)
 
     # per-instance plain searches: one epsm_search per pair into its slice
     log("creating device plans for the per-instance baseline")
@@ -639,6 +647,8 @@ def main():
     # size outputs with a count pass (untimed)
     hits = torch.zeros(1, dtype=torch.int64, device="cuda")
     max_hits = 1
+    if args.count_only:
+        cases = [c for c in cases if c.mode == "count"]
     if args.positions_only:
         # counts from one count-only batch (its own kernel), so that every
         # scan dispatch of the process is a timed positions-mode one
@@ -692,9 +702,10 @@ def main():
     # the last search of the step wrote its count: spot-check it
     if int(hits.item()) != cases[-1].count:
         raise AssertionError("count mismatch after timing")
-    if args.positions_only:
-        print(json.dumps({"positions_only": True, "dispatches_per_step": len(cases),
-                          "text_bytes_per_step": step_bytes}), flush=True)
+    if args.positions_only or args.count_only:
+        print(json.dumps({"positions_only" if args.positions_only else "count_only": True,
+                          "dispatches_per_step": len(cases), "text_bytes_per_step": step_bytes,
+                          "ms_per_step": round(elapsed * 1e3 / args.steps, 3)}), flush=True)
         return
 
     for c in cases:

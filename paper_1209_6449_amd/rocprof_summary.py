@@ -6,6 +6,10 @@
     python -m paper_1209_6449_amd.rocprof_summary stats DIR --command "..." --out FILE
     # HBM traffic per dispatch of a kernel from two --pmc runs (FETCH_SIZE,
     # WRITE_SIZE), scaled by the same counters on the calibration copy
+    # shader-sequencer counters per 1 KiB of text of each scan dispatch
+    python -m paper_1209_6449_amd.rocprof_summary sq DIR --bytes-per-dispatch N --command "..." --out FILE
+    # L2 read requests by size (what FETCH_SIZE's formula assumes about them)
+    python -m paper_1209_6449_amd.rocprof_summary requests DIR --command "..." --out FILE
     python -m paper_1209_6449_amd.rocprof_summary traffic --fetch DIR --write DIR \
         --calib-fetch DIR --calib-write DIR --calib-bytes N --kernel scan_kernel \
         --workload sweep1g --command "..." --out-json FILE --out-txt FILE
@@ -25,9 +29,8 @@ import sys
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 # what decides the traffic of a search: the kernels, the host's choice of
 # tile and write strategy, and the packaged tune table
-KERNEL_SOURCES = ["paper_1209_6449_amd/csrc/epsm_kernels.hip", "paper_1209_6449_amd/csrc/epsm_device.h",
-                  "paper_1209_6449_amd/csrc/epsm_internal.h", "paper_1209_6449_amd/csrc/epsm_api.hip",
-                  "paper_1209_6449_amd/tuned/gfx950_256cu.json"]
+KERNEL_SOURCES = sorted(os.path.relpath(p, ROOT) for p in glob.glob(os.path.join(ROOT, "paper_1209_6449_amd", "csrc", "*"))
+                        if p.endswith((".hip", ".h"))) + ["paper_1209_6449_amd/tuned/gfx950_256cu.json"]
 
 
 def _code_only(text: str) -> str:
@@ -107,6 +110,62 @@ def cmd_stats(args):
                 per_unit += total / max(units, 1)
         if len(names) > 1 and units:
             lines.append(f"per {names[0]} dispatch, {' + '.join(names)}: {per_unit / 1e3:.2f} us")
+    text = "\n".join(lines) + "\n"
+    with open(args.out, "w") as f:
+        f.write(text)
+    print(text)
+
+
+def cmd_sq(args):
+    """Shader-sequencer counters of each dispatch of a kernel, per 1 KiB of
+    text (one wave's piece): the instruction mix that bounds a scan."""
+    rows = list(csv.DictReader(open(_find(args.dir, "counter_collection.csv"))))
+    disp = {}
+    for r in rows:
+        if args.kernel not in r["Kernel_Name"]:
+            continue
+        d = disp.setdefault(int(r["Dispatch_Id"]), {"name": r["Kernel_Name"],
+                                                    "us": (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3})
+        d[r["Counter_Name"]] = float(r["Counter_Value"])
+    labels = args.labels.split(",") if args.labels else []
+    counters = sorted({k for d in disp.values() for k in d if k.startswith("SQ_")})
+    pieces = args.bytes_per_dispatch / 1024
+    lines = [f"# {args.title}", f"command: {args.command}",
+             f"counts per 1 KiB of text ({pieces:.0f} pieces per dispatch); kernel duration under counters",
+             "", f"{'search':>14} {'us':>9} " + " ".join(f"{c[3:]:>16}" for c in counters) + "  kernel"]
+    per = args.per_label
+    for i, (k, d) in enumerate(sorted(disp.items())[args.skip:]):
+        lab = labels[i // per] if i // per < len(labels) else str(k)
+        if args.last_only and (i % per) != per - 1:
+            continue
+        tmpl = d["name"].split("scan_kernel")[-1][:40] if "scan_kernel" in d["name"] else d["name"][:40]
+        lines.append(f"{lab:>14} {d['us']:9.1f} " + " ".join(f"{d.get(c, 0) / pieces:16.1f}" for c in counters)
+                     + f"  {tmpl}")
+    text = "\n".join(lines) + "\n"
+    with open(args.out, "w") as f:
+        f.write(text)
+    print(text)
+
+
+def cmd_requests(args):
+    """Read requests the L2 sends to memory, by size, for each dispatch of a
+    kernel (from a run with TCC_EA0_RDREQ_sum, TCC_EA0_RDREQ_32B_sum,
+    TCC_EA0_RDREQ_128B_sum and TCC_BUBBLE_sum)."""
+    rows = list(csv.DictReader(open(_find(args.dir, "counter_collection.csv"))))
+    disp = {}
+    for r in rows:
+        if args.kernel not in r["Kernel_Name"]:
+            continue
+        disp.setdefault(int(r["Dispatch_Id"]), {"name": r["Kernel_Name"]})[r["Counter_Name"]] = float(r["Counter_Value"])
+    lines = [f"# {args.title}", f"command: {args.command}", "",
+             f"{'dispatch':>8} {'RDREQ':>12} {'RDREQ_128B':>12} {'RDREQ_32B':>10} {'BUBBLE':>8} "
+             f"{'128B x 128 (MB)':>16} {'FETCH_SIZE formula (MB)':>24}  kernel"]
+    for k, d in sorted(disp.items()):
+        rq, r128 = d.get("TCC_EA0_RDREQ_sum", 0), d.get("TCC_EA0_RDREQ_128B_sum", 0)
+        r32, bub = d.get("TCC_EA0_RDREQ_32B_sum", 0), d.get("TCC_BUBBLE_sum", 0)
+        formula = (bub * 128 + (rq - bub - r32) * 64 + r32 * 32) / 1e6
+        lines.append(f"{k:8d} {rq:12.0f} {r128:12.0f} {r32:10.0f} {bub:8.0f} {r128 * 128 / 1e6:16.1f} "
+                     f"{formula:24.1f}  {d['name'][:50]}")
     text = "\n".join(lines) + "\n"
     with open(args.out, "w") as f:
         f.write(text)
@@ -197,8 +256,26 @@ def main(argv=None):
     t.add_argument("--command", required=True)
     t.add_argument("--out-json", required=True)
     t.add_argument("--out-txt", required=True)
+    q = sub.add_parser("sq")
+    q.add_argument("dir")
+    q.add_argument("--kernel", default="scan_kernel")
+    q.add_argument("--bytes-per-dispatch", type=int, required=True)
+    q.add_argument("--labels", default="", help="comma-separated names of the searches, in dispatch order")
+    q.add_argument("--per-label", type=int, default=1, help="dispatches per search (steps)")
+    q.add_argument("--last-only", action="store_true", help="only the last dispatch of each search")
+    q.add_argument("--skip", type=int, default=0, help="leave out the first SKIP dispatches (e.g. a sizing pass)")
+    q.add_argument("--title", default="shader-sequencer counters")
+    q.add_argument("--command", required=True)
+    q.add_argument("--out", required=True)
+    r = sub.add_parser("requests")
+    r.add_argument("dir")
+    r.add_argument("--kernel", default="")
+    r.add_argument("--title", default="L2 read requests by size")
+    r.add_argument("--command", required=True)
+    r.add_argument("--out", required=True)
     args = ap.parse_args(argv)
-    {"calibrate": cmd_calibrate, "stats": cmd_stats, "traffic": cmd_traffic}[args.cmd](args)
+    {"calibrate": cmd_calibrate, "stats": cmd_stats, "traffic": cmd_traffic, "sq": cmd_sq,
+     "requests": cmd_requests}[args.cmd](args)
 
 
 if __name__ == "__main__":
