@@ -643,11 +643,13 @@ epsm_status build_batch(const epsm_batch *b, int waves, HostBatch &hb, bool chec
                 if (hb.pairs[k].plan.m < 4) continue;
                 if (hb.groups.size() == d.group_begin || hb.groups.back().count == kGroupMax) {
                     hb.groups.push_back({(uint32_t)hb.group_pairs.size(), 0});
-                    hb.group_tables.resize(hb.group_tables.size() + kGroupBuckets, 0);
+                    hb.group_tables.resize(hb.group_tables.size() + kGroupTableWords, 0);
                 }
                 BatchGroupDesc &g = hb.groups.back();
                 const uint32_t bucket = group_bucket(hb.pairs[k].plan.pw[0]);
-                hb.group_tables[(hb.groups.size() - 1) * kGroupBuckets + bucket] |= 1u << g.count;
+                uint32_t *table = hb.group_tables.data() + (hb.groups.size() - 1) * kGroupTableWords;
+                table[bucket] |= 1u << g.count;
+                table[kGroupBuckets + bucket / 32] |= 1u << (bucket % 32);
                 hb.group_pairs.push_back(k);
                 g.count++;
             }

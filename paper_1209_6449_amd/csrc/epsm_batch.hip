@@ -59,9 +59,16 @@ __device__ __forceinline__ void group_count(const uint32_t (&w)[kBatchNL * 4 + 1
                                             const uint32_t (*s_pm)[8], const uint64_t *s_m,
                                             const uint8_t *const *s_pat, uint32_t *s_cnt,
                                             const BatchTextDesc &t, uint64_t s0, uint32_t lane_byte) {
+    // first the bitmap of non-empty buckets (32 words, one per LDS bank: no
+    // bank conflicts whatever buckets the lanes test), then, for the rare
+    // windows whose bucket holds members, the member masks
+    const uint32_t *s_bits = s_tab + kGroupBuckets;
     uint32_t cand = 0;
 #pragma unroll
-    for (int k = 0; k < 16; ++k) cand |= (s_tab[group_bucket(window(w, k))] != 0 ? 1u : 0u) << k;
+    for (int k = 0; k < 16; ++k) {
+        const uint32_t b = group_bucket(window(w, k));
+        cand |= ((s_bits[b >> 5] >> (b & 31)) & 1u) << k;
+    }
     while (cand) {
         const uint32_t k = __builtin_ctz(cand);
         cand &= cand - 1;
@@ -183,7 +190,7 @@ __global__ __launch_bounds__(WAVES * kWave) void batch_kernel(BatchArgs a) {
     // groups: the piece goes to LDS once (windows at run-time offsets), then
     // each group's table, first words and lengths are staged in turn
     __shared__ uint32_t s_text[WAVES][kTextWords];
-    __shared__ uint32_t s_tab[kGroupBuckets];
+    __shared__ uint32_t s_tab[kGroupTableWords];
     __shared__ uint32_t s_pw[kGroupMax][8], s_pm[kGroupMax][8];
     __shared__ uint64_t s_m[kGroupMax];
     __shared__ const uint8_t *s_pat[kGroupMax];
@@ -199,8 +206,8 @@ __global__ __launch_bounds__(WAVES * kWave) void batch_kernel(BatchArgs a) {
 #pragma unroll 1
     for (uint32_t g = t.group_begin; g < t.group_end; ++g) {
         const BatchGroupDesc gd = a.groups[g];
-        const uint32_t *gt = a.group_tables + (size_t)g * kGroupBuckets;
-        for (uint32_t i = tid; i < kGroupBuckets; i += kThreads) s_tab[i] = gt[i];
+        const uint32_t *gt = a.group_tables + (size_t)g * kGroupTableWords;
+        for (uint32_t i = tid; i < kGroupTableWords; i += kThreads) s_tab[i] = gt[i];
         for (uint32_t i = tid; i < gd.count * 8; i += kThreads) {
             const DevPlan &p = a.pairs[a.group_pairs[gd.first + i / 8]].plan;
             s_pw[i / 8][i % 8] = p.pw[i % 8];

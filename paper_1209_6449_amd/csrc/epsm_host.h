@@ -46,7 +46,7 @@ struct HostBatch {
     std::vector<uint32_t> solo;            // count pass: pairs filtered alone
     std::vector<BatchGroupDesc> groups;    // count pass: pattern groups
     std::vector<uint32_t> group_pairs;
-    std::vector<uint32_t> group_tables;    // kGroupBuckets per group
+    std::vector<uint32_t> group_tables;    // kGroupTableWords per group (masks, then bitmap)
     std::vector<BatchUnit> units;
     // device data of host-only plans (fingerprint tables, long patterns),
     // uploaded with the descriptors; per pair the blob offsets (or kNoBlob)

@@ -151,6 +151,11 @@ struct BatchTextDesc {
 constexpr uint32_t kGroupMax = 32;
 constexpr int kGroupBits = 10;
 constexpr uint32_t kGroupBuckets = 1u << kGroupBits;
+// A group's table in memory: the kGroupBuckets member masks, then a bitmap
+// of the buckets that are not empty (one bit per bucket, kGroupBuckets / 32
+// words: one word per LDS bank, so lanes testing any buckets never conflict).
+constexpr uint32_t kGroupBitmapWords = kGroupBuckets / 32;
+constexpr uint32_t kGroupTableWords = kGroupBuckets + kGroupBitmapWords;
 // A text's word patterns are grouped only when it has at least this many.
 constexpr uint32_t kGroupMin = 4;
 
@@ -185,7 +190,7 @@ struct BatchArgs {
     const uint32_t *solo_order;
     const BatchGroupDesc *groups;
     const uint32_t *group_pairs;
-    const uint32_t *group_tables;  // [groups][kGroupBuckets]
+    const uint32_t *group_tables;  // [groups][kGroupTableWords]
     const BatchUnit *units;
     uint32_t *pt_count;        // [entries] hits of each (pair, tile)
     const uint64_t *pt_offset; // [entries + 1] exclusive prefix of pt_count (write pass)

@@ -157,15 +157,22 @@ def cmd_requests(args):
         if args.kernel not in r["Kernel_Name"]:
             continue
         disp.setdefault(int(r["Dispatch_Id"]), {"name": r["Kernel_Name"]})[r["Counter_Name"]] = float(r["Counter_Value"])
+    labels = args.labels.split(",") if args.labels else []
+    items = sorted(disp.items())
+    if labels:  # only the labelled dispatches, the first ones of the run
+        items = items[:len(labels)]
+    ratio = f" {'text / fetched':>15}" if args.text_bytes else ""
     lines = [f"# {args.title}", f"command: {args.command}", "",
-             f"{'dispatch':>8} {'RDREQ':>12} {'RDREQ_128B':>12} {'RDREQ_32B':>10} {'BUBBLE':>8} "
-             f"{'128B x 128 (MB)':>16} {'FETCH_SIZE formula (MB)':>24}  kernel"]
-    for k, d in sorted(disp.items()):
+             f"{'dispatch':>14} {'RDREQ':>12} {'RDREQ_128B':>12} {'RDREQ_32B':>10} {'BUBBLE':>8} "
+             f"{'128B x 128 (MB)':>16} {'FETCH_SIZE formula (MB)':>24}{ratio}  kernel"]
+    for i, (k, d) in enumerate(items):
         rq, r128 = d.get("TCC_EA0_RDREQ_sum", 0), d.get("TCC_EA0_RDREQ_128B_sum", 0)
         r32, bub = d.get("TCC_EA0_RDREQ_32B_sum", 0), d.get("TCC_BUBBLE_sum", 0)
         formula = (bub * 128 + (rq - bub - r32) * 64 + r32 * 32) / 1e6
-        lines.append(f"{k:8d} {rq:12.0f} {r128:12.0f} {r32:10.0f} {bub:8.0f} {r128 * 128 / 1e6:16.1f} "
-                     f"{formula:24.1f}  {d['name'][:50]}")
+        lab = labels[i] if labels else str(k)
+        r = f" {args.text_bytes / max(r128 * 128, 1):15.2f}" if args.text_bytes else ""
+        lines.append(f"{lab:>14} {rq:12.0f} {r128:12.0f} {r32:10.0f} {bub:8.0f} {r128 * 128 / 1e6:16.1f} "
+                     f"{formula:24.1f}{r}  {d['name'][:50]}")
     text = "\n".join(lines) + "\n"
     with open(args.out, "w") as f:
         f.write(text)
@@ -271,6 +278,8 @@ def main(argv=None):
     r.add_argument("dir")
     r.add_argument("--kernel", default="")
     r.add_argument("--title", default="L2 read requests by size")
+    r.add_argument("--labels", default="", help="comma-separated names of the first dispatches; only those are listed")
+    r.add_argument("--text-bytes", type=int, default=0, help="bytes of text each dispatch scans (adds text / fetched)")
     r.add_argument("--command", required=True)
     r.add_argument("--out", required=True)
     args = ap.parse_args(argv)
