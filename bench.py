@@ -429,6 +429,9 @@ def run_serve_workload(args, torch, W, epsm):
     sat_qps = n_q / wall
     points = [{"load": "burst", "qps": round(sat_qps, 1), "wall_s": round(wall, 3),
                "gbs": round(logical(burst) / wall / 1e9, 1),
+               # the batch kernel's ALU roofline over the whole burst, host
+               # staging and copies included (wall clock, not kernel time)
+               "alu_frac": round(ALU_OPS_PER_PAIR_BYTE * logical(burst) / wall / 1e12 / VALU_INT32_PEAK_TOPS, 4),
                "p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 2),
                "p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 2),
                "mean_batch_queries": round(float(np.mean([o.batch_queries for o in outs])), 2)}]

@@ -521,10 +521,8 @@ epsm_status run_search(epsm_plan_t plan, const uint8_t *d_text, uint64_t n, int6
 int g_batch_waves = 8;  // batch tile = g_batch_waves KiB
 
 BatchPtrs batch_ptrs(uint8_t *base, const BatchLayout &L) {
-    return {(BatchTextDesc *)(base + L.texts), (BatchPairDesc *)(base + L.pairs),
-            (uint32_t *)(base + L.order), (uint32_t *)(base + L.solo),
-            (BatchGroupDesc *)(base + L.groups), (uint32_t *)(base + L.gpairs),
-            (uint32_t *)(base + L.gtables), (BatchUnit *)(base + L.units),
+    return {(BatchTextDesc *)(base + L.texts), (BatchPairDesc *)(base + L.kpairs),
+            (BatchSpan *)(base + L.spans), (uint32_t *)(base + L.gtables), (BatchUnit *)(base + L.units),
             (uint32_t *)(base + L.ptc), (uint64_t *)(base + L.pto), (uint64_t *)(base + L.bsum)};
 }
 
@@ -611,50 +609,46 @@ epsm_status build_batch(const epsm_batch *b, int waves, HostBatch &hb, bool chec
         hb.blob_table[k] = it->second.first;
         hb.blob_pattern[k] = it->second.second;
     }
-    // pairs grouped by text (pair order kept within a text)
+    // pairs grouped by text (the caller's order kept within a text)
     std::vector<uint32_t> start(b->n_texts + 1, 0);
     for (uint32_t i = 0; i < b->n_texts; ++i) start[i + 1] = start[i] + text_pairs[i];
-    hb.order.assign(start[b->n_texts], 0);
+    std::vector<uint32_t> order(start[b->n_texts], 0);
     std::vector<uint32_t> fillp(start.begin(), start.end() - 1);
     for (uint32_t k = 0; k < b->n_pairs; ++k)
-        if (hb.pairs[k].tiles) hb.order[fillp[hb.pairs[k].text]++] = k;
+        if (hb.pairs[k].tiles) order[fillp[hb.pairs[k].text]++] = k;
     uint64_t units = 0;
-    for (uint32_t i = 0; i < b->n_texts; ++i) {
-        hb.texts[i].pair_begin = start[i];
-        hb.texts[i].pair_end = start[i + 1];
+    for (uint32_t i = 0; i < b->n_texts; ++i)
         if (text_pairs[i]) units += text_tiles[i];
-    }
-    // count pass: a text with at least kGroupMin patterns of m >= 4 filters
-    // them in groups of up to kGroupMax through one bucket table of their
-    // first four bytes; its other pairs are filtered one by one
+    // kernel order: a text with at least kGroupMin patterns of m >= 4 filters
+    // them in the count pass in groups of up to kGroupMax through one bucket
+    // table of their first four bytes; its other pairs, filtered one by one,
+    // come first
+    hb.korder.reserve(order.size());
     for (uint32_t i = 0; i < b->n_texts; ++i) {
         BatchTextDesc &d = hb.texts[i];
         uint32_t words = 0;
-        for (uint32_t q = start[i]; q < start[i + 1]; ++q) words += hb.pairs[hb.order[q]].plan.m >= 4;
+        for (uint32_t q = start[i]; q < start[i + 1]; ++q) words += hb.pairs[order[q]].plan.m >= 4;
         const bool grouped = group && words >= kGroupMin;
-        d.solo_begin = (uint32_t)hb.solo.size();
+        d.pair_begin = (uint32_t)hb.korder.size();
         for (uint32_t q = start[i]; q < start[i + 1]; ++q)
-            if (!grouped || hb.pairs[hb.order[q]].plan.m < 4) hb.solo.push_back(hb.order[q]);
-        d.solo_end = (uint32_t)hb.solo.size();
-        d.group_begin = (uint32_t)hb.groups.size();
+            if (!grouped || hb.pairs[order[q]].plan.m < 4) hb.korder.push_back(order[q]);
+        d.solo_end = (uint32_t)hb.korder.size();
+        d.group_begin = (uint32_t)(hb.group_tables.size() / kGroupTableWords);
         if (grouped) {
             for (uint32_t q = start[i]; q < start[i + 1]; ++q) {
-                const uint32_t k = hb.order[q];
+                const uint32_t k = order[q];
                 if (hb.pairs[k].plan.m < 4) continue;
-                if (hb.groups.size() == d.group_begin || hb.groups.back().count == kGroupMax) {
-                    hb.groups.push_back({(uint32_t)hb.group_pairs.size(), 0});
-                    hb.group_tables.resize(hb.group_tables.size() + kGroupTableWords, 0);
-                }
-                BatchGroupDesc &g = hb.groups.back();
+                const uint32_t member = (uint32_t)(hb.korder.size() - d.solo_end) % kGroupMax;
+                if (member == 0) hb.group_tables.resize(hb.group_tables.size() + kGroupTableWords, 0);
                 const uint32_t bucket = group_bucket(hb.pairs[k].plan.pw[0]);
-                uint32_t *table = hb.group_tables.data() + (hb.groups.size() - 1) * kGroupTableWords;
-                table[bucket] |= 1u << g.count;
+                uint32_t *table = hb.group_tables.data() + hb.group_tables.size() - kGroupTableWords;
+                table[bucket] |= 1u << member;
                 table[kGroupBuckets + bucket / 32] |= 1u << (bucket % 32);
-                hb.group_pairs.push_back(k);
-                g.count++;
+                hb.korder.push_back(k);
             }
         }
-        d.group_end = (uint32_t)hb.groups.size();
+        d.pair_end = (uint32_t)hb.korder.size();
+        d.group_end = (uint32_t)(hb.group_tables.size() / kGroupTableWords);
     }
     if (units > 0x7FFFFFFFull) return fail(EPSM_EUNSUPPORTED, "batch has too many tiles");
     hb.units.reserve(units);
@@ -685,11 +679,12 @@ epsm_status upload_batch(HostBatch &hb, const BatchLayout &L, uint8_t *dev, hipS
     };
     put(L.blob, hb.blob.data(), hb.blob.size());
     put(L.texts, hb.texts.data(), hb.texts.size() * sizeof(BatchTextDesc));
-    put(L.pairs, hb.pairs.data(), hb.pairs.size() * sizeof(BatchPairDesc));
-    put(L.order, hb.order.data(), hb.order.size() * sizeof(uint32_t));
-    put(L.solo, hb.solo.data(), hb.solo.size() * sizeof(uint32_t));
-    put(L.groups, hb.groups.data(), hb.groups.size() * sizeof(BatchGroupDesc));
-    put(L.gpairs, hb.group_pairs.data(), hb.group_pairs.size() * sizeof(uint32_t));
+    for (size_t i = 0; i < hb.korder.size(); ++i)
+        put(L.kpairs + i * sizeof(BatchPairDesc), &hb.pairs[hb.korder[i]], sizeof(BatchPairDesc));
+    for (size_t k = 0; k < hb.pairs.size(); ++k) {
+        const BatchSpan sp{hb.pairs[k].cnt_base, hb.pairs[k].tiles};
+        put(L.spans + k * sizeof(BatchSpan), &sp, sizeof(sp));
+    }
     put(L.gtables, hb.group_tables.data(), hb.group_tables.size() * sizeof(uint32_t));
     put(L.units, hb.units.data(), hb.units.size() * sizeof(BatchUnit));
     e = hipMemcpyAsync(dev, h, bytes, hipMemcpyHostToDevice, s);
@@ -709,11 +704,7 @@ epsm_status run_batch_count(const BatchPtrs &P, const HostBatch &hb, const epsm_
                             hipStream_t s) {
     BatchArgs a{};
     a.texts = P.texts;
-    a.pairs = P.pairs;
-    a.pair_order = P.order;
-    a.solo_order = P.solo;
-    a.groups = P.groups;
-    a.group_pairs = P.gpairs;
+    a.kpairs = P.kpairs;
     a.group_tables = P.gtables;
     a.units = P.units;
     a.pt_count = P.ptc;
@@ -722,7 +713,7 @@ epsm_status run_batch_count(const BatchPtrs &P, const HostBatch &hb, const epsm_
     hipError_t e = launch_batch(a, hb.waves, (uint32_t)hb.units.size(), s);
     if (e == hipSuccess) e = launch_scan_counts(P.ptc, hb.entries, P.pto, P.bsum, s);
     if (e == hipSuccess)
-        e = launch_batch_finalize(P.pairs, (uint32_t)hb.pairs.size(), P.pto, hb.entries, o.d_counts,
+        e = launch_batch_finalize(P.spans, (uint32_t)hb.pairs.size(), P.pto, hb.entries, o.d_counts,
                                   o.d_offsets, o.d_total, s);
     return e == hipSuccess ? EPSM_OK : hip_fail(e, "batch launch (count)");
 }
@@ -732,8 +723,7 @@ epsm_status run_batch_write(const BatchPtrs &P, const HostBatch &hb, const epsm_
     if (!o.write || !o.cap) return EPSM_OK;
     BatchArgs a{};
     a.texts = P.texts;
-    a.pairs = P.pairs;
-    a.pair_order = P.order;
+    a.kpairs = P.kpairs;
     a.units = P.units;
     a.pt_count = P.ptc;
     a.pt_offset = P.pto;
@@ -1103,13 +1093,9 @@ epsm_status epsm_batch_prepare(const epsm_batch *batch, epsm_batch_plan_t *out) 
     // descriptors stay on the device; the host copies are no longer needed
     bp->hb.texts.clear();
     bp->hb.texts.shrink_to_fit();
-    bp->hb.order.clear();
-    bp->hb.order.shrink_to_fit();
+    bp->hb.korder = std::vector<uint32_t>();
     bp->hb.blob.clear();
     bp->hb.blob.shrink_to_fit();
-    bp->hb.solo = std::vector<uint32_t>();
-    bp->hb.groups = std::vector<BatchGroupDesc>();
-    bp->hb.group_pairs = std::vector<uint32_t>();
     bp->hb.group_tables = std::vector<uint32_t>();
     bp->hb.units.shrink_to_fit();
     *out = bp;

@@ -92,12 +92,66 @@ __device__ __forceinline__ void group_count(const uint32_t (&w)[kBatchNL * 4 + 1
     }
 }
 
+// Count pass over the groups of the unit's text (after its solo pairs): the
+// piece goes to LDS once (windows at run-time offsets), then each group's
+// table, first words and lengths are staged in turn.
 template <int WAVES>
-__global__ __launch_bounds__(WAVES * kWave) void batch_kernel(BatchArgs a) {
+__device__ __forceinline__ void batch_groups(const BatchArgs &a, const BatchUnit &unit, const BatchTextDesc &t,
+                                             const uint32_t (&w)[kBatchNL * 4 + 1], uint64_t s0) {
+    constexpr int kThreads = WAVES * kWave;
+    const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
+    if (t.group_begin == t.group_end) return;
+    __shared__ uint32_t s_text[WAVES][kTextWords];
+    __shared__ uint32_t s_tab[kGroupTableWords];
+    __shared__ uint32_t s_pw[kGroupMax][8], s_pm[kGroupMax][8];
+    __shared__ uint64_t s_m[kGroupMax];
+    __shared__ const uint8_t *s_pat[kGroupMax];
+    __shared__ uint32_t s_cnt[kGroupMax];
+    __shared__ uint64_t s_cb[kGroupMax];
+    uint32_t *tw = s_text[wave];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) tw[lane * 4 + i] = w[i];
+    if (lane == kWave - 1) {
+#pragma unroll
+        for (int i = 0; i < 8; ++i) tw[kWavePiece / 4 + i] = w[4 + i];
+        tw[kTextWords - 1] = 0;
+    }
+#pragma unroll 1
+    for (uint32_t g = t.group_begin; g < t.group_end; ++g) {
+        // members: the next kGroupMax (or fewer) grouped pairs of the text
+        const uint32_t first = t.solo_end + (g - t.group_begin) * kGroupMax;
+        const uint32_t count = min(kGroupMax, t.pair_end - first);
+        const uint32_t *gt = a.group_tables + (size_t)g * kGroupTableWords;
+        for (uint32_t i = tid; i < kGroupTableWords; i += kThreads) s_tab[i] = gt[i];
+        for (uint32_t i = tid; i < count * 8; i += kThreads) {
+            const BatchPairDesc &pd = a.kpairs[first + i / 8];
+            s_pw[i / 8][i % 8] = pd.plan.pw[i % 8];
+            s_pm[i / 8][i % 8] = pd.plan.pmask[i % 8];
+            if (i % 8 == 0) {
+                s_m[i / 8] = pd.plan.m;
+                s_pat[i / 8] = pd.plan.pattern;
+                s_cb[i / 8] = pd.cnt_base;
+                s_cnt[i / 8] = 0;
+            }
+        }
+        __syncthreads();
+        group_count(w, tw, s_tab, s_pw, s_pm, s_m, s_pat, s_cnt, t, s0, (uint32_t)lane * kPiece);
+        __syncthreads();
+        if ((uint32_t)tid < count) a.pt_count[s_cb[tid] + unit.tile] = s_cnt[tid];
+        __syncthreads();  // s_cnt and the staged group are rewritten next
+    }
+}
+
+// One unit of the count pass (WRITE false) or of the write pass (WRITE
+// true).  The two passes are separate kernels so that each allocates only
+// its own LDS: the count pass has no position stage, the write pass no group
+// tables.
+template <int WAVES, bool WRITE>
+__device__ __forceinline__ void batch_unit(const BatchArgs &a) {
     constexpr int kThreads = WAVES * kWave;
     constexpr uint32_t kTileB = WAVES * kWavePiece;
     __shared__ uint32_t s_wcnt[WAVES];
-    __shared__ uint32_t s_stage[WAVES][kStage];
+    __shared__ uint32_t s_stage[WRITE ? WAVES : 1][WRITE ? kStage : 1];
     const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
 
     const BatchUnit unit = a.units[blockIdx.x];
@@ -114,16 +168,14 @@ __global__ __launch_bounds__(WAVES * kWave) void batch_kernel(BatchArgs a) {
     // wave-uniform load), so the tile crosses the cache hierarchy once
     uint32_t wl[1][kBatchNL * 4 + 1];
     load_chunk<1, kBatchNL>(wl, rsrc, lane_off);
-    fill_halo<kBatchNL>(wl[0]);
     uint32_t (&w)[kBatchNL * 4 + 1] = wl[0];
 
     // the count pass filters the solo pairs one by one and the groups
     // together; the write pass redoes, pair by pair, only entries with hits.
     // Pair descriptors are staged in LDS a chunk at a time, so the loop over
     // pairs waits on no global load.
-    const uint32_t *order = a.write ? a.pair_order : a.solo_order;
-    const uint32_t pb = a.write ? t.pair_begin : t.solo_begin;
-    const uint32_t pe = a.write ? t.pair_end : t.solo_end;
+    const uint32_t pb = t.pair_begin;
+    const uint32_t pe = WRITE ? t.pair_end : t.solo_end;
     const int64_t wave_pos0 = (int64_t)(tile_start + (uint64_t)wave * kWavePiece) - (int64_t)t.delta;
     constexpr uint32_t kDescWords = sizeof(BatchPairDesc) / 4;
     static_assert(sizeof(BatchPairDesc) % 4 == 0, "descriptors are copied as words");
@@ -134,21 +186,22 @@ __global__ __launch_bounds__(WAVES * kWave) void batch_kernel(BatchArgs a) {
     for (uint32_t cb = pb; cb < pe; cb += kPairChunk) {
         const uint32_t nc = min(kPairChunk, pe - cb);
         for (uint32_t i = tid; i < nc * kDescWords; i += kThreads)
-            reinterpret_cast<uint32_t *>(s_pd)[i] =
-                reinterpret_cast<const uint32_t *>(&a.pairs[order[cb + i / kDescWords]])[i % kDescWords];
+            reinterpret_cast<uint32_t *>(s_pd)[i] = reinterpret_cast<const uint32_t *>(a.kpairs + cb)[i];
         if ((uint32_t)tid < nc) {
-            const BatchPairDesc &pd = a.pairs[order[cb + tid]];
-            const uint64_t entry = pd.cnt_base + unit.tile;
-            const bool live = pd.tiles != 0;  // m > n: the pair has no entries
-            s_pcnt[tid] = a.write && live ? a.pt_count[entry] : 0;
-            s_poff[tid] = a.write && live ? a.pt_offset[entry] : 0;
+            if constexpr (WRITE) {
+                const uint64_t entry = a.kpairs[cb + tid].cnt_base + unit.tile;
+                s_pcnt[tid] = a.pt_count[entry];
+                s_poff[tid] = a.pt_offset[entry];
+            } else {
+                s_pcnt[tid] = 0;
+            }
         }
         __syncthreads();
+        if (cb == pb) fill_halo<kBatchNL>(wl[0]);
 #pragma unroll 1
         for (uint32_t j = 0; j < nc; ++j) {
             const BatchPairDesc &pd = s_pd[j];
-            if (pd.tiles == 0) continue;
-            if (a.write && s_pcnt[j] == 0) continue;
+            if (WRITE && s_pcnt[j] == 0) continue;
             const DevPlan &p = pd.plan;
             uint32_t mk = any_mask(w, p);
             const uint64_t last = t.delta + t.n - p.m;  // m <= n here
@@ -158,85 +211,61 @@ __global__ __launch_bounds__(WAVES * kWave) void batch_kernel(BatchArgs a) {
             const uint32_t c = __popc(mk);
             const uint32_t incl = wave_incl_scan32(c);
             const uint32_t wtot = last_lane(incl);
-            if (!a.write) {
+            if constexpr (!WRITE) {
                 // count pass: waves add their totals; no barrier per pair
                 if (lane == 0 && wtot) atomicAdd(&s_pcnt[j], wtot);
-                continue;
-            }
-            if (lane == 0) s_wcnt[wave] = wtot;
-            __syncthreads();
-            if (wtot) {
-                uint64_t obase = s_poff[j];
-                for (int i = 0; i < wave; ++i) obase += s_wcnt[i];
-                uint32_t at = incl - c;
-                const uint32_t rel0 = (uint32_t)lane * kPiece;
-                uint32_t bits = mk;
-                while (bits) {
-                    const uint32_t k = __builtin_ctz(bits);
-                    bits &= bits - 1;
-                    s_stage[wave][at++] = rel0 + k;
+            } else {
+                if (lane == 0) s_wcnt[wave] = wtot;
+                __syncthreads();
+                if (wtot) {
+                    uint64_t obase = s_poff[j];
+                    for (int i = 0; i < wave; ++i) obase += s_wcnt[i];
+                    uint32_t at = incl - c;
+                    const uint32_t rel0 = (uint32_t)lane * kPiece;
+                    uint32_t bits = mk;
+                    while (bits) {
+                        const uint32_t k = __builtin_ctz(bits);
+                        bits &= bits - 1;
+                        s_stage[wave][at++] = rel0 + k;
+                    }
+                    flush_stage(s_stage[wave], wtot, a.out, a.cap, obase, wave_pos0, lane);
                 }
-                flush_stage(s_stage[wave], wtot, a.out, a.cap, obase, wave_pos0, lane);
+                __syncthreads();  // s_wcnt is rewritten by the next pattern
             }
-            __syncthreads();  // s_wcnt is rewritten by the next pattern
         }
         __syncthreads();
-        if (!a.write && (uint32_t)tid < nc && s_pd[tid].tiles)
-            a.pt_count[s_pd[tid].cnt_base + unit.tile] = s_pcnt[tid];
+        if (!WRITE && (uint32_t)tid < nc) a.pt_count[s_pd[tid].cnt_base + unit.tile] = s_pcnt[tid];
         __syncthreads();  // the next chunk restages s_pd and s_pcnt
     }
-    if (a.write || t.group_begin == t.group_end) return;
+    if (pb == pe) fill_halo<kBatchNL>(wl[0]);
+    if constexpr (!WRITE) batch_groups<WAVES>(a, unit, t, w, s0);
+}
 
-    // groups: the piece goes to LDS once (windows at run-time offsets), then
-    // each group's table, first words and lengths are staged in turn
-    __shared__ uint32_t s_text[WAVES][kTextWords];
-    __shared__ uint32_t s_tab[kGroupTableWords];
-    __shared__ uint32_t s_pw[kGroupMax][8], s_pm[kGroupMax][8];
-    __shared__ uint64_t s_m[kGroupMax];
-    __shared__ const uint8_t *s_pat[kGroupMax];
-    __shared__ uint32_t s_cnt[kGroupMax];
-    uint32_t *tw = s_text[wave];
-#pragma unroll
-    for (int i = 0; i < 4; ++i) tw[lane * 4 + i] = w[i];
-    if (lane == kWave - 1) {
-#pragma unroll
-        for (int i = 0; i < 8; ++i) tw[kWavePiece / 4 + i] = w[4 + i];
-        tw[kTextWords - 1] = 0;
-    }
-#pragma unroll 1
-    for (uint32_t g = t.group_begin; g < t.group_end; ++g) {
-        const BatchGroupDesc gd = a.groups[g];
-        const uint32_t *gt = a.group_tables + (size_t)g * kGroupTableWords;
-        for (uint32_t i = tid; i < kGroupTableWords; i += kThreads) s_tab[i] = gt[i];
-        for (uint32_t i = tid; i < gd.count * 8; i += kThreads) {
-            const DevPlan &p = a.pairs[a.group_pairs[gd.first + i / 8]].plan;
-            s_pw[i / 8][i % 8] = p.pw[i % 8];
-            s_pm[i / 8][i % 8] = p.pmask[i % 8];
-            if (i % 8 == 0) {
-                s_m[i / 8] = p.m;
-                s_pat[i / 8] = p.pattern;
-                s_cnt[i / 8] = 0;
-            }
-        }
-        __syncthreads();
-        group_count(w, tw, s_tab, s_pw, s_pm, s_m, s_pat, s_cnt, t, s0, (uint32_t)lane * kPiece);
-        __syncthreads();
-        if ((uint32_t)tid < gd.count) {
-            const BatchPairDesc &pd = a.pairs[a.group_pairs[gd.first + tid]];
-            a.pt_count[pd.cnt_base + unit.tile] = s_cnt[tid];
-        }
-        __syncthreads();  // s_cnt and the staged group are rewritten next
-    }
+template <int WAVES>
+__global__ __launch_bounds__(WAVES * kWave) __attribute__((amdgpu_waves_per_eu(5, 8))) void batch_kernel_count(BatchArgs a) {
+    batch_unit<WAVES, false>(a);
+}
+
+template <int WAVES>
+__global__ __launch_bounds__(WAVES * kWave) void batch_kernel_write(BatchArgs a) {
+    batch_unit<WAVES, true>(a);
 }
 
 bool batch_waves_supported(int waves) { return waves == 4 || waves == 8 || waves == 16; }
 
 hipError_t launch_batch(const BatchArgs &a, int waves, uint32_t n_units, hipStream_t s) {
     if (n_units == 0) return hipSuccess;
+    auto launch = [&](auto waves_c) {
+        constexpr int W = decltype(waves_c)::value;
+        if (a.write)
+            hipLaunchKernelGGL(batch_kernel_write<W>, dim3(n_units), dim3(W * kWave), 0, s, a);
+        else
+            hipLaunchKernelGGL(batch_kernel_count<W>, dim3(n_units), dim3(W * kWave), 0, s, a);
+    };
     switch (waves) {
-        case 4: hipLaunchKernelGGL(batch_kernel<4>, dim3(n_units), dim3(4 * kWave), 0, s, a); break;
-        case 8: hipLaunchKernelGGL(batch_kernel<8>, dim3(n_units), dim3(8 * kWave), 0, s, a); break;
-        case 16: hipLaunchKernelGGL(batch_kernel<16>, dim3(n_units), dim3(16 * kWave), 0, s, a); break;
+        case 4: launch(std::integral_constant<int, 4>()); break;
+        case 8: launch(std::integral_constant<int, 8>()); break;
+        case 16: launch(std::integral_constant<int, 16>()); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -332,24 +361,24 @@ hipError_t launch_scan_counts(const uint32_t *counts, uint64_t entries, uint64_t
     return hipGetLastError();
 }
 
-__global__ void batch_finalize_kernel(const BatchPairDesc *pairs, uint32_t n_pairs,
+__global__ void batch_finalize_kernel(const BatchSpan *spans, uint32_t n_pairs,
                                       const uint64_t *offsets, uint64_t entries, uint64_t *counts,
                                       uint64_t *pair_offsets, uint64_t *total) {
     const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k < n_pairs) {
-        const uint64_t b = pairs[k].cnt_base;
-        const uint64_t begin = offsets[b], end = offsets[b + pairs[k].tiles];
+        const uint64_t b = spans[k].cnt_base;
+        const uint64_t begin = offsets[b], end = offsets[b + spans[k].tiles];
         pair_offsets[k] = begin;
         counts[k] = end - begin;
     }
     if (k == 0 && total) *total = offsets[entries];
 }
 
-hipError_t launch_batch_finalize(const BatchPairDesc *pairs, uint32_t n_pairs,
+hipError_t launch_batch_finalize(const BatchSpan *spans, uint32_t n_pairs,
                                  const uint64_t *offsets, uint64_t entries, uint64_t *counts,
                                  uint64_t *pair_offsets, uint64_t *total, hipStream_t s) {
     const uint32_t blocks = n_pairs ? (n_pairs + 255) / 256 : 1;
-    hipLaunchKernelGGL(batch_finalize_kernel, dim3(blocks), dim3(256), 0, s, pairs, n_pairs, offsets,
+    hipLaunchKernelGGL(batch_finalize_kernel, dim3(blocks), dim3(256), 0, s, spans, n_pairs, offsets,
                        entries, counts, pair_offsets, total);
     return hipGetLastError();
 }

@@ -41,11 +41,10 @@ epsm_status check_plan(epsm_plan_t plan);
 
 struct HostBatch {
     std::vector<BatchTextDesc> texts;
-    std::vector<BatchPairDesc> pairs;
-    std::vector<uint32_t> order;
-    std::vector<uint32_t> solo;            // count pass: pairs filtered alone
-    std::vector<BatchGroupDesc> groups;    // count pass: pattern groups
-    std::vector<uint32_t> group_pairs;
+    std::vector<BatchPairDesc> pairs;      // the caller's order
+    // kernel order (indices into pairs, pairs with entries only): per text,
+    // its pairs filtered alone, then its grouped pairs, kGroupMax a group
+    std::vector<uint32_t> korder;
     std::vector<uint32_t> group_tables;    // kGroupTableWords per group (masks, then bitmap)
     std::vector<BatchUnit> units;
     // device data of host-only plans (fingerprint tables, long patterns),
@@ -60,17 +59,14 @@ constexpr uint64_t kNoBlob = ~uint64_t(0);
 // Byte layout of the device copy of a batch: descriptors, then the
 // (pair, tile) counts, their offsets and the scan's block sums.
 struct BatchLayout {
-    size_t blob, texts, pairs, order, solo, groups, gpairs, gtables, units, ptc, pto, bsum, total;
+    size_t blob, texts, kpairs, spans, gtables, units, ptc, pto, bsum, total;
     explicit BatchLayout(const HostBatch &hb) {
         auto up = [](size_t x) { return (x + 255) & ~size_t(255); };
         size_t at = 0;
         blob = at; at += up(hb.blob.size());
         texts = at; at += up(hb.texts.size() * sizeof(BatchTextDesc));
-        pairs = at; at += up(hb.pairs.size() * sizeof(BatchPairDesc));
-        order = at; at += up(hb.order.size() * sizeof(uint32_t));
-        solo = at; at += up(hb.solo.size() * sizeof(uint32_t));
-        groups = at; at += up(hb.groups.size() * sizeof(BatchGroupDesc));
-        gpairs = at; at += up(hb.group_pairs.size() * sizeof(uint32_t));
+        kpairs = at; at += up(hb.korder.size() * sizeof(BatchPairDesc));
+        spans = at; at += up(hb.pairs.size() * sizeof(BatchSpan));
         gtables = at; at += up(hb.group_tables.size() * sizeof(uint32_t));
         units = at; at += up(hb.units.size() * sizeof(BatchUnit));
         ptc = at; at += up(hb.entries * sizeof(uint32_t));
@@ -82,11 +78,8 @@ struct BatchLayout {
 
 struct BatchPtrs {
     BatchTextDesc *texts;
-    BatchPairDesc *pairs;
-    uint32_t *order;
-    uint32_t *solo;
-    BatchGroupDesc *groups;
-    uint32_t *gpairs;
+    BatchPairDesc *kpairs;
+    BatchSpan *spans;
     uint32_t *gtables;
     BatchUnit *units;
     uint32_t *ptc;

@@ -136,12 +136,16 @@ struct BatchTextDesc {
     uint64_t delta;          // text start - base
     uint64_t n;              // text length
     uint64_t load_end;       // round_up(delta + n, 16)
-    uint32_t pair_begin;     // this text's pairs are pair_order[pair_begin, pair_end)
+    // this text's pairs are kpairs[pair_begin, pair_end): first those the
+    // count pass filters one by one, [pair_begin, solo_end), then those it
+    // filters in groups, kGroupMax to a group, through the bucket tables
+    // group_begin .. group_end - 1
+    uint32_t pair_begin;
+    uint32_t solo_end;
     uint32_t pair_end;
-    uint32_t solo_begin;     // count pass: pairs filtered one by one,
-    uint32_t solo_end;       //   solo_order[solo_begin, solo_end)
-    uint32_t group_begin;    // count pass: pattern groups filtered together,
-    uint32_t group_end;      //   groups[group_begin, group_end)
+    uint32_t group_begin;
+    uint32_t group_end;
+    uint32_t pad_;
 };
 
 // Multi-pattern count (several patterns of one text through one filter).
@@ -159,11 +163,6 @@ constexpr uint32_t kGroupTableWords = kGroupBuckets + kGroupBitmapWords;
 // A text's word patterns are grouped only when it has at least this many.
 constexpr uint32_t kGroupMin = 4;
 
-struct BatchGroupDesc {
-    uint32_t first;          // members are group_pairs[first, first + count)
-    uint32_t count;
-};
-
 // Bucket of a 4-byte window x (little endian): fold the top byte into the
 // low 24 bits, one 24-bit multiply, keep the top kGroupBits bits.
 __host__ __device__ inline uint32_t group_bucket(uint32_t x) {
@@ -178,6 +177,12 @@ struct BatchPairDesc {
     uint32_t tiles;          // entries of this pair: tiles of its text, 0 if m > n
 };
 
+// Entries of a pair in the caller's order (for its count and offset).
+struct BatchSpan {
+    uint64_t cnt_base;
+    uint64_t tiles;
+};
+
 struct BatchUnit {
     uint32_t text;
     uint32_t tile;
@@ -185,11 +190,7 @@ struct BatchUnit {
 
 struct BatchArgs {
     const BatchTextDesc *texts;
-    const BatchPairDesc *pairs;
-    const uint32_t *pair_order;
-    const uint32_t *solo_order;
-    const BatchGroupDesc *groups;
-    const uint32_t *group_pairs;
+    const BatchPairDesc *kpairs;   // descriptors in kernel order: pairs with entries, per text contiguous
     const uint32_t *group_tables;  // [groups][kGroupTableWords]
     const BatchUnit *units;
     uint32_t *pt_count;        // [entries] hits of each (pair, tile)
@@ -206,7 +207,7 @@ bool batch_waves_supported(int waves);
 constexpr uint32_t kScanBlock = 4096;
 hipError_t launch_scan_counts(const uint32_t *counts, uint64_t entries, uint64_t *offsets,
                               uint64_t *block_sums, hipStream_t s);
-hipError_t launch_batch_finalize(const BatchPairDesc *pairs, uint32_t n_pairs,
+hipError_t launch_batch_finalize(const BatchSpan *spans, uint32_t n_pairs,
                                  const uint64_t *offsets, uint64_t entries, uint64_t *counts,
                                  uint64_t *pair_offsets, uint64_t *total, hipStream_t s);
 
