@@ -55,9 +55,7 @@ constexpr uint32_t kTextWords = kWavePiece / 4 + 8 + 1;
 // up to 32 bytes) and, past 32 bytes, the tail check.  Hits of member j are
 // added to s_cnt[j].
 __device__ __forceinline__ void group_count(const uint32_t (&w)[kBatchNL * 4 + 1], const uint32_t *tw,
-                                            const uint32_t *s_tab, const uint32_t (*s_pw)[8],
-                                            const uint32_t (*s_pm)[8], const uint64_t *s_m,
-                                            const uint8_t *const *s_pat, uint32_t *s_cnt,
+                                            const uint32_t *s_tab, const BatchPairDesc *s_gd, uint32_t *s_cnt,
                                             const BatchTextDesc &t, uint64_t s0, uint32_t lane_byte) {
     // first the bitmap of non-empty buckets (32 words, one per LDS bank: no
     // bank conflicts whatever buckets the lanes test), then, for the rare
@@ -79,35 +77,55 @@ __device__ __forceinline__ void group_count(const uint32_t (&w)[kBatchNL * 4 + 1
         while (members) {
             const uint32_t j = __builtin_ctz(members);
             members &= members - 1;
-            if (x != s_pw[j][0]) continue;
-            const uint64_t m = s_m[j];
+            const DevPlan &p = s_gd[j].plan;
+            if (x != p.pw[0]) continue;
+            const uint64_t m = p.m;
             if (s < t.delta || s > t.delta + t.n - m) continue;
             const uint32_t nw = m >= 32 ? 8u : (uint32_t)((m + 3) / 4);
             bool ok = true;
             for (uint32_t i = 1; i < nw && ok; ++i)
-                ok = (lds_window(tw, off + 4 * i) & s_pm[j][i]) == s_pw[j][i];
-            if (ok && m > 32) ok = tail_check(1u, s, t.base, s_pat[j], m, 32) != 0;
+                ok = (lds_window(tw, off + 4 * i) & p.pmask[i]) == p.pw[i];
+            if (ok && m > 32) ok = tail_check(1u, s, t.base, p.pattern, m, 32) != 0;
             if (ok) atomicAdd(&s_cnt[j], 1u);
         }
     }
 }
 
+// Copy n elements from global memory to LDS with all of the workgroup's
+// loads in flight at once: each thread loads its elements into registers,
+// then stores them (a plain copy loop waits on each load before its store,
+// one memory round trip per iteration).
+template <int THREADS, uint32_t MAXN, class T>
+__device__ __forceinline__ void stage(T *dst, const T *src, uint32_t n, int tid) {
+    constexpr int kPer = (int)((MAXN + THREADS - 1) / THREADS);
+    T v[kPer];
+#pragma unroll
+    for (int r = 0; r < kPer; ++r) {
+        const uint32_t i = (uint32_t)tid + (uint32_t)r * THREADS;
+        if (i < n) v[r] = src[i];
+    }
+#pragma unroll
+    for (int r = 0; r < kPer; ++r) {
+        const uint32_t i = (uint32_t)tid + (uint32_t)r * THREADS;
+        if (i < n) dst[i] = v[r];
+    }
+}
+
 // Count pass over the groups of the unit's text (after its solo pairs): the
 // piece goes to LDS once (windows at run-time offsets), then each group's
-// table, first words and lengths are staged in turn.
+// table and member descriptors are staged in turn (the members into s_gd,
+// the solo pairs' staging array, free by now).
 template <int WAVES>
 __device__ __forceinline__ void batch_groups(const BatchArgs &a, const BatchUnit &unit, const BatchTextDesc &t,
-                                             const uint32_t (&w)[kBatchNL * 4 + 1], uint64_t s0) {
+                                             const uint32_t (&w)[kBatchNL * 4 + 1], uint64_t s0,
+                                             BatchPairDesc *s_gd) {
     constexpr int kThreads = WAVES * kWave;
+    constexpr uint32_t kDescU64 = sizeof(BatchPairDesc) / 8;
     const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
     if (t.group_begin == t.group_end) return;
     __shared__ uint32_t s_text[WAVES][kTextWords];
-    __shared__ uint32_t s_tab[kGroupTableWords];
-    __shared__ uint32_t s_pw[kGroupMax][8], s_pm[kGroupMax][8];
-    __shared__ uint64_t s_m[kGroupMax];
-    __shared__ const uint8_t *s_pat[kGroupMax];
+    __shared__ __attribute__((aligned(16))) uint32_t s_tab[kGroupTableWords];
     __shared__ uint32_t s_cnt[kGroupMax];
-    __shared__ uint64_t s_cb[kGroupMax];
     uint32_t *tw = s_text[wave];
 #pragma unroll
     for (int i = 0; i < 4; ++i) tw[lane * 4 + i] = w[i];
@@ -123,21 +141,13 @@ __device__ __forceinline__ void batch_groups(const BatchArgs &a, const BatchUnit
         const uint32_t count = min(kGroupMax, t.pair_end - first);
         const uint32_t *gt = a.group_tables + (size_t)g * kGroupTableWords;
         for (uint32_t i = tid; i < kGroupTableWords; i += kThreads) s_tab[i] = gt[i];
-        for (uint32_t i = tid; i < count * 8; i += kThreads) {
-            const BatchPairDesc &pd = a.kpairs[first + i / 8];
-            s_pw[i / 8][i % 8] = pd.plan.pw[i % 8];
-            s_pm[i / 8][i % 8] = pd.plan.pmask[i % 8];
-            if (i % 8 == 0) {
-                s_m[i / 8] = pd.plan.m;
-                s_pat[i / 8] = pd.plan.pattern;
-                s_cb[i / 8] = pd.cnt_base;
-                s_cnt[i / 8] = 0;
-            }
-        }
+        const uint64_t *gd = reinterpret_cast<const uint64_t *>(a.kpairs + first);
+        for (uint32_t i = tid; i < count * kDescU64; i += kThreads) reinterpret_cast<uint64_t *>(s_gd)[i] = gd[i];
+        if ((uint32_t)tid < count) s_cnt[tid] = 0;
         __syncthreads();
-        group_count(w, tw, s_tab, s_pw, s_pm, s_m, s_pat, s_cnt, t, s0, (uint32_t)lane * kPiece);
+        group_count(w, tw, s_tab, s_gd, s_cnt, t, s0, (uint32_t)lane * kPiece);
         __syncthreads();
-        if ((uint32_t)tid < count) a.pt_count[s_cb[tid] + unit.tile] = s_cnt[tid];
+        if ((uint32_t)tid < count) a.pt_count[s_gd[tid].cnt_base + unit.tile] = s_cnt[tid];
         __syncthreads();  // s_cnt and the staged group are rewritten next
     }
 }
@@ -177,16 +187,17 @@ __device__ __forceinline__ void batch_unit(const BatchArgs &a) {
     const uint32_t pb = t.pair_begin;
     const uint32_t pe = WRITE ? t.pair_end : t.solo_end;
     const int64_t wave_pos0 = (int64_t)(tile_start + (uint64_t)wave * kWavePiece) - (int64_t)t.delta;
-    constexpr uint32_t kDescWords = sizeof(BatchPairDesc) / 4;
-    static_assert(sizeof(BatchPairDesc) % 4 == 0, "descriptors are copied as words");
+    constexpr uint32_t kDescU64 = sizeof(BatchPairDesc) / 8;
+    static_assert(sizeof(BatchPairDesc) % 8 == 0, "descriptors are copied as 8-byte words");
+    static_assert(kGroupTableWords % 4 == 0, "group tables are copied as 16-byte words");
     __shared__ BatchPairDesc s_pd[kPairChunk];
     __shared__ uint32_t s_pcnt[kPairChunk];
     __shared__ uint64_t s_poff[kPairChunk];
 #pragma unroll 1
     for (uint32_t cb = pb; cb < pe; cb += kPairChunk) {
         const uint32_t nc = min(kPairChunk, pe - cb);
-        for (uint32_t i = tid; i < nc * kDescWords; i += kThreads)
-            reinterpret_cast<uint32_t *>(s_pd)[i] = reinterpret_cast<const uint32_t *>(a.kpairs + cb)[i];
+        stage<kThreads, kPairChunk * kDescU64>(reinterpret_cast<uint64_t *>(s_pd),
+                                               reinterpret_cast<const uint64_t *>(a.kpairs + cb), nc * kDescU64, tid);
         if ((uint32_t)tid < nc) {
             if constexpr (WRITE) {
                 const uint64_t entry = a.kpairs[cb + tid].cnt_base + unit.tile;
@@ -206,6 +217,7 @@ __device__ __forceinline__ void batch_unit(const BatchArgs &a) {
             uint32_t mk = any_mask(w, p);
             const uint64_t last = t.delta + t.n - p.m;  // m <= n here
             if (tile_start + kTileB > last || tile_start < t.delta) mk &= valid_mask(s0, t.delta, last);
+            // the pattern is on the device only for plans with m > 4 * nw
             if (p.m > 4u * p.nw && wave_any(mk != 0))
                 mk = tail_check(mk, s0, t.base, p.pattern, p.m, 4u * p.nw);
             const uint32_t c = __popc(mk);
@@ -238,16 +250,16 @@ __device__ __forceinline__ void batch_unit(const BatchArgs &a) {
         __syncthreads();  // the next chunk restages s_pd and s_pcnt
     }
     if (pb == pe) fill_halo<kBatchNL>(wl[0]);
-    if constexpr (!WRITE) batch_groups<WAVES>(a, unit, t, w, s0);
+    if constexpr (!WRITE) batch_groups<WAVES>(a, unit, t, w, s0, s_pd);
 }
 
 template <int WAVES>
-__global__ __launch_bounds__(WAVES * kWave) __attribute__((amdgpu_waves_per_eu(5, 8))) void batch_kernel_count(BatchArgs a) {
+__global__ __launch_bounds__(WAVES * kWave) __attribute__((amdgpu_waves_per_eu(WAVES == 4 ? 6 : 5, 8))) void batch_kernel_count(BatchArgs a) {
     batch_unit<WAVES, false>(a);
 }
 
 template <int WAVES>
-__global__ __launch_bounds__(WAVES * kWave) void batch_kernel_write(BatchArgs a) {
+__global__ __launch_bounds__(WAVES * kWave) __attribute__((amdgpu_waves_per_eu(5, 8))) void batch_kernel_write(BatchArgs a) {
     batch_unit<WAVES, true>(a);
 }
 

@@ -181,6 +181,30 @@ def test_host_only_and_mixed_plans(epsm):
         assert np.array_equal(pos[offsets[k]:offsets[k] + counts[k]], exp), k
 
 
+def test_host_only_direct_plans_m17_to_32(epsm):
+    """Host-only direct plans of m in [17, 32] (three loads per lane, all of
+    the pattern compared from registers): their pattern is not uploaded, so
+    no pass may read it; cut patterns make every pass write positions."""
+    texts, host, _ = make_batch(seed=33, n_texts=24, min_len=2000)
+    rng = np.random.default_rng(33)
+    pairs = []
+    for ti, t in enumerate(host):
+        for m in (17, 20, 24, 31, 32):
+            if t.size < m:
+                continue
+            o = int(rng.integers(0, t.size - m + 1))
+            pairs.append((ti, epsm.Plan(t[o:o + m].tobytes(), epsm.PLAN_HOST_ONLY | epsm.PLAN_FORCE_DIRECT)))
+    assert any(pl.info()["run_blocks"] == 3 for _, pl in pairs)
+    say(f"host-only direct m 17..32: pairs={len(pairs)}")
+    pos, counts, offsets = epsm.search_batch(texts, pairs)
+    epsm.stream_check()
+    pos, counts, offsets = pos.cpu().numpy(), counts.cpu().numpy(), offsets.cpu().numpy()
+    for k, (ti, plan) in enumerate(pairs):
+        exp = oracle.positions(host[ti], plan.pattern)
+        assert exp.size >= 1
+        assert np.array_equal(pos[offsets[k]:offsets[k] + counts[k]], exp), k
+
+
 def test_long_patterns_in_batch(epsm):
     """m > 32 needs the tail check against the pattern in device memory."""
     rng = np.random.default_rng(77)
