@@ -91,23 +91,24 @@ __device__ __forceinline__ void group_count(const uint32_t (&w)[kBatchNL * 4 + 1
     }
 }
 
-// Copy n elements from global memory to LDS with all of the workgroup's
-// loads in flight at once: each thread loads its elements into registers,
-// then stores them (a plain copy loop waits on each load before its store,
-// one memory round trip per iteration).
-template <int THREADS, uint32_t MAXN, class T>
-__device__ __forceinline__ void stage(T *dst, const T *src, uint32_t n, int tid) {
-    constexpr int kPer = (int)((MAXN + THREADS - 1) / THREADS);
-    T v[kPer];
-#pragma unroll
-    for (int r = 0; r < kPer; ++r) {
-        const uint32_t i = (uint32_t)tid + (uint32_t)r * THREADS;
-        if (i < n) v[r] = src[i];
-    }
-#pragma unroll
-    for (int r = 0; r < kPer; ++r) {
-        const uint32_t i = (uint32_t)tid + (uint32_t)r * THREADS;
-        if (i < n) dst[i] = v[r];
+// Copy n 16-byte elements from global memory to LDS through the LDS DMA
+// path (buffer loads with the lds bit): each lane's element goes from memory
+// straight into LDS, wave w of round r writing elements r * THREADS + w * 64
+// + lane at its own base (lane i at base + 16 i).  The copy holds no data in
+// registers and all of the workgroup's loads are in flight at once; the
+// next __syncthreads() waits for them (vmcnt).
+typedef __attribute__((address_space(3))) void lds_void;
+template <int THREADS>
+__device__ __forceinline__ void stage_lds(void *dst, const void *src, uint32_t n, int tid) {
+    const __amdgpu_buffer_rsrc_t r = make_rsrc(static_cast<const uint8_t *>(src), n * 16);
+    // the wave index in a scalar register: the loop and the LDS bases are scalar
+    const uint32_t wave = __builtin_amdgcn_readfirstlane((uint32_t)tid / kWave);
+    const uint32_t lane = (uint32_t)tid & (kWave - 1);
+#pragma unroll 1
+    for (uint32_t base = wave * kWave; base < n; base += THREADS) {
+        if (base + lane < n)
+            __builtin_amdgcn_raw_ptr_buffer_load_lds(r, (lds_void *)(static_cast<uint4 *>(dst) + base), 16,
+                                                     (int)(lane * 16), (int)(base * 16), 0, 0);
     }
 }
 
@@ -120,7 +121,7 @@ __device__ __forceinline__ void batch_groups(const BatchArgs &a, const BatchUnit
                                              const uint32_t (&w)[kBatchNL * 4 + 1], uint64_t s0,
                                              BatchPairDesc *s_gd) {
     constexpr int kThreads = WAVES * kWave;
-    constexpr uint32_t kDescU64 = sizeof(BatchPairDesc) / 8;
+    constexpr uint32_t kDescU128 = sizeof(BatchPairDesc) / 16;
     const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
     if (t.group_begin == t.group_end) return;
     __shared__ uint32_t s_text[WAVES][kTextWords];
@@ -140,9 +141,8 @@ __device__ __forceinline__ void batch_groups(const BatchArgs &a, const BatchUnit
         const uint32_t first = t.solo_end + (g - t.group_begin) * kGroupMax;
         const uint32_t count = min(kGroupMax, t.pair_end - first);
         const uint32_t *gt = a.group_tables + (size_t)g * kGroupTableWords;
-        for (uint32_t i = tid; i < kGroupTableWords; i += kThreads) s_tab[i] = gt[i];
-        const uint64_t *gd = reinterpret_cast<const uint64_t *>(a.kpairs + first);
-        for (uint32_t i = tid; i < count * kDescU64; i += kThreads) reinterpret_cast<uint64_t *>(s_gd)[i] = gd[i];
+        stage_lds<kThreads>(s_tab, gt, kGroupTableWords / 4, tid);
+        stage_lds<kThreads>(s_gd, a.kpairs + first, count * kDescU128, tid);
         if ((uint32_t)tid < count) s_cnt[tid] = 0;
         __syncthreads();
         group_count(w, tw, s_tab, s_gd, s_cnt, t, s0, (uint32_t)lane * kPiece);
@@ -187,17 +187,16 @@ __device__ __forceinline__ void batch_unit(const BatchArgs &a) {
     const uint32_t pb = t.pair_begin;
     const uint32_t pe = WRITE ? t.pair_end : t.solo_end;
     const int64_t wave_pos0 = (int64_t)(tile_start + (uint64_t)wave * kWavePiece) - (int64_t)t.delta;
-    constexpr uint32_t kDescU64 = sizeof(BatchPairDesc) / 8;
-    static_assert(sizeof(BatchPairDesc) % 8 == 0, "descriptors are copied as 8-byte words");
-    static_assert(kGroupTableWords % 4 == 0, "group tables are copied as 16-byte words");
-    __shared__ BatchPairDesc s_pd[kPairChunk];
+    constexpr uint32_t kDescU128 = sizeof(BatchPairDesc) / 16;
+    static_assert(sizeof(BatchPairDesc) % 16 == 0, "descriptors are copied as 16-byte elements");
+    static_assert(kGroupTableWords % 4 == 0, "group tables are copied as 16-byte elements");
+    __shared__ __attribute__((aligned(16))) BatchPairDesc s_pd[kPairChunk];
     __shared__ uint32_t s_pcnt[kPairChunk];
     __shared__ uint64_t s_poff[kPairChunk];
 #pragma unroll 1
     for (uint32_t cb = pb; cb < pe; cb += kPairChunk) {
         const uint32_t nc = min(kPairChunk, pe - cb);
-        stage<kThreads, kPairChunk * kDescU64>(reinterpret_cast<uint64_t *>(s_pd),
-                                               reinterpret_cast<const uint64_t *>(a.kpairs + cb), nc * kDescU64, tid);
+        stage_lds<kThreads>(s_pd, a.kpairs + cb, nc * kDescU128, tid);
         if ((uint32_t)tid < nc) {
             if constexpr (WRITE) {
                 const uint64_t entry = a.kpairs[cb + tid].cnt_base + unit.tile;

@@ -175,6 +175,7 @@ struct BatchPairDesc {
     uint64_t cnt_base;       // first (pair, tile) entry of this pair
     uint32_t text;
     uint32_t tiles;          // entries of this pair: tiles of its text, 0 if m > n
+    uint32_t pad_[2];        // 160 bytes: copied to LDS as 16-byte elements
 };
 
 // Entries of a pair in the caller's order (for its count and offset).
