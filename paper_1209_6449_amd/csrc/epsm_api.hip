@@ -523,7 +523,8 @@ int g_batch_waves = 8;  // batch tile = g_batch_waves KiB
 BatchPtrs batch_ptrs(uint8_t *base, const BatchLayout &L) {
     return {(BatchTextDesc *)(base + L.texts), (BatchPairDesc *)(base + L.kpairs),
             (BatchSpan *)(base + L.spans), (uint32_t *)(base + L.gtables), (BatchUnit *)(base + L.units),
-            (uint32_t *)(base + L.ptc), (uint64_t *)(base + L.pto), (uint64_t *)(base + L.bsum)};
+            (uint32_t *)(base + L.park), (uint32_t *)(base + L.parkn), (uint32_t *)(base + L.ptc),
+            (uint64_t *)(base + L.pto), (uint64_t *)(base + L.bsum)};
 }
 
 epsm_status build_batch(const epsm_batch *b, int waves, HostBatch &hb, bool check_outputs,
@@ -707,6 +708,8 @@ epsm_status run_batch_count(const BatchPtrs &P, const HostBatch &hb, const epsm_
     a.kpairs = P.kpairs;
     a.group_tables = P.gtables;
     a.units = P.units;
+    a.park = P.park;
+    a.park_n = P.parkn;
     a.pt_count = P.ptc;
     a.pt_offset = P.pto;
     a.write = 0;
@@ -725,6 +728,8 @@ epsm_status run_batch_write(const BatchPtrs &P, const HostBatch &hb, const epsm_
     a.texts = P.texts;
     a.kpairs = P.kpairs;
     a.units = P.units;
+    a.park = P.park;
+    a.park_n = P.parkn;
     a.pt_count = P.ptc;
     a.pt_offset = P.pto;
     a.out = o.d_out;

@@ -56,7 +56,9 @@ constexpr uint32_t kTextWords = kWavePiece / 4 + 8 + 1;
 // added to s_cnt[j].
 __device__ __forceinline__ void group_count(const uint32_t (&w)[kBatchNL * 4 + 1], const uint32_t *tw,
                                             const uint32_t *s_tab, const BatchPairDesc *s_gd, uint32_t *s_cnt,
-                                            const BatchTextDesc &t, uint64_t s0, uint32_t lane_byte) {
+                                            uint32_t *s_park, uint32_t *s_npark, uint32_t member0,
+                                            const BatchTextDesc &t, uint64_t s0, uint32_t lane_byte,
+                                            uint32_t unit_off) {
     // first the bitmap of non-empty buckets (32 words, one per LDS bank: no
     // bank conflicts whatever buckets the lanes test), then, for the rare
     // windows whose bucket holds members, the member masks
@@ -86,7 +88,11 @@ __device__ __forceinline__ void group_count(const uint32_t (&w)[kBatchNL * 4 + 1
             for (uint32_t i = 1; i < nw && ok; ++i)
                 ok = (lds_window(tw, off + 4 * i) & p.pmask[i]) == p.pw[i];
             if (ok && m > 32) ok = tail_check(1u, s, t.base, p.pattern, m, 32) != 0;
-            if (ok) atomicAdd(&s_cnt[j], 1u);
+            if (ok) {
+                atomicAdd(&s_cnt[j], 1u);
+                const uint32_t q = atomicAdd(s_npark, 1u);
+                if (q < kParkMax) s_park[q] = ((member0 + j) << 16) | (unit_off + k);
+            }
         }
     }
 }
@@ -116,6 +122,9 @@ __device__ __forceinline__ void stage_lds(void *dst, const void *src, uint32_t n
 // piece goes to LDS once (windows at run-time offsets), then each group's
 // table and member descriptors are staged in turn (the members into s_gd,
 // the solo pairs' staging array, free by now).
+// The hits are also parked: listed in LDS as they are found, then sorted by
+// (member, offset) and stored as the unit's park list, whose length (or
+// kParkOverflow) goes to park_n.
 template <int WAVES>
 __device__ __forceinline__ void batch_groups(const BatchArgs &a, const BatchUnit &unit, const BatchTextDesc &t,
                                              const uint32_t (&w)[kBatchNL * 4 + 1], uint64_t s0,
@@ -123,10 +132,16 @@ __device__ __forceinline__ void batch_groups(const BatchArgs &a, const BatchUnit
     constexpr int kThreads = WAVES * kWave;
     constexpr uint32_t kDescU128 = sizeof(BatchPairDesc) / 16;
     const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
-    if (t.group_begin == t.group_end) return;
+    if (t.group_begin == t.group_end) {
+        if (tid == 0) a.park_n[blockIdx.x] = 0;
+        return;
+    }
     __shared__ uint32_t s_text[WAVES][kTextWords];
     __shared__ __attribute__((aligned(16))) uint32_t s_tab[kGroupTableWords];
     __shared__ uint32_t s_cnt[kGroupMax];
+    __shared__ uint32_t s_park[kParkMax];
+    __shared__ uint32_t s_npark;
+    if (tid == 0) s_npark = 0;  // ordered before the first hit by the staging barrier
     uint32_t *tw = s_text[wave];
 #pragma unroll
     for (int i = 0; i < 4; ++i) tw[lane * 4 + i] = w[i];
@@ -145,11 +160,22 @@ __device__ __forceinline__ void batch_groups(const BatchArgs &a, const BatchUnit
         stage_lds<kThreads>(s_gd, a.kpairs + first, count * kDescU128, tid);
         if ((uint32_t)tid < count) s_cnt[tid] = 0;
         __syncthreads();
-        group_count(w, tw, s_tab, s_gd, s_cnt, t, s0, (uint32_t)lane * kPiece);
+        group_count(w, tw, s_tab, s_gd, s_cnt, s_park, &s_npark, (g - t.group_begin) * kGroupMax, t, s0,
+                    (uint32_t)lane * kPiece, (uint32_t)wave * kWavePiece + (uint32_t)lane * kPiece);
         __syncthreads();
         if ((uint32_t)tid < count) a.pt_count[s_gd[tid].cnt_base + unit.tile] = s_cnt[tid];
         __syncthreads();  // s_cnt and the staged group are rewritten next
     }
+    // park: the keys are distinct, so a key's rank is the number of smaller keys
+    const uint32_t n = s_npark;
+    const bool fits = n <= kParkMax && t.pair_end - t.solo_end <= 65536u;
+    if (fits && (uint32_t)tid < n) {
+        const uint32_t key = s_park[tid];
+        uint32_t rank = 0;
+        for (uint32_t i = 0; i < n; ++i) rank += s_park[i] < key ? 1u : 0u;
+        a.park[(uint64_t)blockIdx.x * kParkMax + rank] = key;
+    }
+    if (tid == 0) a.park_n[blockIdx.x] = fits ? n : kParkOverflow;
 }
 
 // One unit of the count pass (WRITE false) or of the write pass (WRITE
@@ -181,11 +207,14 @@ __device__ __forceinline__ void batch_unit(const BatchArgs &a) {
     uint32_t (&w)[kBatchNL * 4 + 1] = wl[0];
 
     // the count pass filters the solo pairs one by one and the groups
-    // together; the write pass redoes, pair by pair, only entries with hits.
+    // together; the write pass redoes, pair by pair, only entries with hits:
+    // of the solo pairs, and of the grouped pairs only when the unit's group
+    // hits did not fit in its park list (else it places the parked hits).
     // Pair descriptors are staged in LDS a chunk at a time, so the loop over
     // pairs waits on no global load.
+    const uint32_t parked = WRITE ? a.park_n[blockIdx.x] : 0u;
     const uint32_t pb = t.pair_begin;
-    const uint32_t pe = WRITE ? t.pair_end : t.solo_end;
+    const uint32_t pe = WRITE && parked == kParkOverflow ? t.pair_end : t.solo_end;
     const int64_t wave_pos0 = (int64_t)(tile_start + (uint64_t)wave * kWavePiece) - (int64_t)t.delta;
     constexpr uint32_t kDescU128 = sizeof(BatchPairDesc) / 16;
     static_assert(sizeof(BatchPairDesc) % 16 == 0, "descriptors are copied as 16-byte elements");
@@ -249,7 +278,24 @@ __device__ __forceinline__ void batch_unit(const BatchArgs &a) {
         __syncthreads();  // the next chunk restages s_pd and s_pcnt
     }
     if (pb == pe) fill_halo<kBatchNL>(wl[0]);
-    if constexpr (!WRITE) batch_groups<WAVES>(a, unit, t, w, s0, s_pd);
+    if constexpr (!WRITE) {
+        batch_groups<WAVES>(a, unit, t, w, s0, s_pd);
+    } else if (parked != kParkOverflow && parked != 0) {
+        // parked group hits, sorted by (member, offset): hit i of a member is
+        // its entry's (i - first)-th position, first being the member's first
+        // index in the list
+        uint32_t *s_keys = &s_stage[0][0];
+        if ((uint32_t)tid < parked) s_keys[tid] = a.park[(uint64_t)blockIdx.x * kParkMax + tid];
+        __syncthreads();
+        if ((uint32_t)tid < parked) {
+            const uint32_t key = s_keys[tid], member = key >> 16;
+            uint32_t first = (uint32_t)tid;
+            while (first > 0 && (s_keys[first - 1] >> 16) == member) --first;
+            const uint64_t entry = a.kpairs[t.solo_end + member].cnt_base + unit.tile;
+            const uint64_t pos = a.pt_offset[entry] + ((uint32_t)tid - first);
+            if (pos < a.cap) a.out[pos] = (int64_t)(tile_start + (key & 0xFFFFu)) - (int64_t)t.delta;
+        }
+    }
 }
 
 template <int WAVES>

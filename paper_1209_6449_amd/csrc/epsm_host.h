@@ -57,9 +57,10 @@ struct HostBatch {
 constexpr uint64_t kNoBlob = ~uint64_t(0);
 
 // Byte layout of the device copy of a batch: descriptors, then the
-// (pair, tile) counts, their offsets and the scan's block sums.
+// (pair, tile) counts, their offsets, the scan's block sums and the parked
+// group hits (the device-only part, not uploaded).
 struct BatchLayout {
-    size_t blob, texts, kpairs, spans, gtables, units, ptc, pto, bsum, total;
+    size_t blob, texts, kpairs, spans, gtables, units, park, parkn, ptc, pto, bsum, total;
     explicit BatchLayout(const HostBatch &hb) {
         auto up = [](size_t x) { return (x + 255) & ~size_t(255); };
         size_t at = 0;
@@ -72,6 +73,8 @@ struct BatchLayout {
         ptc = at; at += up(hb.entries * sizeof(uint32_t));
         pto = at; at += up((hb.entries + 1) * sizeof(uint64_t));
         bsum = at; at += up(((hb.entries + kScanBlock - 1) / kScanBlock + 1) * sizeof(uint64_t));
+        park = at; at += up(hb.units.size() * kParkMax * sizeof(uint32_t));
+        parkn = at; at += up(hb.units.size() * sizeof(uint32_t));
         total = at;
     }
 };
@@ -82,6 +85,8 @@ struct BatchPtrs {
     BatchSpan *spans;
     uint32_t *gtables;
     BatchUnit *units;
+    uint32_t *park;
+    uint32_t *parkn;
     uint32_t *ptc;
     uint64_t *pto;
     uint64_t *bsum;

@@ -162,6 +162,15 @@ constexpr uint32_t kGroupBitmapWords = kGroupBuckets / 32;
 constexpr uint32_t kGroupTableWords = kGroupBuckets + kGroupBitmapWords;
 // A text's word patterns are grouped only when it has at least this many.
 constexpr uint32_t kGroupMin = 4;
+// Parked group hits: the count pass lists up to kParkMax hits of a unit's
+// grouped pairs, each as (member << 16) | (offset in the unit), member being
+// the pair's index among its text's grouped pairs; sorted, these are the
+// unit's grouped positions in output order, so the write pass places them
+// without running the group filter again.  A unit with more hits (or a text
+// with more than 65536 grouped pairs) stores kParkOverflow and the write
+// pass recomputes its grouped pairs.
+constexpr uint32_t kParkMax = 64;
+constexpr uint32_t kParkOverflow = 0xFFFFFFFFu;
 
 // Bucket of a 4-byte window x (little endian): fold the top byte into the
 // low 24 bits, one 24-bit multiply, keep the top kGroupBits bits.
@@ -194,6 +203,8 @@ struct BatchArgs {
     const BatchPairDesc *kpairs;   // descriptors in kernel order: pairs with entries, per text contiguous
     const uint32_t *group_tables;  // [groups][kGroupTableWords]
     const BatchUnit *units;
+    uint32_t *park;            // [units][kParkMax] parked group hits, sorted
+    uint32_t *park_n;          // [units] parked hits, or kParkOverflow
     uint32_t *pt_count;        // [entries] hits of each (pair, tile)
     const uint64_t *pt_offset; // [entries + 1] exclusive prefix of pt_count (write pass)
     int64_t *out;
