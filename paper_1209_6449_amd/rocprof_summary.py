@@ -188,7 +188,9 @@ def cmd_traffic(args):
     fetch_factor = args.calib_bytes / (statistics.median(cf) * 1024.0)
     write_factor = args.calib_bytes / (statistics.median(cw) * 1024.0)
     # per unit: all dispatches of the listed kernels over the number of
-    # dispatches of the first one (e.g. per scan: scan + expand + zero)
+    # dispatches of the first one (e.g. per scan: scan + expand + zero);
+    # with --sum-means, the sum of each kernel's mean per dispatch (a unit
+    # runs each listed kernel once, e.g. one batch replay)
     names = args.kernel.split(",")
     f_all, w_all, units = 0.0, 0.0, None
     for k in names:
@@ -196,12 +198,16 @@ def cmd_traffic(args):
         w = counter_per_dispatch(args.write, "WRITE_SIZE", k)
         if len(f) != len(w):
             raise SystemExit(f"{k}: unequal dispatch counts ({len(f)} vs {len(w)})")
+        if not f:
+            raise SystemExit(f"no dispatches of {k}")
         if units is None:
             units = len(f)
-            if not units:
-                raise SystemExit(f"no dispatches of {k}")
-        f_all += sum(f)
-        w_all += sum(w)
+        if args.sum_means:
+            f_all += statistics.mean(f) * units
+            w_all += statistics.mean(w) * units
+        else:
+            f_all += sum(f)
+            w_all += sum(w)
     f = [f_all / units]
     w = [w_all / units]
     fetch_b = [x * 1024.0 * fetch_factor for x in f]
@@ -259,6 +265,8 @@ def main(argv=None):
     t.add_argument("--calib-kernel", default="copy")
     t.add_argument("--kernel", default="scan_kernel,expand_kernel,zero_u64,tile_offsets_kernel",
                    help="comma-separated kernel names; the first counts the units")
+    t.add_argument("--sum-means", action="store_true",
+                   help="traffic per unit = sum over the kernels of their mean per dispatch")
     t.add_argument("--workload", default="sweep1g")
     t.add_argument("--command", required=True)
     t.add_argument("--out-json", required=True)
