@@ -535,13 +535,20 @@ def cpu_baseline(torch, texts, cases, seconds: float, threads: int):
 
 
 def cpu_model() -> str:
-    """The host CPU's model name (lscpu, else /proc/cpuinfo)."""
+    """The host CPU's model name with its family, model and stepping numbers
+    (a virtual machine may report only a generic name), from lscpu, else
+    /proc/cpuinfo."""
     import subprocess
     try:
         r = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10)
+        f = {}
         for line in r.stdout.splitlines():
-            if line.strip().startswith("Model name:"):
-                return line.split(":", 1)[1].strip()
+            if ":" in line:
+                k, v = line.split(":", 1)
+                f.setdefault(k.strip(), v.strip())
+        if "Model name" in f:
+            ids = ", ".join(f"{k.lower()} {f[k]}" for k in ("CPU family", "Model", "Stepping") if k in f)
+            return f"{f['Model name']} ({ids})" if ids else f["Model name"]
     except (OSError, subprocess.SubprocessError):
         pass
     try:

@@ -4,8 +4,8 @@ object inside libepsm.so (CPU only: the ROCm binutils read our own build).
 A private array indexed at run time, or a 64-bit value the compiler turns
 into one access of a register run, silently moves that run to scratch
 memory; a loop-carried value past the VGPR cap spills.  Either costs the
-scans up to 3x, so no kernel may use scratch, and the batch kernel (which
-holds every compare variant at once) must keep four waves per SIMD."""
+scans up to 3x, so no kernel may use scratch, and the batch kernels (which
+hold every compare variant at once) must keep their occupancy."""
 import os
 import re
 import shutil
@@ -72,7 +72,13 @@ def test_no_kernel_uses_scratch(kernels):
     assert not spilled, spilled
 
 
-def test_batch_kernel_keeps_four_waves_per_simd(kernels):
+def test_batch_kernels_keep_their_occupancy(kernels):
+    """The batch kernels are latency bound: the 4-wave count kernel keeps six
+    waves per SIMD (80 registers), every other batch kernel five (96)."""
+    seen = 0
     for k, v in kernels.items():
-        if "batch_kernel" in k:
-            assert v["vgpr_count"] <= 128, (k, v)
+        if "batch_kernel_" in k:
+            seen += 1
+            cap = 80 if "batch_kernel_countILi4E" in k else 96
+            assert v["vgpr_count"] <= cap, (k, v)
+    assert seen == 6
