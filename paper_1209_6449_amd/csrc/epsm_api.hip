@@ -621,9 +621,9 @@ epsm_status build_batch(const epsm_batch *b, int waves, HostBatch &hb, bool chec
     for (uint32_t i = 0; i < b->n_texts; ++i)
         if (text_pairs[i]) units += text_tiles[i];
     // kernel order: a text with at least kGroupMin patterns of m >= 4 filters
-    // them in the count pass in groups of up to kGroupMax through one bucket
-    // table of their first four bytes; its other pairs, filtered one by one,
-    // come first
+    // them in the count pass in groups of up to kGroupMax, each through one
+    // bucket table of their first four (m = 4..7) or eight (m >= 8) bytes;
+    // its other pairs, filtered one by one, come first
     hb.korder.reserve(order.size());
     for (uint32_t i = 0; i < b->n_texts; ++i) {
         BatchTextDesc &d = hb.texts[i];
@@ -635,13 +635,22 @@ epsm_status build_batch(const epsm_batch *b, int waves, HostBatch &hb, bool chec
             if (!grouped || hb.pairs[order[q]].plan.m < 4) hb.korder.push_back(order[q]);
         d.solo_end = (uint32_t)hb.korder.size();
         d.group_begin = (uint32_t)(hb.group_tables.size() / kGroupTableWords);
-        if (grouped) {
+        // groups of the patterns of m = 4..7 (4-byte keys), then of m >= 8
+        // (8-byte keys); each kind starts a new group
+        for (int kind = 0; kind < 2; ++kind) {
+            if (kind == 1) {
+                d.short_end = (uint32_t)hb.korder.size();
+                d.long_group = (uint32_t)(hb.group_tables.size() / kGroupTableWords);
+            }
+            if (!grouped) continue;
+            const uint32_t kind_begin = (uint32_t)hb.korder.size();
             for (uint32_t q = start[i]; q < start[i + 1]; ++q) {
                 const uint32_t k = order[q];
-                if (hb.pairs[k].plan.m < 4) continue;
-                const uint32_t member = (uint32_t)(hb.korder.size() - d.solo_end) % kGroupMax;
+                const DevPlan &pl = hb.pairs[k].plan;
+                if (pl.m < 4 || (pl.m >= 8) != (kind == 1)) continue;
+                const uint32_t member = (uint32_t)(hb.korder.size() - kind_begin) % kGroupMax;
                 if (member == 0) hb.group_tables.resize(hb.group_tables.size() + kGroupTableWords, 0);
-                const uint32_t bucket = group_bucket(hb.pairs[k].plan.pw[0]);
+                const uint32_t bucket = kind == 0 ? group_bucket(pl.pw[0]) : group_bucket8(pl.pw[0], pl.pw[1]);
                 uint32_t *table = hb.group_tables.data() + hb.group_tables.size() - kGroupTableWords;
                 table[bucket] |= 1u << member;
                 table[kGroupBuckets + bucket / 32] |= 1u << (bucket % 32);

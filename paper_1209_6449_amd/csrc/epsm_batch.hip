@@ -57,16 +57,17 @@ constexpr uint32_t kTextWords = kWavePiece / 4 + 8 + 1;
 __device__ __forceinline__ void group_count(const uint32_t (&w)[kBatchNL * 4 + 1], const uint32_t *tw,
                                             const uint32_t *s_tab, const BatchPairDesc *s_gd, uint32_t *s_cnt,
                                             uint32_t *s_park, uint32_t *s_npark, uint32_t member0,
-                                            const BatchTextDesc &t, uint64_t s0, uint32_t lane_byte,
-                                            uint32_t unit_off) {
+                                            bool long_keys, const BatchTextDesc &t, uint64_t s0,
+                                            uint32_t lane_byte, uint32_t unit_off) {
     // first the bitmap of non-empty buckets (32 words, one per LDS bank: no
     // bank conflicts whatever buckets the lanes test), then, for the rare
-    // windows whose bucket holds members, the member masks
+    // windows whose bucket holds members, the member masks.  long_keys: the
+    // group's keys are 8-byte windows (all members have m >= 8)
     const uint32_t *s_bits = s_tab + kGroupBuckets;
     uint32_t cand = 0;
 #pragma unroll
     for (int k = 0; k < 16; ++k) {
-        const uint32_t b = group_bucket(window(w, k));
+        const uint32_t b = long_keys ? group_bucket8(window(w, k), window(w, k + 4)) : group_bucket(window(w, k));
         cand |= ((s_bits[b >> 5] >> (b & 31)) & 1u) << k;
     }
     while (cand) {
@@ -74,7 +75,7 @@ __device__ __forceinline__ void group_count(const uint32_t (&w)[kBatchNL * 4 + 1
         cand &= cand - 1;
         const uint32_t off = lane_byte + k;
         const uint32_t x = lds_window(tw, off);
-        uint32_t members = s_tab[group_bucket(x)];
+        uint32_t members = s_tab[long_keys ? group_bucket8(x, lds_window(tw, off + 4)) : group_bucket(x)];
         const uint64_t s = s0 + k;
         while (members) {
             const uint32_t j = __builtin_ctz(members);
@@ -152,15 +153,18 @@ __device__ __forceinline__ void batch_groups(const BatchArgs &a, const BatchUnit
     }
 #pragma unroll 1
     for (uint32_t g = t.group_begin; g < t.group_end; ++g) {
-        // members: the next kGroupMax (or fewer) grouped pairs of the text
-        const uint32_t first = t.solo_end + (g - t.group_begin) * kGroupMax;
-        const uint32_t count = min(kGroupMax, t.pair_end - first);
+        // members: the next kGroupMax (or fewer) grouped pairs of the text of
+        // the group's kind (m = 4..7, then m >= 8)
+        const bool long_keys = g >= t.long_group;
+        const uint32_t first = (long_keys ? t.short_end + (g - t.long_group) * kGroupMax
+                                          : t.solo_end + (g - t.group_begin) * kGroupMax);
+        const uint32_t count = min(kGroupMax, (long_keys ? t.pair_end : t.short_end) - first);
         const uint32_t *gt = a.group_tables + (size_t)g * kGroupTableWords;
         stage_lds<kThreads>(s_tab, gt, kGroupTableWords / 4, tid);
         stage_lds<kThreads>(s_gd, a.kpairs + first, count * kDescU128, tid);
         if ((uint32_t)tid < count) s_cnt[tid] = 0;
         __syncthreads();
-        group_count(w, tw, s_tab, s_gd, s_cnt, s_park, &s_npark, (g - t.group_begin) * kGroupMax, t, s0,
+        group_count(w, tw, s_tab, s_gd, s_cnt, s_park, &s_npark, first - t.solo_end, long_keys, t, s0,
                     (uint32_t)lane * kPiece, (uint32_t)wave * kWavePiece + (uint32_t)lane * kPiece);
         __syncthreads();
         if ((uint32_t)tid < count) a.pt_count[s_gd[tid].cnt_base + unit.tile] = s_cnt[tid];

@@ -138,20 +138,28 @@ struct BatchTextDesc {
     uint64_t load_end;       // round_up(delta + n, 16)
     // this text's pairs are kpairs[pair_begin, pair_end): first those the
     // count pass filters one by one, [pair_begin, solo_end), then those it
-    // filters in groups, kGroupMax to a group, through the bucket tables
-    // group_begin .. group_end - 1
+    // filters in groups of up to kGroupMax: the patterns of m = 4..7,
+    // [solo_end, short_end), in the groups group_begin .. long_group - 1,
+    // keyed by their first 4 bytes, then those of m >= 8, [short_end,
+    // pair_end), in the groups long_group .. group_end - 1, keyed by their
+    // first 8 bytes
     uint32_t pair_begin;
     uint32_t solo_end;
+    uint32_t short_end;
     uint32_t pair_end;
     uint32_t group_begin;
+    uint32_t long_group;
     uint32_t group_end;
     uint32_t pad_;
 };
 
 // Multi-pattern count (several patterns of one text through one filter).
-// A group holds up to kGroupMax patterns of m >= 4 aimed at one text; its
-// bucket table maps the hash of a 4-byte window to the set of group members
-// (bit j) whose first four bytes hash there.
+// A group holds up to kGroupMax patterns aimed at one text; its bucket table
+// maps the hash of a window to the set of group members (bit j) whose first
+// bytes hash there: 4-byte windows for patterns of m = 4..7, 8-byte windows
+// for m >= 8 (on small alphabets a 4-byte prefix matches too often to
+// filter: over 4 symbols a text window equals one of 30 patterns' first
+// words at about one position in eight).
 constexpr uint32_t kGroupMax = 32;
 constexpr int kGroupBits = 10;
 constexpr uint32_t kGroupBuckets = 1u << kGroupBits;
@@ -177,6 +185,12 @@ constexpr uint32_t kParkOverflow = 0xFFFFFFFFu;
 __host__ __device__ inline uint32_t group_bucket(uint32_t x) {
     const uint32_t y = (x ^ (x >> 16)) & 0xFFFFFFu;
     return (y * 0x9E3779u) >> (32 - kGroupBits);
+}
+
+// Bucket of an 8-byte window (lo, hi): the high word rotated by 7 bits and
+// xor-ed into the low one, then the 4-byte bucket.
+__host__ __device__ inline uint32_t group_bucket8(uint32_t lo, uint32_t hi) {
+    return group_bucket(lo ^ ((hi << 7) | (hi >> 25)));
 }
 
 struct BatchPairDesc {
