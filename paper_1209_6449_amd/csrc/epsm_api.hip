@@ -600,7 +600,10 @@ epsm_status build_batch(const epsm_batch *b, int waves, HostBatch &hb, bool chec
                 hb.blob.insert(hb.blob.end(), src, src + pl->table.size() * sizeof(uint16_t));
                 hb.blob.resize((hb.blob.size() + 15) & ~size_t(15), 0);
             }
-            if (pl->dev.m > 4u * pl->dev.nw) {
+            // the pattern goes along whenever a kernel may read it: the
+            // tail check past the register words, and the write pass, which
+            // compares only 16 bytes from registers
+            if (pl->dev.m > 16 || pl->dev.m > 4u * pl->dev.nw) {
                 pat = hb.blob.size();
                 hb.blob.insert(hb.blob.end(), pl->pattern.begin(), pl->pattern.end());
                 hb.blob.resize((hb.blob.size() + 15) & ~size_t(15), 0);

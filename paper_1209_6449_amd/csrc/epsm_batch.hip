@@ -21,9 +21,15 @@ constexpr uint32_t kPairChunk = 32;  // pair descriptors staged in LDS at a time
 // 64-bit prefix (pk 5..8) are filtered on their first word and verified: the
 // 64-bit variants in this kernel, which holds every variant at once, took
 // it from 105 to 153 VGPRs (three waves per SIMD instead of four).
+// WIDE: plans with three loads per lane (m > 16) compare up to 32 bytes
+// from registers; otherwise their first 16, and the tail check reads the
+// rest of the pattern from device memory (a batch uploads the pattern of
+// every plan with m > 16).  The write pass, which runs only entries with
+// hits, takes the narrow form to stay at six waves per SIMD.
+template <bool WIDE>
 __device__ __forceinline__ uint32_t any_mask(const uint32_t (&w)[kBatchNL * 4 + 1], const DevPlan &p) {
     if (p.variant == 2) return fingerprint_mask<kBatchNL>(w, p, p.table);
-    if (p.nl == 3) return direct_mask<kBatchNL, 4, 0>(w, p);
+    if (WIDE && p.nl == 3) return direct_mask<kBatchNL, 4, 0>(w, p);
     switch (p.pk) {
         case 1: return direct_mask<kBatchNL, 1, 1>(w, p);
         case 2: return direct_mask<kBatchNL, 2, 1>(w, p);
@@ -224,8 +230,11 @@ __device__ __forceinline__ void batch_unit(const BatchArgs &a) {
     static_assert(sizeof(BatchPairDesc) % 16 == 0, "descriptors are copied as 16-byte elements");
     static_assert(kGroupTableWords % 4 == 0, "group tables are copied as 16-byte elements");
     __shared__ __attribute__((aligned(16))) BatchPairDesc s_pd[kPairChunk];
-    __shared__ uint32_t s_pcnt[kPairChunk];
-    __shared__ uint64_t s_poff[kPairChunk];
+    // per staged pair: the count pass accumulates its entry's count in
+    // s_pcnt; the write pass loads the entry's count and output offset into
+    // s_po (one slot per pair keeps one LDS base live across the loop)
+    __shared__ uint32_t s_pcnt[WRITE ? 1 : kPairChunk];
+    __shared__ uint64_t s_po[WRITE ? kPairChunk : 1][2];
 #pragma unroll 1
     for (uint32_t cb = pb; cb < pe; cb += kPairChunk) {
         const uint32_t nc = min(kPairChunk, pe - cb);
@@ -233,8 +242,8 @@ __device__ __forceinline__ void batch_unit(const BatchArgs &a) {
         if ((uint32_t)tid < nc) {
             if constexpr (WRITE) {
                 const uint64_t entry = a.kpairs[cb + tid].cnt_base + unit.tile;
-                s_pcnt[tid] = a.pt_count[entry];
-                s_poff[tid] = a.pt_offset[entry];
+                s_po[tid][0] = a.pt_count[entry];
+                s_po[tid][1] = a.pt_offset[entry];
             } else {
                 s_pcnt[tid] = 0;
             }
@@ -244,14 +253,14 @@ __device__ __forceinline__ void batch_unit(const BatchArgs &a) {
 #pragma unroll 1
         for (uint32_t j = 0; j < nc; ++j) {
             const BatchPairDesc &pd = s_pd[j];
-            if (WRITE && s_pcnt[j] == 0) continue;
+            if (WRITE && s_po[j][0] == 0) continue;
             const DevPlan &p = pd.plan;
-            uint32_t mk = any_mask(w, p);
+            uint32_t mk = any_mask<!WRITE>(w, p);
             const uint64_t last = t.delta + t.n - p.m;  // m <= n here
             if (tile_start + kTileB > last || tile_start < t.delta) mk &= valid_mask(s0, t.delta, last);
-            // the pattern is on the device only for plans with m > 4 * nw
-            if (p.m > 4u * p.nw && wave_any(mk != 0))
-                mk = tail_check(mk, s0, t.base, p.pattern, p.m, 4u * p.nw);
+            const uint32_t verified = WRITE && p.variant != 2 && p.nl == 3 ? 16u : 4u * p.nw;
+            if (p.m > verified && wave_any(mk != 0))
+                mk = tail_check(mk, s0, t.base, p.pattern, p.m, verified);
             const uint32_t c = __popc(mk);
             const uint32_t incl = wave_incl_scan32(c);
             const uint32_t wtot = last_lane(incl);
@@ -262,7 +271,7 @@ __device__ __forceinline__ void batch_unit(const BatchArgs &a) {
                 if (lane == 0) s_wcnt[wave] = wtot;
                 __syncthreads();
                 if (wtot) {
-                    uint64_t obase = s_poff[j];
+                    uint64_t obase = s_po[j][1];
                     for (int i = 0; i < wave; ++i) obase += s_wcnt[i];
                     uint32_t at = incl - c;
                     const uint32_t rel0 = (uint32_t)lane * kPiece;
@@ -279,7 +288,7 @@ __device__ __forceinline__ void batch_unit(const BatchArgs &a) {
         }
         __syncthreads();
         if (!WRITE && (uint32_t)tid < nc) a.pt_count[s_pd[tid].cnt_base + unit.tile] = s_pcnt[tid];
-        __syncthreads();  // the next chunk restages s_pd and s_pcnt
+        __syncthreads();  // the next chunk restages s_pd, s_pcnt and s_po
     }
     if (pb == pe) fill_halo<kBatchNL>(wl[0]);
     if constexpr (!WRITE) {
@@ -308,7 +317,7 @@ __global__ __launch_bounds__(WAVES * kWave) __attribute__((amdgpu_waves_per_eu(W
 }
 
 template <int WAVES>
-__global__ __launch_bounds__(WAVES * kWave) __attribute__((amdgpu_waves_per_eu(5, 8))) void batch_kernel_write(BatchArgs a) {
+__global__ __launch_bounds__(WAVES * kWave) __attribute__((amdgpu_waves_per_eu(WAVES == 4 ? 6 : 5, 8))) void batch_kernel_write(BatchArgs a) {
     batch_unit<WAVES, true>(a);
 }
 

@@ -195,14 +195,18 @@ def test_host_only_direct_plans_m17_to_32(epsm):
             o = int(rng.integers(0, t.size - m + 1))
             pairs.append((ti, epsm.Plan(t[o:o + m].tobytes(), epsm.PLAN_HOST_ONLY | epsm.PLAN_FORCE_DIRECT)))
     assert any(pl.info()["run_blocks"] == 3 for _, pl in pairs)
-    say(f"host-only direct m 17..32: pairs={len(pairs)}")
-    pos, counts, offsets = epsm.search_batch(texts, pairs)
-    epsm.stream_check()
-    pos, counts, offsets = pos.cpu().numpy(), counts.cpu().numpy(), offsets.cpu().numpy()
-    for k, (ti, plan) in enumerate(pairs):
-        exp = oracle.positions(host[ti], plan.pattern)
-        assert exp.size >= 1
-        assert np.array_equal(pos[offsets[k]:offsets[k] + counts[k]], exp), k
+    # grouped: the count pass parks the hits; ungrouped: the write pass
+    # recomputes every pair (16 bytes from registers, then the tail check
+    # against the uploaded pattern)
+    for groups in (True, False):
+        say(f"host-only direct m 17..32: pairs={len(pairs)} groups={groups}")
+        pos, counts, offsets = epsm.search_batch(texts, pairs, groups=groups)
+        epsm.stream_check()
+        pos, counts, offsets = pos.cpu().numpy(), counts.cpu().numpy(), offsets.cpu().numpy()
+        for k, (ti, plan) in enumerate(pairs):
+            exp = oracle.positions(host[ti], plan.pattern)
+            assert exp.size >= 1
+            assert np.array_equal(pos[offsets[k]:offsets[k] + counts[k]], exp), (k, groups)
 
 
 def test_long_patterns_in_batch(epsm):
