@@ -153,6 +153,52 @@ def test_batch_with_config4_shapes_small(epsm):
         assert np.array_equal(pos[offsets[k]:offsets[k] + counts[k]], exp), k
 
 
+def test_parked_hits_at_the_list_boundary(epsm):
+    """Grouped hits are parked per 4 KiB unit up to 64: a unit with exactly
+    64 (one of them crossing into the next unit), a unit with 65 (the write
+    pass recomputes it), a unit with a few; and texts whose grouped patterns
+    are all of m = 4..7 (4-byte keys) or all of m >= 8 (8-byte keys).
+    Patterns use bytes the texts never hold, so the planted hits are all."""
+    epsm.set_batch_config(4)
+    try:
+        rng = np.random.default_rng(77)
+        U = 4096
+
+        def pattern(m):
+            return bytes(rng.integers(200, 256, m).astype(np.uint8))
+
+        def text_with(n, plants):
+            t = rng.integers(0, 64, n).astype(np.uint8)
+            for off, p in plants:
+                t[off:off + len(p)] = np.frombuffer(p, dtype=np.uint8)
+            return t
+
+        mixed = [pattern(m) for m in (4, 5, 6, 7, 8, 11, 16, 24)]
+        plants = [(60 * i, mixed[i % 8]) for i in range(63)] + [(U - 3, mixed[4])]  # unit 0: 64
+        plants += [(U + 16 + 60 * i, mixed[i % 8]) for i in range(65)]               # unit 1: 65
+        plants += [(2 * U + 100 * i, mixed[i % 8]) for i in range(10)]               # unit 2: 10
+        short = [pattern(m) for m in (4, 5, 6, 7, 5)]
+        long_ = [pattern(m) for m in (8, 9, 12, 20, 31, 33)]
+        host = [text_with(3 * U, plants),
+                text_with(2 * U + 77, [(50 * i, short[i % 5]) for i in range(120)]),
+                text_with(2 * U + 5, [(70 * i, long_[i % 6]) for i in range(100)])]
+        texts = [torch.from_numpy(t.copy()).cuda() for t in host]
+        pairs = [(0, epsm.Plan(p, epsm.PLAN_HOST_ONLY if k % 2 else 0)) for k, p in enumerate(mixed)]
+        pairs += [(0, epsm.Plan(bytes([7])))]  # a solo pair beside the groups
+        pairs += [(1, epsm.Plan(p)) for p in short] + [(2, epsm.Plan(p, epsm.PLAN_HOST_ONLY)) for p in long_]
+        for groups in (True, False):
+            say(f"parked-hit boundary: groups={groups}")
+            pos, counts, offsets = epsm.search_batch(texts, pairs, groups=groups)
+            epsm.stream_check()
+            pos, counts, offsets = pos.cpu().numpy(), counts.cpu().numpy(), offsets.cpu().numpy()
+            for k, (ti, plan) in enumerate(pairs):
+                exp = oracle.positions(host[ti], plan.pattern)
+                assert np.array_equal(pos[offsets[k]:offsets[k] + counts[k]], exp), (k, groups)
+        assert sum(int(c) for c in counts[:8]) == 64 + 65 + 10
+    finally:
+        epsm.set_batch_config(8)
+
+
 def test_empty_batch(epsm):
     say("empty batch")
     b = epsm.Batch([], [], count_only=False)
