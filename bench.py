@@ -30,7 +30,10 @@ by the workloads module; texts are resident in HBM before timing starts):
 value = logical text bytes scanned per second over the timed steps (GB/s,
 1 GB = 1e9 B).  roofline = the positions-mode scan kernel: algorithmic bytes
 (n read once + 8 bytes per reported position) / kernel time, timed with
-events on the launch stream, against the 8 TB/s HBM peak.
+events on the launch stream, against the 8 TB/s HBM peak; traffic and
+traffic_frac: the calibrated rocprofv3 FETCH_SIZE + WRITE_SIZE bytes per
+launch from profiles/ (when taken on the same kernel sources) and their rate
+over the same launch time.
 """
 from __future__ import annotations
 
@@ -384,7 +387,9 @@ def run_batch_workload(args, torch, W, epsm):
                 "alg_ops_per_launch": alg_ops, "avg_launch_ms": round(batched_gpu_ms, 4),
                 "hbm": {"bytes_per_launch": hbm_bytes,
                         "gbs": round(hbm_bytes / (batched_gpu_ms / 1e3) / 1e9, 1),
-                        "frac": round(hbm_bytes / (batched_gpu_ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4)}}
+                        "frac": round(hbm_bytes / (batched_gpu_ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
+                        "traffic_frac": (round(traffic["bytes_per_launch"] / (batched_gpu_ms / 1e3) / 1e9
+                                               / HBM_PEAK_GBS, 4) if traffic else None)}}
     extra = {"batched_ms": round(batched_s * 1e3, 3), "batched_gpu_ms": round(batched_gpu_ms, 3),
              "oneshot_ms": round(oneshot_s * 1e3, 3), "plain_ms": round(plain_s * 1e3, 3),
              "speedup_vs_plain": round(plain_s / batched_s, 2),
@@ -744,6 +749,11 @@ def main():
         "avg_launch_ms": round(pos_ms / n_pos_launches, 4),
         "alg_bytes_per_launch": round(pos_alg_bytes / len(pos_cases)),
     }
+    if traffic:
+        # measured fraction: the calibrated HBM bytes per launch over the
+        # same average launch time
+        roofline["traffic_frac"] = round(traffic["bytes_per_launch"] / (pos_ms / n_pos_launches / 1e3)
+                                         / 1e9 / HBM_PEAK_GBS, 4)
 
     result = {
         "metric": METRIC,
