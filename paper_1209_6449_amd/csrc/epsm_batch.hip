@@ -3,13 +3,14 @@
 // Work is cut into units, one unit = one tile of one text.  The unit's
 // workgroup loads the tile once (each lane its 16 bytes, the 32-byte halo
 // from its neighbours) and runs every pattern aimed at that text over it, so
-// a text read from HBM serves all of its patterns.  Output is pair-major: pair k's positions,
-// ascending, fill d_out[offsets[k] .. offsets[k] + counts[k]).  That order is
-// produced in three steps: a count pass writes the hits of every
-// (pair, tile) entry, a device exclusive scan turns the entries (in pair
-// order) into output offsets, and a write pass recomputes only the entries
-// that have hits and writes their positions.  No step needs a host round
-// trip, so the whole sequence can be captured once into a graph.
+// a text read from HBM serves all of its patterns.  Output is pair-major:
+// pair k's positions, ascending, fill d_out[offsets[k] .. offsets[k] +
+// counts[k]).  That order is produced in three steps: a count pass writes
+// the hits of every (pair, tile) entry (and lists the unit's hits of grouped
+// patterns, up to kParkMax), a device exclusive scan turns the entries (in
+// pair order) into output offsets, and a write pass places the listed hits
+// and recomputes only the other entries that have hits.  No step needs a
+// host round trip, so the whole sequence can be captured once into a graph.
 #include "epsm_device.h"
 
 namespace epsm {
