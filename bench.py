@@ -61,8 +61,8 @@ def log(msg: str) -> None:
 def parse_args():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="zipf4g", choices=["sweep1g", "zipf4g", "batch", "serve", "dna", "long"])
     ap.add_argument("--scan-only", action="store_true",
                     help="zipf4g: leave out the batch and serving legs of the default run")
