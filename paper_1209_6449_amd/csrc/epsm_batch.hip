@@ -33,8 +33,8 @@ __device__ __forceinline__ uint32_t any_mask(const uint32_t (&w)[kBatchNL * 4 + 
     if (WIDE && p.nl == 3) return direct_mask<kBatchNL, 4, 0>(w, p);
     switch (p.pk) {
         case 1: return direct_mask<kBatchNL, 1, 1>(w, p);
-        case 2: return direct_mask<kBatchNL, 2, 1>(w, p);
-        case 3: return direct_mask<kBatchNL, 3, 1>(w, p);
+        case 2: return short_mask<2>(w, p.pw[0]);  // per-lane byte runs: no wave masks
+        case 3: return short_mask<3>(w, p.pw[0]);
         default: break;  // 64-bit prefixes (pk 5..8) take the 4-byte path here
     }
     switch (p.nw) {

@@ -120,6 +120,28 @@ __device__ __forceinline__ uint32_t byte_mask(const uint32_t *w, uint32_t c) {
     return mk;
 }
 
+// m = 2 or 3, the same per-lane test on byte runs: start 4q + i matches iff
+// bytes 4q + i .. 4q + i + M - 1 equal p[0..M-1].  The word, and its copies
+// advanced by one (and two) bytes, are xor-ed with the repeated pattern
+// bytes and or-ed together, so a byte is zero iff its start matches; the
+// zero-byte test of byte_mask then gathers the four bits.  Reads w[0..4].
+template <int M>
+__device__ __forceinline__ uint32_t short_mask(const uint32_t *w, uint32_t pw0) {
+    static_assert(M == 2 || M == 3, "byte runs of 2 or 3");
+    const uint32_t r0 = (pw0 & 0xFFu) * 0x01010101u;
+    const uint32_t r1 = ((pw0 >> 8) & 0xFFu) * 0x01010101u;
+    const uint32_t r2 = ((pw0 >> 16) & 0xFFu) * 0x01010101u;
+    uint32_t mk = 0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        uint32_t x = (w[q] ^ r0) | (__builtin_amdgcn_alignbyte(w[q + 1], w[q], 1) ^ r1);
+        if constexpr (M == 3) x |= __builtin_amdgcn_alignbyte(w[q + 1], w[q], 2) ^ r2;
+        const uint32_t z = ~(((x & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | x | 0x7F7F7F7Fu);
+        mk |= ((((z >> 7) & 0x01010101u) * 0x10204080u) >> 28) << (4 * q);
+    }
+    return mk;
+}
+
 // Wave masks of the direct variant (PK >= 2): bit L of b[k] is set iff
 // lane L's start k matches the prefix and the remaining register words.
 // Returns false, with b undefined, when no lane has a hit.
