@@ -656,7 +656,7 @@ epsm_status build_batch(const epsm_batch *b, int waves, HostBatch &hb, bool chec
                 const uint32_t bucket = kind == 0 ? group_bucket(pl.pw[0]) : group_bucket8(pl.pw[0], pl.pw[1]);
                 uint32_t *table = hb.group_tables.data() + hb.group_tables.size() - kGroupTableWords;
                 table[bucket] |= 1u << member;
-                table[kGroupBuckets + bucket / 32] |= 1u << (bucket % 32);
+                reinterpret_cast<uint8_t *>(table + kGroupBuckets)[bucket] = 1;
                 hb.korder.push_back(k);
             }
         }

@@ -66,16 +66,15 @@ __device__ __forceinline__ void group_count(const uint32_t (&w)[kBatchNL * 4 + 1
                                             uint32_t *s_park, uint32_t *s_npark, uint32_t member0,
                                             bool long_keys, const BatchTextDesc &t, uint64_t s0,
                                             uint32_t lane_byte, uint32_t unit_off) {
-    // first the bitmap of non-empty buckets (32 words, one per LDS bank: no
-    // bank conflicts whatever buckets the lanes test), then, for the rare
-    // windows whose bucket holds members, the member masks.  long_keys: the
-    // group's keys are 8-byte windows (all members have m >= 8)
-    const uint32_t *s_bits = s_tab + kGroupBuckets;
+    // first the flag bytes of non-empty buckets, then, for the rare windows
+    // whose bucket holds members, the member masks.  long_keys: the group's
+    // keys are 8-byte windows (all members have m >= 8)
+    const uint8_t *s_flag = reinterpret_cast<const uint8_t *>(s_tab + kGroupBuckets);
     uint32_t cand = 0;
 #pragma unroll
     for (int k = 0; k < 16; ++k) {
         const uint32_t b = long_keys ? group_bucket8(window(w, k), window(w, k + 4)) : group_bucket(window(w, k));
-        cand |= ((s_bits[b >> 5] >> (b & 31)) & 1u) << k;
+        cand |= (uint32_t)s_flag[b] << k;
     }
     while (cand) {
         const uint32_t k = __builtin_ctz(cand);

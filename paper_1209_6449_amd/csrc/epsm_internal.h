@@ -163,11 +163,11 @@ struct BatchTextDesc {
 constexpr uint32_t kGroupMax = 32;
 constexpr int kGroupBits = 10;
 constexpr uint32_t kGroupBuckets = 1u << kGroupBits;
-// A group's table in memory: the kGroupBuckets member masks, then a bitmap
-// of the buckets that are not empty (one bit per bucket, kGroupBuckets / 32
-// words: one word per LDS bank, so lanes testing any buckets never conflict).
-constexpr uint32_t kGroupBitmapWords = kGroupBuckets / 32;
-constexpr uint32_t kGroupTableWords = kGroupBuckets + kGroupBitmapWords;
+// A group's table in memory: the kGroupBuckets member masks, then one flag
+// byte per bucket (1: not empty), so testing a window's bucket is one LDS
+// byte read at the bucket index, with no word and bit to extract.
+constexpr uint32_t kGroupFlagWords = kGroupBuckets / 4;
+constexpr uint32_t kGroupTableWords = kGroupBuckets + kGroupFlagWords;
 // A text's word patterns are grouped only when it has at least this many.
 constexpr uint32_t kGroupMin = 4;
 // Parked group hits: the count pass lists up to kParkMax hits of a unit's
