@@ -19,9 +19,10 @@ constexpr int kBatchNL = 3;  // 48 bytes per lane: any m <= 32 verified from reg
 constexpr uint32_t kPairChunk = 32;  // pair descriptors staged in LDS at a time
 
 // Mask of one lane piece for a runtime-described pattern.  Plans with a
-// 64-bit prefix (pk 5..8) are filtered on their first word and verified: the
-// 64-bit variants in this kernel, which holds every variant at once, took
-// it from 105 to 153 VGPRs (three waves per SIMD instead of four).
+// 64-bit prefix (pk 5..8) are filtered on their first word and verified:
+// this kernel holds every variant at once, and the 64-bit variants cost
+// more registers than the occupancy the batch needs allows (measured: 105
+// -> 153 VGPRs when they were added).
 // WIDE: plans with three loads per lane (m > 16) compare up to 32 bytes
 // from registers; otherwise their first 16, and the tail check reads the
 // rest of the pattern from device memory (a batch uploads the pattern of
@@ -55,12 +56,14 @@ __device__ __forceinline__ uint32_t lds_window(const uint32_t *tw, uint32_t off)
 // 32 bytes after it, and one zero word for the last window.
 constexpr uint32_t kTextWords = kWavePiece / 4 + 8 + 1;
 
-// Multi-pattern count of one lane piece against group g (staged in LDS):
-// each of the 16 windows is looked up in the bucket table; a window whose
+// Multi-pattern count of one lane piece against a group (staged in LDS):
+// each of the 16 windows (4 bytes, or 8 for a group of m >= 8 patterns) is
+// hashed to its bucket and the bucket's flag byte read; a window whose
 // bucket is not empty is compared with the first word of every member in it,
 // then with the member's remaining words (from the LDS copy of the piece,
 // up to 32 bytes) and, past 32 bytes, the tail check.  Hits of member j are
-// added to s_cnt[j].
+// added to s_cnt[j] and listed in s_park (up to kParkMax; s_npark counts
+// them all).
 __device__ __forceinline__ void group_count(const uint32_t (&w)[kBatchNL * 4 + 1], const uint32_t *tw,
                                             const uint32_t *s_tab, const BatchPairDesc *s_gd, uint32_t *s_cnt,
                                             uint32_t *s_park, uint32_t *s_npark, uint32_t member0,
@@ -311,13 +314,20 @@ __device__ __forceinline__ void batch_unit(const BatchArgs &a) {
     }
 }
 
+// Both passes are latency bound (dependent loads per unit, barriers per
+// pair), so they ask for six waves per SIMD at 4 waves per workgroup (80
+// registers) and five otherwise.
+static_assert(kParkMax <= 4 * kWave, "one thread per parked hit");
+
 template <int WAVES>
-__global__ __launch_bounds__(WAVES * kWave) __attribute__((amdgpu_waves_per_eu(WAVES == 4 ? 6 : 5, 8))) void batch_kernel_count(BatchArgs a) {
+__global__ __launch_bounds__(WAVES * kWave) __attribute__((amdgpu_waves_per_eu(WAVES == 4 ? 6 : 5, 8)))
+void batch_kernel_count(BatchArgs a) {
     batch_unit<WAVES, false>(a);
 }
 
 template <int WAVES>
-__global__ __launch_bounds__(WAVES * kWave) __attribute__((amdgpu_waves_per_eu(WAVES == 4 ? 6 : 5, 8))) void batch_kernel_write(BatchArgs a) {
+__global__ __launch_bounds__(WAVES * kWave) __attribute__((amdgpu_waves_per_eu(WAVES == 4 ? 6 : 5, 8)))
+void batch_kernel_write(BatchArgs a) {
     batch_unit<WAVES, true>(a);
 }
 
