@@ -744,6 +744,7 @@ epsm_status run_batch_write(const BatchPtrs &P, const HostBatch &hb, const epsm_
     a.park_n = P.parkn;
     a.pt_count = P.ptc;
     a.pt_offset = P.pto;
+    a.entries = hb.entries;
     a.out = o.d_out;
     a.cap = o.cap;
     a.write = 1;

@@ -228,6 +228,25 @@ __device__ __forceinline__ void batch_unit(const BatchArgs &a) {
     const uint32_t parked = WRITE ? a.park_n[blockIdx.x] : 0u;
     const uint32_t pb = t.pair_begin;
     const uint32_t pe = WRITE && parked == kParkOverflow ? t.pair_end : t.solo_end;
+    // write pass: the unit's parked keys and the first entries of its text's
+    // grouped pairs go to LDS by DMA now, with the text, so that placing the
+    // parked hits after the solo pairs waits on one load instead of three
+    // (keys, then descriptors, then offsets)
+    __shared__ __attribute__((aligned(16))) uint32_t s_keys[WRITE ? kParkMax : 1];
+    __shared__ uint32_t s_gbase[WRITE ? 2 : 1][WRITE ? kThreads : 1];  // low and high words
+    if constexpr (WRITE) {
+        stage_lds<kThreads>(s_keys, a.park + (uint64_t)blockIdx.x * kParkMax, kParkMax / 4, tid);
+        const uint32_t ng = min(t.pair_end - t.solo_end, (uint32_t)kThreads);
+        const __amdgpu_buffer_rsrc_t rg =
+            make_rsrc(reinterpret_cast<const uint8_t *>(a.kpairs + t.solo_end), ng * (uint32_t)sizeof(BatchPairDesc));
+        const uint32_t gw = __builtin_amdgcn_readfirstlane((uint32_t)tid / kWave) * kWave;  // the wave's first pair
+        if (gw + (uint32_t)lane < ng) {
+            constexpr uint32_t kBaseAt = offsetof(BatchPairDesc, cnt_base);
+            const int vo = lane * (int)sizeof(BatchPairDesc) + (int)kBaseAt, so = (int)(gw * sizeof(BatchPairDesc));
+            __builtin_amdgcn_raw_ptr_buffer_load_lds(rg, (lds_void *)&s_gbase[0][gw], 4, vo, so, 0, 0);
+            __builtin_amdgcn_raw_ptr_buffer_load_lds(rg, (lds_void *)&s_gbase[1][gw], 4, vo + 4, so, 0, 0);
+        }
+    }
     const int64_t wave_pos0 = (int64_t)(tile_start + (uint64_t)wave * kWavePiece) - (int64_t)t.delta;
     constexpr uint32_t kDescU128 = sizeof(BatchPairDesc) / 16;
     static_assert(sizeof(BatchPairDesc) % 16 == 0, "descriptors are copied as 16-byte elements");
@@ -300,16 +319,19 @@ __device__ __forceinline__ void batch_unit(const BatchArgs &a) {
         // parked group hits, sorted by (member, offset): hit i of a member is
         // its entry's (i - first)-th position, first being the member's first
         // index in the list
-        uint32_t *s_keys = &s_stage[0][0];
-        if ((uint32_t)tid < parked) s_keys[tid] = a.park[(uint64_t)blockIdx.x * kParkMax + tid];
-        __syncthreads();
+        __syncthreads();  // the DMA into s_keys and s_gbase (no barrier yet without solo pairs)
         if ((uint32_t)tid < parked) {
             const uint32_t key = s_keys[tid], member = key >> 16;
             uint32_t first = (uint32_t)tid;
             while (first > 0 && (s_keys[first - 1] >> 16) == member) --first;
-            const uint64_t entry = a.kpairs[t.solo_end + member].cnt_base + unit.tile;
-            const uint64_t pos = a.pt_offset[entry] + ((uint32_t)tid - first);
-            if (pos < a.cap) a.out[pos] = (int64_t)(tile_start + (key & 0xFFFFu)) - (int64_t)t.delta;
+            const uint64_t base = member < (uint32_t)kThreads
+                                      ? ((uint64_t)s_gbase[1][member] << 32) | s_gbase[0][member]
+                                      : a.kpairs[t.solo_end + member].cnt_base;
+            const uint64_t entry = base + unit.tile;
+            if (entry < a.entries) {
+                const uint64_t pos = a.pt_offset[entry] + ((uint32_t)tid - first);
+                if (pos < a.cap) a.out[pos] = (int64_t)(tile_start + (key & 0xFFFFu)) - (int64_t)t.delta;
+            }
         }
     }
 }

@@ -221,6 +221,7 @@ struct BatchArgs {
     uint32_t *park_n;          // [units] parked hits, or kParkOverflow
     uint32_t *pt_count;        // [entries] hits of each (pair, tile)
     const uint64_t *pt_offset; // [entries + 1] exclusive prefix of pt_count (write pass)
+    uint64_t entries;
     int64_t *out;
     uint64_t cap;
     uint32_t write;
