@@ -320,17 +320,23 @@ __device__ __forceinline__ void batch_unit(const BatchArgs &a) {
         // its entry's (i - first)-th position, first being the member's first
         // index in the list
         __syncthreads();  // the DMA into s_keys and s_gbase (no barrier yet without solo pairs)
-        if ((uint32_t)tid < parked) {
-            const uint32_t key = s_keys[tid], member = key >> 16;
-            uint32_t first = (uint32_t)tid;
-            while (first > 0 && (s_keys[first - 1] >> 16) == member) --first;
-            const uint64_t base = member < (uint32_t)kThreads
-                                      ? ((uint64_t)s_gbase[1][member] << 32) | s_gbase[0][member]
-                                      : a.kpairs[t.solo_end + member].cnt_base;
-            const uint64_t entry = base + unit.tile;
-            if (entry < a.entries) {
-                const uint64_t pos = a.pt_offset[entry] + ((uint32_t)tid - first);
-                if (pos < a.cap) a.out[pos] = (int64_t)(tile_start + (key & 0xFFFFu)) - (int64_t)t.delta;
+        if (wave == 0) {  // the list fits one wave: lane i places hit i
+            const bool live = (uint32_t)lane < parked;
+            const uint32_t key = live ? s_keys[lane] : 0u, member = key >> 16;
+            // a member's hits are consecutive; its first is the nearest lane
+            // at or below this one that starts a member
+            const bool head = live && (lane == 0 || (s_keys[lane - 1] >> 16) != member);
+            const uint64_t heads = __ballot(head);
+            const uint32_t first = 63u - (uint32_t)__clzll(heads & (~0ull >> (63 - lane)));
+            if (live) {
+                const uint64_t base = member < (uint32_t)kThreads
+                                          ? ((uint64_t)s_gbase[1][member] << 32) | s_gbase[0][member]
+                                          : a.kpairs[t.solo_end + member].cnt_base;
+                const uint64_t entry = base + unit.tile;
+                if (entry < a.entries) {
+                    const uint64_t pos = a.pt_offset[entry] + ((uint32_t)lane - first);
+                    if (pos < a.cap) a.out[pos] = (int64_t)(tile_start + (key & 0xFFFFu)) - (int64_t)t.delta;
+                }
             }
         }
     }
@@ -339,7 +345,7 @@ __device__ __forceinline__ void batch_unit(const BatchArgs &a) {
 // Both passes are latency bound (dependent loads per unit, barriers per
 // pair), so they ask for six waves per SIMD at 4 waves per workgroup (80
 // registers) and five otherwise.
-static_assert(kParkMax <= 4 * kWave, "one thread per parked hit");
+static_assert(kParkMax <= kWave, "one lane of wave 0 per parked hit");
 
 template <int WAVES>
 __global__ __launch_bounds__(WAVES * kWave) __attribute__((amdgpu_waves_per_eu(WAVES == 4 ? 6 : 5, 8)))
