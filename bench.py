@@ -382,7 +382,7 @@ def run_batch_workload(args, torch, W, epsm):
     roofline = {"bound": "alu", "achieved": round(achieved, 2), "peak": VALU_INT32_PEAK_TOPS,
                 "unit": "Top/s", "frac": round(achieved / VALU_INT32_PEAK_TOPS, 4),
                 "traffic": traffic["bytes_per_launch"] if traffic else None,
-                "kernel": "batch replay (count pass, scan of the (pair, tile) counts, finalize, write pass), "
+                "kernel": "batch replay (count pass, scan of the (pair, tile) counts, pair counts and offsets, write pass), "
                           "event-timed per replay",
                 "alg_ops_per_launch": alg_ops, "avg_launch_ms": round(batched_gpu_ms, 4),
                 "hbm": {"bytes_per_launch": hbm_bytes,

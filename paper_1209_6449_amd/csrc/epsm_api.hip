@@ -524,7 +524,8 @@ BatchPtrs batch_ptrs(uint8_t *base, const BatchLayout &L) {
     return {(BatchTextDesc *)(base + L.texts), (BatchPairDesc *)(base + L.kpairs),
             (BatchSpan *)(base + L.spans), (uint32_t *)(base + L.gtables), (BatchUnit *)(base + L.units),
             (uint32_t *)(base + L.park), (uint32_t *)(base + L.parkn), (uint32_t *)(base + L.ptc),
-            (uint64_t *)(base + L.pto), (uint64_t *)(base + L.bsum)};
+            (uint64_t *)(base + L.pto), (uint64_t *)(base + L.bsum), (int64_t *)(base + L.shift),
+            (uint64_t *)(base + L.pbsum)};
 }
 
 epsm_status build_batch(const epsm_batch *b, int waves, HostBatch &hb, bool check_outputs,
@@ -556,12 +557,12 @@ epsm_status build_batch(const epsm_batch *b, int waves, HostBatch &hb, bool chec
         const uintptr_t addr = (uintptr_t)t.d_text;
         BatchTextDesc &d = hb.texts[i];
         d.base = (const uint8_t *)(addr & ~uintptr_t(15));
-        d.delta = addr & 15;
+        d.delta = (uint32_t)(addr & 15);
         d.n = t.n;
-        d.load_end = (d.delta + t.n + 15) & ~uint64_t(15);
         const uint64_t tiles = t.n ? (d.delta + t.n + tile_bytes - 1) / tile_bytes : 0;
         if (tiles > 0xFFFFFFFFull) return fail(EPSM_EUNSUPPORTED, "text too long for a batch");
         text_tiles[i] = (uint32_t)tiles;
+        d.tiles = (uint32_t)tiles;
     }
     hb.pairs.assign(b->n_pairs, BatchPairDesc{});
     uint64_t entries = 0;
@@ -578,8 +579,7 @@ epsm_status build_batch(const epsm_batch *b, int waves, HostBatch &hb, bool chec
         if (d.plan.variant == EPSM_VARIANT_STRIDE) d.plan.variant = EPSM_VARIANT_FINGERPRINT;  // tile filter
         d.text = pr.text;
         d.tiles = pr.plan->dev.m <= b->texts[pr.text].n ? text_tiles[pr.text] : 0;
-        d.cnt_base = entries;
-        entries += d.tiles;
+        entries += d.tiles;  // cnt_base is given in kernel order below
         if (d.tiles) text_pairs[pr.text]++;
     }
     hb.entries = entries;
@@ -663,6 +663,17 @@ epsm_status build_batch(const epsm_batch *b, int waves, HostBatch &hb, bool chec
         d.pair_end = (uint32_t)hb.korder.size();
         d.group_end = (uint32_t)(hb.group_tables.size() / kGroupTableWords);
     }
+    // entries in kernel order: a text's pairs, each with one entry per tile
+    uint64_t next = 0;
+    for (uint32_t i = 0; i < b->n_texts; ++i) {
+        BatchTextDesc &d = hb.texts[i];
+        d.entry_begin = next;
+        for (uint32_t q = d.pair_begin; q < d.pair_end; ++q) {
+            hb.pairs[hb.korder[q]].cnt_base = next;
+            next += text_tiles[i];
+        }
+    }
+    if (next != entries) return fail(EPSM_EINVAL, "internal: batch entries do not add up");
     if (units > 0x7FFFFFFFull) return fail(EPSM_EUNSUPPORTED, "batch has too many tiles");
     hb.units.reserve(units);
     for (uint32_t i = 0; i < b->n_texts; ++i)
@@ -694,8 +705,10 @@ epsm_status upload_batch(HostBatch &hb, const BatchLayout &L, uint8_t *dev, hipS
     put(L.texts, hb.texts.data(), hb.texts.size() * sizeof(BatchTextDesc));
     for (size_t i = 0; i < hb.korder.size(); ++i)
         put(L.kpairs + i * sizeof(BatchPairDesc), &hb.pairs[hb.korder[i]], sizeof(BatchPairDesc));
+    std::vector<uint32_t> kq(hb.pairs.size(), kNoKq);
+    for (size_t q = 0; q < hb.korder.size(); ++q) kq[hb.korder[q]] = (uint32_t)q;
     for (size_t k = 0; k < hb.pairs.size(); ++k) {
-        const BatchSpan sp{hb.pairs[k].cnt_base, hb.pairs[k].tiles};
+        const BatchSpan sp{hb.pairs[k].cnt_base, hb.pairs[k].tiles, kq[k]};
         put(L.spans + k * sizeof(BatchSpan), &sp, sizeof(sp));
     }
     put(L.gtables, hb.group_tables.data(), hb.group_tables.size() * sizeof(uint32_t));
@@ -729,7 +742,7 @@ epsm_status run_batch_count(const BatchPtrs &P, const HostBatch &hb, const epsm_
     if (e == hipSuccess) e = launch_scan_counts(P.ptc, hb.entries, P.pto, P.bsum, s);
     if (e == hipSuccess)
         e = launch_batch_finalize(P.spans, (uint32_t)hb.pairs.size(), P.pto, hb.entries, o.d_counts,
-                                  o.d_offsets, o.d_total, s);
+                                  o.d_offsets, o.d_total, P.shift, P.pbsum, s);
     return e == hipSuccess ? EPSM_OK : hip_fail(e, "batch launch (count)");
 }
 
@@ -744,6 +757,7 @@ epsm_status run_batch_write(const BatchPtrs &P, const HostBatch &hb, const epsm_
     a.park_n = P.parkn;
     a.pt_count = P.ptc;
     a.pt_offset = P.pto;
+    a.shift = P.shift;
     a.entries = hb.entries;
     a.out = o.d_out;
     a.cap = o.cap;

@@ -206,7 +206,7 @@ __device__ __forceinline__ void batch_unit(const BatchArgs &a) {
     const BatchUnit unit = a.units[blockIdx.x];
     const BatchTextDesc t = a.texts[unit.text];
     const uint64_t tile_start = (uint64_t)unit.tile * kTileB;
-    const uint64_t avail = t.load_end - tile_start;
+    const uint64_t avail = ((t.delta + t.n + 15) & ~15ull) - tile_start;
     const uint32_t nrec = avail > 0xFFFFFFF0ull ? 0xFFFFFFF0u : (uint32_t)avail;
     const __amdgpu_buffer_rsrc_t rsrc = make_rsrc(t.base + tile_start, nrec);
     const uint32_t lane_off = (uint32_t)wave * kWavePiece + (uint32_t)lane * kPiece;
@@ -228,25 +228,9 @@ __device__ __forceinline__ void batch_unit(const BatchArgs &a) {
     const uint32_t parked = WRITE ? a.park_n[blockIdx.x] : 0u;
     const uint32_t pb = t.pair_begin;
     const uint32_t pe = WRITE && parked == kParkOverflow ? t.pair_end : t.solo_end;
-    // write pass: the unit's parked keys and the first entries of its text's
-    // grouped pairs go to LDS by DMA now, with the text, so that placing the
-    // parked hits after the solo pairs waits on one load instead of three
-    // (keys, then descriptors, then offsets)
+    // write pass: the unit's parked keys go to LDS by DMA now, with the text
     __shared__ __attribute__((aligned(16))) uint32_t s_keys[WRITE ? kParkMax : 1];
-    __shared__ uint32_t s_gbase[WRITE ? 2 : 1][WRITE ? kThreads : 1];  // low and high words
-    if constexpr (WRITE) {
-        stage_lds<kThreads>(s_keys, a.park + (uint64_t)blockIdx.x * kParkMax, kParkMax / 4, tid);
-        const uint32_t ng = min(t.pair_end - t.solo_end, (uint32_t)kThreads);
-        const __amdgpu_buffer_rsrc_t rg =
-            make_rsrc(reinterpret_cast<const uint8_t *>(a.kpairs + t.solo_end), ng * (uint32_t)sizeof(BatchPairDesc));
-        const uint32_t gw = __builtin_amdgcn_readfirstlane((uint32_t)tid / kWave) * kWave;  // the wave's first pair
-        if (gw + (uint32_t)lane < ng) {
-            constexpr uint32_t kBaseAt = offsetof(BatchPairDesc, cnt_base);
-            const int vo = lane * (int)sizeof(BatchPairDesc) + (int)kBaseAt, so = (int)(gw * sizeof(BatchPairDesc));
-            __builtin_amdgcn_raw_ptr_buffer_load_lds(rg, (lds_void *)&s_gbase[0][gw], 4, vo, so, 0, 0);
-            __builtin_amdgcn_raw_ptr_buffer_load_lds(rg, (lds_void *)&s_gbase[1][gw], 4, vo + 4, so, 0, 0);
-        }
-    }
+    if constexpr (WRITE) stage_lds<kThreads>(s_keys, a.park + (uint64_t)blockIdx.x * kParkMax, kParkMax / 4, tid);
     const int64_t wave_pos0 = (int64_t)(tile_start + (uint64_t)wave * kWavePiece) - (int64_t)t.delta;
     constexpr uint32_t kDescU128 = sizeof(BatchPairDesc) / 16;
     static_assert(sizeof(BatchPairDesc) % 16 == 0, "descriptors are copied as 16-byte elements");
@@ -263,9 +247,11 @@ __device__ __forceinline__ void batch_unit(const BatchArgs &a) {
         stage_lds<kThreads>(s_pd, a.kpairs + cb, nc * kDescU128, tid);
         if ((uint32_t)tid < nc) {
             if constexpr (WRITE) {
-                const uint64_t entry = a.kpairs[cb + tid].cnt_base + unit.tile;
+                // the entry follows from the text's descriptor alone
+                const uint32_t q = cb + (uint32_t)tid;
+                const uint64_t entry = t.entry_begin + (uint64_t)(q - pb) * t.tiles + unit.tile;
                 s_po[tid][0] = a.pt_count[entry];
-                s_po[tid][1] = a.pt_offset[entry];
+                s_po[tid][1] = a.pt_offset[entry] + (uint64_t)a.shift[q];
             } else {
                 s_pcnt[tid] = 0;
             }
@@ -319,7 +305,7 @@ __device__ __forceinline__ void batch_unit(const BatchArgs &a) {
         // parked group hits, sorted by (member, offset): hit i of a member is
         // its entry's (i - first)-th position, first being the member's first
         // index in the list
-        __syncthreads();  // the DMA into s_keys and s_gbase (no barrier yet without solo pairs)
+        __syncthreads();  // the DMA into s_keys (no barrier yet without solo pairs)
         if (wave == 0) {  // the list fits one wave: lane i places hit i
             const bool live = (uint32_t)lane < parked;
             const uint32_t key = live ? s_keys[lane] : 0u, member = key >> 16;
@@ -328,15 +314,11 @@ __device__ __forceinline__ void batch_unit(const BatchArgs &a) {
             const bool head = live && (lane == 0 || (s_keys[lane - 1] >> 16) != member);
             const uint64_t heads = __ballot(head);
             const uint32_t first = 63u - (uint32_t)__clzll(heads & (~0ull >> (63 - lane)));
-            if (live) {
-                const uint64_t base = member < (uint32_t)kThreads
-                                          ? ((uint64_t)s_gbase[1][member] << 32) | s_gbase[0][member]
-                                          : a.kpairs[t.solo_end + member].cnt_base;
-                const uint64_t entry = base + unit.tile;
-                if (entry < a.entries) {
-                    const uint64_t pos = a.pt_offset[entry] + ((uint32_t)lane - first);
-                    if (pos < a.cap) a.out[pos] = (int64_t)(tile_start + (key & 0xFFFFu)) - (int64_t)t.delta;
-                }
+            const uint32_t q = t.solo_end + member;  // the member's pair in kernel order
+            if (live && q < t.pair_end) {
+                const uint64_t entry = t.entry_begin + (uint64_t)(q - t.pair_begin) * t.tiles + unit.tile;
+                const uint64_t pos = a.pt_offset[entry] + (uint64_t)a.shift[q] + ((uint32_t)lane - first);
+                if (pos < a.cap) a.out[pos] = (int64_t)(tile_start + (key & 0xFFFFu)) - (int64_t)t.delta;
             }
         }
     }
@@ -469,25 +451,85 @@ hipError_t launch_scan_counts(const uint32_t *counts, uint64_t entries, uint64_t
     return hipGetLastError();
 }
 
-__global__ void batch_finalize_kernel(const BatchSpan *spans, uint32_t n_pairs,
-                                      const uint64_t *offsets, uint64_t entries, uint64_t *counts,
-                                      uint64_t *pair_offsets, uint64_t *total) {
-    const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k < n_pairs) {
-        const uint64_t b = spans[k].cnt_base;
-        const uint64_t begin = offsets[b], end = offsets[b + spans[k].tiles];
-        pair_offsets[k] = begin;
-        counts[k] = end - begin;
+// Pair results in the caller's order.  Step 1: each pair's count from the
+// offsets of its first and past-last entries, and the sum of each block of
+// kScanBlock pairs.
+__global__ __launch_bounds__(256) void pair_count_kernel(const BatchSpan *spans, uint32_t n_pairs,
+                                                         const uint64_t *offsets, uint64_t *counts,
+                                                         uint64_t *block_sums) {
+    __shared__ uint64_t s_part[4];
+    const uint64_t base = (uint64_t)blockIdx.x * kScanBlock;
+    uint64_t v = 0;
+    for (uint32_t i = threadIdx.x; i < kScanBlock; i += 256) {
+        const uint64_t k = base + i;
+        if (k < n_pairs) {
+            const BatchSpan sp = spans[k];
+            const uint64_t c = sp.tiles ? offsets[sp.cnt_base + sp.tiles] - offsets[sp.cnt_base] : 0;
+            counts[k] = c;
+            v += c;
+        }
     }
-    if (k == 0 && total) *total = offsets[entries];
+    v = wave_sum64(v);
+    if ((threadIdx.x & (kWave - 1)) == 0) s_part[threadIdx.x / kWave] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) block_sums[blockIdx.x] = s_part[0] + s_part[1] + s_part[2] + s_part[3];
+}
+
+// Step 3 (after scan_blocks_kernel over the block sums): each pair's output
+// offset, the exclusive prefix of the counts in the caller's order, and the
+// shift that turns its entries' offsets (a prefix in kernel order) into
+// output positions.
+__global__ __launch_bounds__(256) void pair_offset_kernel(const BatchSpan *spans, uint32_t n_pairs,
+                                                          const uint64_t *offsets, const uint64_t *counts,
+                                                          const uint64_t *block_sums, uint64_t *pair_offsets,
+                                                          int64_t *shift, uint64_t entries, uint64_t *total) {
+    __shared__ uint64_t s_wave[4];
+    const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
+    const uint64_t base = (uint64_t)blockIdx.x * kScanBlock + (uint64_t)tid * 16;
+    uint64_t v[16];
+    uint64_t sum = 0;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+        v[i] = base + i < n_pairs ? counts[base + i] : 0ull;
+        sum += v[i];
+    }
+    uint64_t x = sum;
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+        const uint64_t t = __shfl_up(x, d, kWave);
+        if (lane >= d) x += t;
+    }
+    if (lane == kWave - 1) s_wave[wave] = x;
+    __syncthreads();
+    uint64_t run = block_sums[blockIdx.x] + x - sum;
+    for (int w2 = 0; w2 < wave; ++w2) run += s_wave[w2];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+        const uint64_t k = base + i;
+        if (k < n_pairs) {
+            pair_offsets[k] = run;
+            const BatchSpan sp = spans[k];
+            if (sp.kq != kNoKq) shift[sp.kq] = (int64_t)(run - offsets[sp.cnt_base]);
+        }
+        run += v[i];
+    }
+    if (blockIdx.x == 0 && tid == 0 && total) *total = offsets[entries];
 }
 
 hipError_t launch_batch_finalize(const BatchSpan *spans, uint32_t n_pairs,
                                  const uint64_t *offsets, uint64_t entries, uint64_t *counts,
-                                 uint64_t *pair_offsets, uint64_t *total, hipStream_t s) {
-    const uint32_t blocks = n_pairs ? (n_pairs + 255) / 256 : 1;
-    hipLaunchKernelGGL(batch_finalize_kernel, dim3(blocks), dim3(256), 0, s, spans, n_pairs, offsets,
-                       entries, counts, pair_offsets, total);
+                                 uint64_t *pair_offsets, uint64_t *total, int64_t *shift,
+                                 uint64_t *block_sums, hipStream_t s) {
+    const uint32_t blocks = (uint32_t)(((uint64_t)n_pairs + kScanBlock - 1) / kScanBlock);
+    if (blocks)
+        hipLaunchKernelGGL(pair_count_kernel, dim3(blocks), dim3(256), 0, s, spans, n_pairs, offsets, counts,
+                           block_sums);
+    // exclusive scan of the block sums; its grand total goes to the spare
+    // slot past them
+    hipLaunchKernelGGL(scan_blocks_kernel, dim3(1), dim3(1024), 0, s, block_sums, (uint64_t)blocks,
+                       block_sums + blocks, (uint64_t)0);
+    hipLaunchKernelGGL(pair_offset_kernel, dim3(blocks ? blocks : 1), dim3(256), 0, s, spans, n_pairs, offsets,
+                       counts, block_sums, pair_offsets, shift, entries, total);
     return hipGetLastError();
 }
 

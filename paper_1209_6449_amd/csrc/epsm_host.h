@@ -57,10 +57,11 @@ struct HostBatch {
 constexpr uint64_t kNoBlob = ~uint64_t(0);
 
 // Byte layout of the device copy of a batch: descriptors, then the
-// (pair, tile) counts, their offsets, the scan's block sums and the parked
-// group hits (the device-only part, not uploaded).
+// (pair, tile) counts, their offsets, the scan's block sums, the parked
+// group hits and the per-pair shifts and block sums of the pair scan (the
+// device-only part, not uploaded).
 struct BatchLayout {
-    size_t blob, texts, kpairs, spans, gtables, units, park, parkn, ptc, pto, bsum, total;
+    size_t blob, texts, kpairs, spans, gtables, units, park, parkn, ptc, pto, bsum, shift, pbsum, total;
     explicit BatchLayout(const HostBatch &hb) {
         auto up = [](size_t x) { return (x + 255) & ~size_t(255); };
         size_t at = 0;
@@ -75,6 +76,8 @@ struct BatchLayout {
         bsum = at; at += up(((hb.entries + kScanBlock - 1) / kScanBlock + 1) * sizeof(uint64_t));
         park = at; at += up(hb.units.size() * kParkMax * sizeof(uint32_t));
         parkn = at; at += up(hb.units.size() * sizeof(uint32_t));
+        shift = at; at += up(hb.korder.size() * sizeof(int64_t));
+        pbsum = at; at += up(((hb.pairs.size() + kScanBlock - 1) / kScanBlock + 1) * sizeof(uint64_t));
         total = at;
     }
 };
@@ -90,6 +93,8 @@ struct BatchPtrs {
     uint32_t *ptc;
     uint64_t *pto;
     uint64_t *bsum;
+    int64_t *shift;
+    uint64_t *pbsum;
 };
 
 BatchPtrs batch_ptrs(uint8_t *base, const BatchLayout &L);

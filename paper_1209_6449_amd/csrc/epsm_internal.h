@@ -133,16 +133,18 @@ hipError_t launch_copy_u64(const uint64_t *src, uint64_t *dst, hipStream_t s);
 
 struct BatchTextDesc {
     const uint8_t *base;     // 16-byte aligned address at or below the text start
-    uint64_t delta;          // text start - base
     uint64_t n;              // text length
-    uint64_t load_end;       // round_up(delta + n, 16)
+    uint64_t entry_begin;    // first (pair, tile) entry of the text's pairs
+    uint32_t delta;          // text start - base (< 16); readable to round_up(delta + n, 16)
+    uint32_t tiles;          // tiles of the text: each of its pairs has one entry per tile
     // this text's pairs are kpairs[pair_begin, pair_end): first those the
     // count pass filters one by one, [pair_begin, solo_end), then those it
     // filters in groups of up to kGroupMax: the patterns of m = 4..7,
     // [solo_end, short_end), in the groups group_begin .. long_group - 1,
     // keyed by their first 4 bytes, then those of m >= 8, [short_end,
     // pair_end), in the groups long_group .. group_end - 1, keyed by their
-    // first 8 bytes
+    // first 8 bytes.  Entries follow the same order: pair q's entry for tile
+    // i is entry_begin + (q - pair_begin) * tiles + i.
     uint32_t pair_begin;
     uint32_t solo_end;
     uint32_t short_end;
@@ -152,6 +154,7 @@ struct BatchTextDesc {
     uint32_t group_end;
     uint32_t pad_;
 };
+static_assert(sizeof(BatchTextDesc) == 64, "one scalar load per text descriptor");
 
 // Multi-pattern count (several patterns of one text through one filter).
 // A group holds up to kGroupMax patterns aimed at one text; its bucket table
@@ -195,7 +198,7 @@ __host__ __device__ inline uint32_t group_bucket8(uint32_t lo, uint32_t hi) {
 
 struct BatchPairDesc {
     DevPlan plan;
-    uint64_t cnt_base;       // first (pair, tile) entry of this pair
+    uint64_t cnt_base;       // first (pair, tile) entry of this pair (entries are in kernel order)
     uint32_t text;
     uint32_t tiles;          // entries of this pair: tiles of its text, 0 if m > n
     uint32_t pad_[2];        // 160 bytes: copied to LDS as 16-byte elements
@@ -204,8 +207,10 @@ struct BatchPairDesc {
 // Entries of a pair in the caller's order (for its count and offset).
 struct BatchSpan {
     uint64_t cnt_base;
-    uint64_t tiles;
+    uint32_t tiles;
+    uint32_t kq;  // the pair's index in kernel order (kNoKq when it has no entries)
 };
+constexpr uint32_t kNoKq = 0xFFFFFFFFu;
 
 struct BatchUnit {
     uint32_t text;
@@ -221,6 +226,8 @@ struct BatchArgs {
     uint32_t *park_n;          // [units] parked hits, or kParkOverflow
     uint32_t *pt_count;        // [entries] hits of each (pair, tile)
     const uint64_t *pt_offset; // [entries + 1] exclusive prefix of pt_count (write pass)
+    const int64_t *shift;      // [pairs in kernel order] output offset of the pair minus
+                               // pt_offset of its first entry (write pass)
     uint64_t entries;
     int64_t *out;
     uint64_t cap;
@@ -234,9 +241,14 @@ bool batch_waves_supported(int waves);
 constexpr uint32_t kScanBlock = 4096;
 hipError_t launch_scan_counts(const uint32_t *counts, uint64_t entries, uint64_t *offsets,
                               uint64_t *block_sums, hipStream_t s);
+// Per pair in the caller's order: its count, its output offset (exclusive
+// prefix of the counts in that order), and the shift of its entries'
+// offsets (entries are scanned in kernel order); block_sums holds
+// ceil(n_pairs / kScanBlock) + 1 u64.
 hipError_t launch_batch_finalize(const BatchSpan *spans, uint32_t n_pairs,
                                  const uint64_t *offsets, uint64_t entries, uint64_t *counts,
-                                 uint64_t *pair_offsets, uint64_t *total, hipStream_t s);
+                                 uint64_t *pair_offsets, uint64_t *total, int64_t *shift,
+                                 uint64_t *block_sums, hipStream_t s);
 
 // Tile geometry of one kernel configuration.
 struct TileConfig {
