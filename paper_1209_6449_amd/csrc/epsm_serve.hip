@@ -432,11 +432,12 @@ epsm_status epsm_server_submit(epsm_server_t s, uint32_t text_id, const uint8_t 
     if (s->stop) return fail(EPSM_EINVAL, "server is shutting down");
     q->text = text_id;
     q->entries = (uint64_t)n_patterns * s->text_tiles(text_id);
-    // device work: 12 bytes per (pattern, tile) entry, descriptors, tables
+    // device work: 12 bytes per (pattern, tile) entry, descriptors, tables,
+    // and the parked hits of each tile of the text
     uint64_t table_bytes = 0;
     for (epsm_plan_t p : q->plans) table_bytes += p->table.size() * sizeof(uint16_t) + p->pattern.size();
     q->est_bytes = q->entries * 12 + (uint64_t)n_patterns * (sizeof(BatchPairDesc) + 64) +
-                   table_bytes + (64u << 10);
+                   table_bytes + s->text_tiles(text_id) * (kParkMax + 1) * sizeof(uint32_t) + (64u << 10);
     q->id = s->next_id++;
     q->submit = s->now();
     *query_id = q->id;
