@@ -304,10 +304,11 @@ typedef struct {
 epsm_status epsm_search_batch(const epsm_batch *batch, void *stream);
 
 /* Bytes of stream workspace that epsm_search_batch needs for this batch
- * (the descriptors, the per-(pair, tile) counts and offsets, and 260 bytes
- * per text tile for the count pass's parked hits), for epsm_reserve before
- * a graph capture.  Validates the batch as epsm_search_batch does, without
- * its output pointers. */
+ * (the descriptors, the per-(pair, tile) counts and offsets, 8 bytes per
+ * pair for the shift from its entries' offsets to its output offset, and
+ * 260 bytes per text tile for the count pass's parked hits), for
+ * epsm_reserve before a graph capture.  Validates the batch as
+ * epsm_search_batch does, without its output pointers. */
 epsm_status epsm_batch_workspace(const epsm_batch *batch, uint64_t *bytes);
 
 /* ---- tuning ------------------------------------------------------------- */
