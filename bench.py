@@ -331,6 +331,7 @@ def run_batch_workload(args, torch, W, epsm):
     oneshot_s = time.perf_counter() - t0
     if args.no_plain:
         print(json.dumps({"batch_no_plain": True, "batched_gpu_ms": round(batched_gpu_ms, 3),
+                          "oneshot_ms": round(oneshot_s * 1e3, 3),
                           "units": info["units"], "entries": info["entries"]}), flush=True)
         sys.exit(0)
 

@@ -9,6 +9,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <unordered_map>
 #include <memory>
 #include <mutex>
 #include <string>
@@ -566,6 +567,12 @@ epsm_status build_batch(const epsm_batch *b, int waves, HostBatch &hb, bool chec
     }
     hb.pairs.assign(b->n_pairs, BatchPairDesc{});
     uint64_t entries = 0;
+    // per pair, read once from its plan: m (the passes below read it from
+    // this compact array, not from descriptors 160 bytes apart), whether it
+    // is a pair with entries of a plan that lives on the host, and whether
+    // that plan has a table
+    std::vector<uint32_t> pm(b->n_pairs, 0);
+    std::vector<uint8_t> host_only(b->n_pairs, 0), has_table(b->n_pairs, 0);
     for (uint32_t k = 0; k < b->n_pairs; ++k) {
         const epsm_pair_ref &pr = b->pairs[k];
         if (pr.text >= b->n_texts) return fail(EPSM_EINVAL, "pair refers to a text out of range");
@@ -579,40 +586,14 @@ epsm_status build_batch(const epsm_batch *b, int waves, HostBatch &hb, bool chec
         if (d.plan.variant == EPSM_VARIANT_STRIDE) d.plan.variant = EPSM_VARIANT_FINGERPRINT;  // tile filter
         d.text = pr.text;
         d.tiles = pr.plan->dev.m <= b->texts[pr.text].n ? text_tiles[pr.text] : 0;
+        pm[k] = (uint32_t)std::min<uint64_t>(d.plan.m, 0xFFFFFFFFull);
+        host_only[k] = pr.plan->device < 0 && d.tiles;
+        has_table[k] = !pr.plan->table.empty();
         entries += d.tiles;  // cnt_base is given in kernel order below
         if (d.tiles) text_pairs[pr.text]++;
     }
     hb.entries = entries;
-    // host-only plans: their table and (for the tail check) pattern travel
-    // in the batch's own device buffer, one copy per distinct plan
-    hb.blob_table.assign(b->n_pairs, kNoBlob);
-    hb.blob_pattern.assign(b->n_pairs, kNoBlob);
-    std::map<epsm_plan_t, std::pair<uint64_t, uint64_t>> placed;
-    for (uint32_t k = 0; k < b->n_pairs; ++k) {
-        epsm_plan_t pl = b->pairs[k].plan;
-        if (pl->device >= 0 || !hb.pairs[k].tiles) continue;
-        auto it = placed.find(pl);
-        if (it == placed.end()) {
-            uint64_t tab = kNoBlob, pat = kNoBlob;
-            if (!pl->table.empty()) {
-                tab = hb.blob.size();
-                const uint8_t *src = (const uint8_t *)pl->table.data();
-                hb.blob.insert(hb.blob.end(), src, src + pl->table.size() * sizeof(uint16_t));
-                hb.blob.resize((hb.blob.size() + 15) & ~size_t(15), 0);
-            }
-            // the pattern goes along whenever a kernel may read it: the
-            // tail check past the register words, and the write pass, which
-            // compares only 16 bytes from registers
-            if (pl->dev.m > 16 || pl->dev.m > 4u * pl->dev.nw) {
-                pat = hb.blob.size();
-                hb.blob.insert(hb.blob.end(), pl->pattern.begin(), pl->pattern.end());
-                hb.blob.resize((hb.blob.size() + 15) & ~size_t(15), 0);
-            }
-            it = placed.emplace(pl, std::make_pair(tab, pat)).first;
-        }
-        hb.blob_table[k] = it->second.first;
-        hb.blob_pattern[k] = it->second.second;
-    }
+    std::vector<uint8_t> in_group(b->n_pairs, 0);  // filtered in a group by the count pass
     // pairs grouped by text (the caller's order kept within a text)
     std::vector<uint32_t> start(b->n_texts + 1, 0);
     for (uint32_t i = 0; i < b->n_texts; ++i) start[i + 1] = start[i] + text_pairs[i];
@@ -628,14 +609,27 @@ epsm_status build_batch(const epsm_batch *b, int waves, HostBatch &hb, bool chec
     // bucket table of their first four (m = 4..7) or eight (m >= 8) bytes;
     // its other pairs, filtered one by one, come first
     hb.korder.reserve(order.size());
+    {
+        uint64_t groups = 0;  // reserved up front: the tables come to 5 KiB a group
+        for (uint32_t i = 0; i < b->n_texts; ++i) {
+            uint32_t short_ = 0, long_ = 0;
+            for (uint32_t q = start[i]; q < start[i + 1]; ++q) {
+                short_ += pm[order[q]] >= 4 && pm[order[q]] < 8;
+                long_ += pm[order[q]] >= 8;
+            }
+            if (group && short_ + long_ >= kGroupMin)
+                groups += (short_ + kGroupMax - 1) / kGroupMax + (long_ + kGroupMax - 1) / kGroupMax;
+        }
+        hb.group_tables.reserve(groups * kGroupTableWords);
+    }
     for (uint32_t i = 0; i < b->n_texts; ++i) {
         BatchTextDesc &d = hb.texts[i];
         uint32_t words = 0;
-        for (uint32_t q = start[i]; q < start[i + 1]; ++q) words += hb.pairs[order[q]].plan.m >= 4;
+        for (uint32_t q = start[i]; q < start[i + 1]; ++q) words += pm[order[q]] >= 4;
         const bool grouped = group && words >= kGroupMin;
         d.pair_begin = (uint32_t)hb.korder.size();
         for (uint32_t q = start[i]; q < start[i + 1]; ++q)
-            if (!grouped || hb.pairs[order[q]].plan.m < 4) hb.korder.push_back(order[q]);
+            if (!grouped || pm[order[q]] < 4) hb.korder.push_back(order[q]);
         d.solo_end = (uint32_t)hb.korder.size();
         d.group_begin = (uint32_t)(hb.group_tables.size() / kGroupTableWords);
         // groups of the patterns of m = 4..7 (4-byte keys), then of m >= 8
@@ -649,8 +643,8 @@ epsm_status build_batch(const epsm_batch *b, int waves, HostBatch &hb, bool chec
             const uint32_t kind_begin = (uint32_t)hb.korder.size();
             for (uint32_t q = start[i]; q < start[i + 1]; ++q) {
                 const uint32_t k = order[q];
+                if (pm[k] < 4 || (pm[k] >= 8) != (kind == 1)) continue;
                 const DevPlan &pl = hb.pairs[k].plan;
-                if (pl.m < 4 || (pl.m >= 8) != (kind == 1)) continue;
                 const uint32_t member = (uint32_t)(hb.korder.size() - kind_begin) % kGroupMax;
                 if (member == 0) hb.group_tables.resize(hb.group_tables.size() + kGroupTableWords, 0);
                 const uint32_t bucket = kind == 0 ? group_bucket(pl.pw[0]) : group_bucket8(pl.pw[0], pl.pw[1]);
@@ -658,10 +652,53 @@ epsm_status build_batch(const epsm_batch *b, int waves, HostBatch &hb, bool chec
                 table[bucket] |= 1u << member;
                 reinterpret_cast<uint8_t *>(table + kGroupBuckets)[bucket] = 1;
                 hb.korder.push_back(k);
+                in_group[k] = 1;
             }
         }
         d.pair_end = (uint32_t)hb.korder.size();
         d.group_end = (uint32_t)(hb.group_tables.size() / kGroupTableWords);
+    }
+    // host-only plans: their table (for pairs filtered alone) and, for the
+    // tail check, their pattern travel in the batch's own device buffer.
+    // Grouped pairs need no table: the group filter compares pattern words, and a
+    // write-pass recompute of a grouped fingerprint pair compares its first
+    // 16 bytes directly (its batch descriptor is made a direct one) and
+    // checks the rest with the tail check
+    hb.blob_table.assign(b->n_pairs, kNoBlob);
+    hb.blob_pattern.assign(b->n_pairs, kNoBlob);
+    for (uint32_t k = 0; k < b->n_pairs; ++k) {
+        if (!in_group[k]) continue;
+        DevPlan &pl = hb.pairs[k].plan;
+        if (pl.variant == EPSM_VARIANT_FINGERPRINT) {
+            pl.variant = EPSM_VARIANT_DIRECT;
+            pl.hash_bits = 0;
+            pl.table = nullptr;
+        }
+    }
+    // one copy of a table per distinct plan; patterns (at most 48 bytes
+    // padded) are copied per pair
+    std::unordered_map<epsm_plan_t, uint64_t> table_at;
+    auto append = [&](const uint8_t *src, size_t n) {
+        const uint64_t at = hb.blob.size();
+        hb.blob.insert(hb.blob.end(), src, src + n);
+        hb.blob.resize((hb.blob.size() + 15) & ~size_t(15), 0);
+        return at;
+    };
+    for (uint32_t k = 0; k < b->n_pairs; ++k) {
+        if (!host_only[k]) continue;
+        epsm_plan_t pl = b->pairs[k].plan;
+        if (!in_group[k] && has_table[k]) {
+            auto it = table_at.find(pl);
+            if (it == table_at.end())
+                it = table_at.emplace(pl, append((const uint8_t *)pl->table.data(),
+                                                 pl->table.size() * sizeof(uint16_t))).first;
+            hb.blob_table[k] = it->second;
+        }
+        // the pattern goes along whenever a kernel may read it: for m > 16,
+        // the tail check past the register words and the write pass, which
+        // compares only 16 bytes from registers (up to 16 bytes, every
+        // variant holds the whole pattern in its register words)
+        if (pm[k] > 16) hb.blob_pattern[k] = append(pl->pattern.data(), pl->pattern.size());
     }
     // entries in kernel order: a text's pairs, each with one entry per tile
     uint64_t next = 0;

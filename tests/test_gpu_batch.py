@@ -199,6 +199,36 @@ def test_parked_hits_at_the_list_boundary(epsm):
         epsm.set_batch_config(8)
 
 
+def test_grouped_pairs_carry_no_fingerprint_table(epsm):
+    """Host-only fingerprint plans (m >= 16) filtered in a group bring no
+    hash table into the batch (only ungrouped ones do), and their output
+    is the same either way, including a unit whose group hits overflow
+    its park list and are recomputed."""
+    rng = np.random.default_rng(91)
+    n = 3 * 8192
+    t = rng.integers(0, 4, n).astype(np.uint8)
+    pats = [t[o:o + m].tobytes() for o, m in zip(rng.integers(0, n - 40, 12), (16, 17, 20, 24, 28, 31, 32, 18,
+                                                                            16, 22, 26, 30))]
+    stem = bytes(rng.integers(200, 256, 20).astype(np.uint8))
+    for i in range(80):  # 80 hits of one pattern inside the first 8 KiB
+        t[90 * i:90 * i + 20] = np.frombuffer(stem, dtype=np.uint8)
+    pats.append(stem)
+    text = torch.from_numpy(t.copy()).cuda()
+    plans = [(0, epsm.Plan(p, epsm.PLAN_HOST_ONLY)) for p in pats]
+    assert all(pl.info()["variant"] == epsm.VARIANT_FINGERPRINT for _, pl in plans)
+    grouped = epsm.Batch([text], plans).workspace_bytes()
+    alone = epsm.Batch([text], plans, groups=False).workspace_bytes()
+    say(f"workspace grouped={grouped} ungrouped={alone}")
+    assert alone - grouped >= len(plans) * 4096 - 2 * 5120
+    for groups in (True, False):
+        pos, counts, offsets = [x.cpu().numpy() for x in epsm.search_batch([text], plans, groups=groups)]
+        epsm.stream_check()
+        for k, (_, plan) in enumerate(plans):
+            exp = oracle.positions(t, plan.pattern)
+            assert np.array_equal(pos[offsets[k]:offsets[k] + counts[k]], exp), (k, groups)
+    assert counts[-1] == 80
+
+
 def test_empty_batch(epsm):
     say("empty batch")
     b = epsm.Batch([], [], count_only=False)
