@@ -8,9 +8,11 @@
 // counts[k]).  That order is produced in three steps: a count pass writes
 // the hits of every (pair, tile) entry (and lists the unit's hits of grouped
 // patterns, up to kParkMax), a device exclusive scan turns the entries (in
-// pair order) into output offsets, and a write pass places the listed hits
-// and recomputes only the other entries that have hits.  No step needs a
-// host round trip, so the whole sequence can be captured once into a graph.
+// kernel order, a pair's tiles consecutive) into offsets and a scan of the
+// pairs' totals in the caller's order gives each pair its output offset and
+// shift, and a write pass places the listed hits and recomputes only the
+// other entries that have hits.  No step needs a host round trip, so the
+// whole sequence can be captured once into a graph.
 #include "epsm_device.h"
 
 namespace epsm {
