@@ -30,17 +30,34 @@ constexpr uint32_t kPairChunk = 32;  // pair descriptors staged in LDS at a time
 // rest of the pattern from device memory (a batch uploads the pattern of
 // every plan with m > 16).  The write pass, which runs only entries with
 // hits, takes the narrow form to stay at six waves per SIMD.
-template <bool WIDE>
-__device__ __forceinline__ uint32_t any_mask(const uint32_t (&w)[kBatchNL * 4 + 1], const DevPlan &p) {
-    if (p.variant == 2) return fingerprint_mask<kBatchNL>(w, p, p.table);
-    if (WIDE && p.nl == 3) return direct_mask<kBatchNL, 4, 0>(w, p);
-    switch (p.pk) {
+// F gives the plan fields the choice branches on: PlanFields reads them from
+// the plan (in LDS) where they are used, HeldFields holds them in scalar
+// registers, read together beforehand.
+struct PlanFields {
+    const DevPlan &p;
+    __device__ uint32_t var() const { return p.variant; }
+    __device__ uint32_t nl() const { return p.nl; }
+    __device__ uint32_t pk() const { return p.pk; }
+    __device__ uint32_t nw() const { return p.nw; }
+};
+struct HeldFields {
+    uint32_t var_, nl_, pk_, nw_;
+    __device__ uint32_t var() const { return var_; }
+    __device__ uint32_t nl() const { return nl_; }
+    __device__ uint32_t pk() const { return pk_; }
+    __device__ uint32_t nw() const { return nw_; }
+};
+template <bool WIDE, class F>
+__device__ __forceinline__ uint32_t any_mask(const uint32_t (&w)[kBatchNL * 4 + 1], const DevPlan &p, const F &f) {
+    if (f.var() == 2) return fingerprint_mask<kBatchNL>(w, p, p.table);
+    if (WIDE && f.nl() == 3) return direct_mask<kBatchNL, 4, 0>(w, p);
+    switch (f.pk()) {
         case 1: return direct_mask<kBatchNL, 1, 1>(w, p);
         case 2: return short_mask<2>(w, p.pw[0]);  // per-lane byte runs: no wave masks
         case 3: return short_mask<3>(w, p.pw[0]);
         default: break;  // 64-bit prefixes (pk 5..8) take the 4-byte path here
     }
-    switch (p.nw) {
+    switch (f.nw()) {
         case 1: return direct_mask<kBatchNL, 4, 1>(w, p);
         case 2: return direct_mask<kBatchNL, 4, 2>(w, p);
         case 3: return direct_mask<kBatchNL, 4, 3>(w, p);
@@ -265,12 +282,28 @@ __device__ __forceinline__ void batch_unit(const BatchArgs &a) {
             const BatchPairDesc &pd = s_pd[j];
             if (WRITE && s_po[j][0] == 0) continue;
             const DevPlan &p = pd.plan;
-            uint32_t mk = any_mask<!WRITE>(w, p);
-            const uint64_t last = t.delta + t.n - p.m;  // m <= n here
+            uint32_t mk, verified;
+            uint64_t m;
+            if constexpr (WRITE) {
+                // at its register cap, the write pass reads the fields where
+                // it branches on them
+                mk = any_mask<false>(w, p, PlanFields{p});
+                m = p.m;
+                verified = p.variant != 2 && p.nl == 3 ? 16u : 4u * p.nw;
+            } else {
+                // the fields the pair's path branches on, read together (one
+                // LDS round trip instead of one per branch) into scalar
+                // registers
+                auto held = [](uint32_t v) { return (uint32_t)__builtin_amdgcn_readfirstlane(v); };
+                const HeldFields f{held(p.variant), held(p.nl), held(p.pk), held(p.nw)};
+                m = held((uint32_t)p.m);  // m <= EPSM_MAX_M
+                mk = any_mask<true>(w, p, f);
+                verified = 4u * f.nw();
+            }
+            const uint64_t last = t.delta + t.n - m;  // m <= n here
             if (tile_start + kTileB > last || tile_start < t.delta) mk &= valid_mask(s0, t.delta, last);
-            const uint32_t verified = WRITE && p.variant != 2 && p.nl == 3 ? 16u : 4u * p.nw;
-            if (p.m > verified && wave_any(mk != 0))
-                mk = tail_check(mk, s0, t.base, p.pattern, p.m, verified);
+            if (m > verified && wave_any(mk != 0))
+                mk = tail_check(mk, s0, t.base, p.pattern, m, verified);
             const uint32_t c = __popc(mk);
             const uint32_t incl = wave_incl_scan32(c);
             const uint32_t wtot = last_lane(incl);
