@@ -30,31 +30,33 @@ constexpr uint32_t kPairChunk = 32;  // pair descriptors staged in LDS at a time
 // rest of the pattern from device memory (a batch uploads the pattern of
 // every plan with m > 16).  The write pass, which runs only entries with
 // hits, takes the narrow form to stay at six waves per SIMD.
-// F gives the plan fields the choice branches on: PlanFields reads them from
-// the plan (in LDS) where they are used, HeldFields holds them in scalar
-// registers, read together beforehand.
+// F gives the plan fields the choice branches on (and the first pattern
+// word): PlanFields reads them from the plan (in LDS) where they are used,
+// HeldFields holds them in scalar registers, read together beforehand.
 struct PlanFields {
     const DevPlan &p;
     __device__ uint32_t var() const { return p.variant; }
     __device__ uint32_t nl() const { return p.nl; }
     __device__ uint32_t pk() const { return p.pk; }
     __device__ uint32_t nw() const { return p.nw; }
+    __device__ uint32_t pw0() const { return p.pw[0]; }
 };
 struct HeldFields {
-    uint32_t var_, nl_, pk_, nw_;
+    uint32_t var_, nl_, pk_, nw_, pw0_;
     __device__ uint32_t var() const { return var_; }
     __device__ uint32_t nl() const { return nl_; }
     __device__ uint32_t pk() const { return pk_; }
     __device__ uint32_t nw() const { return nw_; }
+    __device__ uint32_t pw0() const { return pw0_; }  // the first pattern word (m <= 3)
 };
 template <bool WIDE, class F>
 __device__ __forceinline__ uint32_t any_mask(const uint32_t (&w)[kBatchNL * 4 + 1], const DevPlan &p, const F &f) {
     if (f.var() == 2) return fingerprint_mask<kBatchNL>(w, p, p.table);
     if (WIDE && f.nl() == 3) return direct_mask<kBatchNL, 4, 0>(w, p);
     switch (f.pk()) {
-        case 1: return direct_mask<kBatchNL, 1, 1>(w, p);
-        case 2: return short_mask<2>(w, p.pw[0]);  // per-lane byte runs: no wave masks
-        case 3: return short_mask<3>(w, p.pw[0]);
+        case 1: return byte_mask(w, f.pw0());
+        case 2: return short_mask<2>(w, f.pw0());  // per-lane byte runs: no wave masks
+        case 3: return short_mask<3>(w, f.pw0());
         default: break;  // 64-bit prefixes (pk 5..8) take the 4-byte path here
     }
     switch (f.nw()) {
@@ -295,7 +297,7 @@ __device__ __forceinline__ void batch_unit(const BatchArgs &a) {
                 // LDS round trip instead of one per branch) into scalar
                 // registers
                 auto held = [](uint32_t v) { return (uint32_t)__builtin_amdgcn_readfirstlane(v); };
-                const HeldFields f{held(p.variant), held(p.nl), held(p.pk), held(p.nw)};
+                const HeldFields f{held(p.variant), held(p.nl), held(p.pk), held(p.nw), held(p.pw[0])};
                 m = held((uint32_t)p.m);  // m <= EPSM_MAX_M
                 mk = any_mask<true>(w, p, f);
                 verified = 4u * f.nw();
