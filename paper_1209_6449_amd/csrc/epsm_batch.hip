@@ -381,6 +381,7 @@ void batch_kernel_write(BatchArgs a) {
 bool batch_waves_supported(int waves) { return waves == 4 || waves == 8 || waves == 16; }
 
 hipError_t launch_batch(const BatchArgs &a, int waves, uint32_t n_units, hipStream_t s) {
+    clear_launch_error();
     if (n_units == 0) return hipSuccess;
     auto launch = [&](auto waves_c) {
         constexpr int W = decltype(waves_c)::value;
@@ -477,6 +478,7 @@ __global__ __launch_bounds__(256) void scan_apply_kernel(const uint32_t *counts,
 
 hipError_t launch_scan_counts(const uint32_t *counts, uint64_t entries, uint64_t *offsets,
                               uint64_t *block_sums, hipStream_t s) {
+    clear_launch_error();
     const uint64_t blocks = (entries + kScanBlock - 1) / kScanBlock;
     if (blocks > 0x7FFFFFFFull) return hipErrorInvalidValue;
     if (blocks) hipLaunchKernelGGL(scan_reduce_kernel, dim3((uint32_t)blocks), dim3(256), 0, s,
@@ -557,6 +559,7 @@ hipError_t launch_batch_finalize(const BatchSpan *spans, uint32_t n_pairs,
                                  const uint64_t *offsets, uint64_t entries, uint64_t *counts,
                                  uint64_t *pair_offsets, uint64_t *total, int64_t *shift,
                                  uint64_t *block_sums, hipStream_t s) {
+    clear_launch_error();
     const uint32_t blocks = (uint32_t)(((uint64_t)n_pairs + kScanBlock - 1) / kScanBlock);
     if (blocks)
         hipLaunchKernelGGL(pair_count_kernel, dim3(blocks), dim3(256), 0, s, spans, n_pairs, offsets, counts,

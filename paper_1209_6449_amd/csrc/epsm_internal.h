@@ -234,6 +234,12 @@ struct BatchArgs {
     uint32_t write;
 };
 
+// The launch helpers report errors with hipGetLastError, which returns the
+// last error of any runtime call on this thread; each clears it first, so
+// that an earlier failure of some other call (its own caller's to handle)
+// is not taken for a failed launch.
+inline void clear_launch_error() { (void)hipGetLastError(); }
+
 hipError_t launch_batch(const BatchArgs &a, int waves, uint32_t n_units, hipStream_t s);
 bool batch_waves_supported(int waves);
 // Exclusive scan of entries u32 counts into offsets[0..entries] (u64), using

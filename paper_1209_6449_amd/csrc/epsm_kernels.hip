@@ -112,11 +112,13 @@ __global__ __launch_bounds__(kSumThreads) void tile_offsets_kernel(const uint32_
 
 hipError_t launch_tile_offsets(const uint32_t *tcnt, uint32_t tiles, uint64_t *toff, uint64_t *total,
                             hipStream_t s) {
+    clear_launch_error();
     hipLaunchKernelGGL(tile_offsets_kernel, dim3(1), dim3(kSumThreads), 0, s, tcnt, tiles, toff, total);
     return hipGetLastError();
 }
 
 hipError_t launch_sum_tiles(const uint32_t *tcnt, uint32_t tiles, uint64_t *out, hipStream_t s) {
+    clear_launch_error();
     hipLaunchKernelGGL(sum_tiles_kernel, dim3(1), dim3(kSumThreads), 0, s, tcnt, tiles, out);
     return hipGetLastError();
 }
@@ -390,6 +392,7 @@ static void launch_dna_wide_block(const ScanArgs &a, int mode, hipStream_t s) {
 }
 
 hipError_t launch_dna_wide(const ScanArgs &a, int mode, hipStream_t s) {
+    clear_launch_error();
     if (a.num_tiles == 0) return hipSuccess;
     if (a.plan.pk == 16) launch_dna_wide_block<8>(a, mode, s);
     else if (a.plan.pk == 8) launch_dna_wide_block<4>(a, mode, s);
@@ -417,6 +420,7 @@ __global__ __launch_bounds__(256) void pack_dna_kernel(const uint8_t *codes, uin
 }
 
 hipError_t launch_pack_dna(const uint8_t *codes, uint64_t n, uint8_t *packed, hipStream_t s) {
+    clear_launch_error();
     if (n == 0) return hipSuccess;
     const uint64_t threads = (n + 15) / 16;
     hipLaunchKernelGGL(pack_dna_kernel, dim3((uint32_t)((threads + 255) / 256)), dim3(256), 0, s, codes,
@@ -448,6 +452,7 @@ __global__ __launch_bounds__(256) void alphabet_kernel(const uint8_t *text, uint
 }
 
 hipError_t launch_alphabet(const uint8_t *text, uint32_t len, uint32_t *out, hipStream_t s) {
+    clear_launch_error();
     hipLaunchKernelGGL(alphabet_kernel, dim3(1), dim3(256), 0, s, text, len, out);
     return hipGetLastError();
 }
@@ -457,6 +462,7 @@ __global__ void set_u64_kernel(uint64_t *p, uint64_t value) {
 }
 
 hipError_t launch_zero_u64(uint64_t *p, uint64_t count, hipStream_t s) {
+    clear_launch_error();
     if (count == 0) return hipSuccess;
     uint64_t blocks = (count + 255) / 256;
     if (blocks > 4096) blocks = 4096;
@@ -465,6 +471,7 @@ hipError_t launch_zero_u64(uint64_t *p, uint64_t count, hipStream_t s) {
 }
 
 hipError_t launch_set_u64(uint64_t *p, uint64_t value, hipStream_t s) {
+    clear_launch_error();
     hipLaunchKernelGGL(set_u64_kernel, dim3(1), dim3(64), 0, s, p, value);
     return hipGetLastError();
 }
@@ -513,6 +520,7 @@ static ExpandFn pick_expand(TileConfig cfg) {
 }
 
 hipError_t launch_expand(ScanArgs a, TileConfig cfg, hipStream_t s) {
+    clear_launch_error();
     ExpandFn fn = pick_expand(cfg);
     if (!fn) return hipErrorInvalidValue;
     // Lists: 8 to kExpandTiles tiles per workgroup, copied together, enough
@@ -529,6 +537,7 @@ hipError_t launch_expand(ScanArgs a, TileConfig cfg, hipStream_t s) {
 }
 
 hipError_t launch_scan(const ScanArgs &a, TileConfig cfg, int grid, hipStream_t s) {
+    clear_launch_error();
     ScanFn fn = pick_fn(cfg, a.plan, a.write == kWriteNone);
     if (!fn) return hipErrorInvalidValue;
     hipLaunchKernelGGL(fn, dim3(grid), dim3(cfg.waves * kWave), table_bytes(a.plan), s, a);

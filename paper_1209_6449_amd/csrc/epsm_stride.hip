@@ -160,6 +160,7 @@ __global__ void copy_u64_kernel(const uint64_t *src, uint64_t *dst) {
 }
 
 hipError_t launch_stride(const StrideArgs &a, uint32_t tiles, hipStream_t s) {
+    clear_launch_error();
     if (tiles == 0) return hipSuccess;
     const size_t lds =
         a.stride * sizeof(uint2) + ((size_t)(1u << a.hash_bits) + 1 + a.stride) * sizeof(uint16_t);
@@ -168,6 +169,7 @@ hipError_t launch_stride(const StrideArgs &a, uint32_t tiles, hipStream_t s) {
 }
 
 hipError_t launch_copy_u64(const uint64_t *src, uint64_t *dst, hipStream_t s) {
+    clear_launch_error();
     hipLaunchKernelGGL(copy_u64_kernel, dim3(1), dim3(64), 0, s, src, dst);
     return hipGetLastError();
 }

@@ -8,7 +8,11 @@
   with the library's test hook; every kernel still exits normally).
 * A serving write stage whose output allocation fails completes its queries
   with EPSM_ENOMEM and releases the memory it was admitted for.
+* A failed runtime call elsewhere on the thread (its error left for
+  hipGetLastError) does not make the library's next launches fail.
 """
+import ctypes
+
 import numpy as np
 import pytest
 import torch
@@ -215,3 +219,43 @@ def test_serving_output_allocation_failure_releases_memory(epsm):
             assert o.status == 0
             for k, p in enumerate(q.patterns):
                 assert np.array_equal(o.pattern_positions(k), oracle.positions(host[q.text], p))
+
+
+def _loaded_hip_runtime():
+    """The HIP runtime this process has loaded (the one the library uses)."""
+    with open("/proc/self/maps") as f:
+        for line in f:
+            path = line.split()[-1]
+            if "libamdhip64.so" in path:
+                return ctypes.CDLL(path)
+    pytest.skip("HIP runtime not found in the process")
+
+
+def test_stale_runtime_error_does_not_fail_launches(epsm):
+    """Each library call runs right after the stale error, with nothing in
+    between (PyTorch's own launches would report that error too)."""
+    hip = _loaded_hip_runtime()
+    hip.hipSetDevice.restype = ctypes.c_int
+    hip.hipSetDevice.argtypes = [ctypes.c_int]
+    t = uniform_text(1 << 20, 4, 7)
+    text = torch.from_numpy(t).cuda()
+    pat, pat2 = t[1000:1003].tobytes(), t[5:25].tobytes()
+    exp, exp2 = oracle.positions(t, pat), oracle.positions(t, pat2)
+    plan, plan2 = epsm.Plan(pat), epsm.Plan(pat2)
+    hits = torch.zeros(1, dtype=torch.int64, device="cuda")
+    out = torch.full((len(exp) + len(exp2),), -1, dtype=torch.int64, device="cuda")
+    b = epsm.Batch([text], [(0, plan), (0, plan2)], out=out)
+    torch.cuda.synchronize()
+    # an ordinal no device has: the call only returns an error, and leaves it
+    # as the thread's last error
+    say("stale error, then a count")
+    assert hip.hipSetDevice(1 << 20) != 0
+    epsm.count_into(plan, text, hits)
+    torch.cuda.synchronize()
+    assert int(hits.item()) == len(exp)
+    say("stale error, then a batch")
+    assert hip.hipSetDevice(1 << 20) != 0
+    b.run()
+    torch.cuda.synchronize()
+    assert np.array_equal(out.cpu().numpy(), np.concatenate([exp, exp2]))
+    epsm.stream_check()
