@@ -316,7 +316,7 @@ epsm_status epsm_batch_workspace(const epsm_batch *batch, uint64_t *bytes);
 /* Select the workgroup tile used by later single-text searches: `waves`
  * wavefronts of 64 lanes per workgroup, each scanning `pieces` KiB per tile
  * (tile = waves * pieces KiB).  Built configurations: 8x16 (default), 8x8,
- * 4x16, 16x8, 16x16; others return EPSM_EUNSUPPORTED.  Process-wide; not thread safe
+ * 4x16, 4x32, 16x8, 16x16; others return EPSM_EUNSUPPORTED.  Process-wide; not thread safe
  * against concurrent searches.  Output never depends on the choice. */
 epsm_status epsm_set_tile_config(uint32_t waves, uint32_t pieces);
 
