@@ -229,6 +229,31 @@ def test_grouped_pairs_carry_no_fingerprint_table(epsm):
     assert counts[-1] == 80
 
 
+def test_shared_host_plans_grouped_and_alone(epsm):
+    """One host-only plan object in several pairs: grouped in a text with
+    many patterns, alone in a text with few, and twice in one text; long
+    fingerprint plans among them.  The table travels once, for the pairs
+    filtered alone, and every pair's positions equal the oracle's."""
+    rng = np.random.default_rng(93)
+    host = [rng.integers(0, 4, n).astype(np.uint8) for n in (40000, 30000, 9000)]
+    texts = [torch.from_numpy(t.copy()).cuda() for t in host]
+    shared = [epsm.Plan(host[0][o:o + m].tobytes(), epsm.PLAN_HOST_ONLY)
+              for o, m in ((100, 20), (2000, 33), (7000, 17), (5000, 9))]
+    many = [epsm.Plan(host[0][o:o + m].tobytes(), epsm.PLAN_HOST_ONLY)
+            for o, m in zip(rng.integers(0, 30000, 10), (4, 5, 8, 12, 16, 24, 30, 6, 10, 40))]
+    pairs = [(0, p) for p in shared + many]          # text 0: all grouped (m >= 4)
+    pairs += [(1, shared[0]), (1, shared[1])]        # text 1: too few to group
+    pairs += [(2, shared[2]), (2, shared[2]), (2, shared[3])] + [(2, p) for p in many[:3]]
+    order = rng.permutation(len(pairs))
+    pairs = [pairs[k] for k in order]
+    say(f"shared host plans: {len(pairs)} pairs")
+    pos, counts, offsets = [x.cpu().numpy() for x in epsm.search_batch(texts, pairs)]
+    epsm.stream_check()
+    for k, (ti, plan) in enumerate(pairs):
+        exp = oracle.positions(host[ti], plan.pattern)
+        assert np.array_equal(pos[offsets[k]:offsets[k] + counts[k]], exp), (k, ti, plan.m)
+
+
 def test_empty_batch(epsm):
     say("empty batch")
     b = epsm.Batch([], [], count_only=False)
